@@ -1,0 +1,219 @@
+/*
+ * mc.h -- C interface of libmc, an MI355X (gfx950) simulator of the
+ * deliver/update simulation cycle of leaky integrate-and-fire networks with
+ * explicitly stored synapses (Kurth, Senk, Terhorst, Finnerty, Diesmann,
+ * "Sub-realtime simulation of a neuronal network of natural density").
+ *
+ * What the paper fixes and this interface follows:
+ *   - the problem statement of the Methods section: instantiate the network
+ *     (not timed), then simulate a span of model time T_model on a fixed grid
+ *     of h = 0.1 ms after a presimulation, and report the realtime factor
+ *     RTF = T_wall / T_model (the one equation of the Methods section);
+ *   - the simulation cycle named in the Fig. 1 caption: "update" advances the
+ *     state of every neuron, "deliver" distributes each spike to its targets;
+ *   - the observable of Supplementary Fig. 1: the spike raster;
+ *   - synaptic events = transmitted spikes (Methods, energy per event);
+ *   - explicit per-synapse weights (Discussion), which makes per-synapse
+ *     gradients well defined (mc_adjoint).
+ *
+ * Conventions for every function:
+ *   - returns MC_OK (0) or a negative mc_status; no C++ exception crosses the
+ *     boundary; mc_last_error() returns a message for the calling thread's
+ *     most recent failure;
+ *   - pointers named *_host are host memory, *_dev device memory; every
+ *     output buffer is owned by the caller; the library owns all memory that
+ *     belongs to an mc_net until mc_free;
+ *   - one host thread may use an mc_net at a time;
+ *   - neuron ids are global and dense: instance b of a batched network holds
+ *     ids [inst_off[b], inst_off[b+1]) (mc_get_instance_offsets), and inside
+ *     an instance the populations follow in configuration order;
+ *   - "step" counts grid steps of h since the network was built (step 0 is
+ *     the first step simulated).
+ */
+#ifndef MC_H
+#define MC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MC_ABI_VERSION 1
+#define MC_MAX_POPS 16
+#define MC_RING_SLOTS 128        /* input ring depth; delays are 1..MC_RING_SLOTS-28 steps */
+
+typedef enum mc_status {
+  MC_OK = 0,
+  MC_ERR_INVALID_ARG = -1,       /* a NULL or malformed argument, or an inconsistent configuration */
+  MC_ERR_RANGE = -2,             /* a value outside what the representation holds (weight, delay, size) */
+  MC_ERR_OOM = -3,               /* host or device allocation failed; the handle stays valid */
+  MC_ERR_HIP = -4,               /* a HIP runtime call failed */
+  MC_ERR_STATE = -5,             /* handle in the wrong state (freed, host-only, failed, or not fresh) */
+  MC_ERR_BUFFER_TOO_SMALL = -6,  /* *count_out holds the required element count */
+  MC_ERR_NO_DEVICE = -7,         /* no usable gfx950 device */
+  MC_ERR_MISMATCH = -8           /* adjoint recomputation did not reproduce the recorded spikes */
+} mc_status;
+
+enum { MC_RULE_FIXED_INDEGREE = 0, MC_RULE_BERNOULLI = 1 };
+enum { MC_GRAD_F64 = 0, MC_GRAD_F32 = 1 };
+enum { MC_FLAG_HOST_ONLY = 1u };  /* build the network on the host only (no device memory) */
+
+typedef struct mc_net mc_net;
+
+/*
+ * Network description.  Populations: n_pops (<= MC_MAX_POPS) of sizes
+ * pop_size; instance b holds max(1, rint(inst_scale[b] * pop_size[a]))
+ * neurons of population a.  Matrices are [post * n_pops + pre].
+ *
+ * Connectivity: MC_RULE_FIXED_INDEGREE -- conn = number of sources per target
+ * drawn from population pre uniformly with replacement (autapses and
+ * multapses allowed); MC_RULE_BERNOULLI -- conn = probability that a given
+ * (source, target) pair is connected (autapses allowed, no multapses).
+ * Weights: N(w_mean, (w_rel_sd*|w_mean|)^2) pA, stored as signed integers in
+ * units of 2^-16 pA (round to nearest even).  Delays: N(d_mean[pre],
+ * (d_rel_sd*d_mean[pre])^2) ms, rounded to the step h and clipped to
+ * [d_min_steps, d_max_steps] (1 <= d_min_steps, d_max_steps <= 100).
+ * Drive: a Poisson number of inputs per neuron and step with mean
+ * nu_ext_hz * k_ext[pop] * h, each of weight w_ext_pA.
+ * Neuron: leaky integrate-and-fire with exponentially decaying current
+ * (tau_m_ms, c_m_pF, e_l_mV, v_reset_mV, v_th_mV, t_ref_ms, tau_syn_ms,
+ * constant current i_e_pA), exact integration at step h_ms; initial
+ * membrane potential uniform in [v0_lo_mV, v0_hi_mV).
+ * All random draws are counter-based (Philox4x64-10) keyed by the instance
+ * seed, so results do not depend on launch configuration, batching or
+ * thread counts.
+ */
+typedef struct mc_config {
+  uint32_t struct_size;          /* sizeof(mc_config); guards the ABI */
+  int32_t n_pops;
+  const int32_t* pop_size;       /* [n_pops] */
+  int32_t rule;
+  const double* conn;            /* [n_pops*n_pops] */
+  const double* w_mean_pA;       /* [n_pops*n_pops], signed */
+  double w_rel_sd;
+  const double* d_mean_ms;       /* [n_pops], by presynaptic population */
+  double d_rel_sd;
+  int32_t d_min_steps, d_max_steps;
+  const double* k_ext;           /* [n_pops] */
+  double nu_ext_hz, w_ext_pA;
+  double tau_m_ms, c_m_pF, e_l_mV, v_reset_mV, v_th_mV, t_ref_ms, tau_syn_ms, i_e_pA, h_ms;
+  double v0_lo_mV, v0_hi_mV;
+  int32_t n_instances;           /* >= 1 */
+  const double* inst_scale;      /* [n_instances]; NULL means 1.0 for every instance */
+  const uint64_t* inst_seed;     /* [n_instances]; required */
+  void* hip_stream;              /* hipStream_t to run on; NULL: a stream owned by the library */
+  uint32_t flags;                /* MC_FLAG_* */
+} mc_config;
+
+/* Launch configuration of the simulation loop (see mc_set_launch). */
+enum { MC_SCHEME_STEP_KERNELS = 0,   /* one update and one delivery kernel per step, replayed from a HIP graph */
+       MC_SCHEME_PERSISTENT_LDS = 1 };/* one persistent kernel per chunk; near-future input held in LDS */
+typedef struct mc_launch {
+  uint32_t struct_size;
+  int32_t scheme;
+  int32_t block;                 /* threads per workgroup: 64..1024, multiple of 64 */
+  int32_t neurons_per_wg;        /* neurons updated by one workgroup: multiple of 4, <= 4*block (0: automatic) */
+  int32_t steps_per_graph;       /* steps captured per graph replay / per persistent launch (>= 1) */
+} mc_launch;
+
+typedef struct mc_counters {
+  int64_t step;                  /* next step to simulate */
+  int64_t spikes;                /* spikes emitted since build */
+  int64_t events;                /* synaptic events delivered since build (sum of out-degrees of spikes) */
+  int64_t spikes_per_pop[MC_MAX_POPS];   /* summed over instances */
+} mc_counters;
+
+typedef struct mc_adjoint_config {
+  uint32_t struct_size;
+  int64_t window_steps;          /* S >= 1 */
+  int64_t ckpt_every;            /* K >= 1: forward state kept every K steps, recomputed in between */
+  double v_target_mV;            /* loss target V* */
+  int32_t grad_dtype;            /* MC_GRAD_F64 or MC_GRAD_F32 */
+} mc_adjoint_config;
+
+/* --- the four calls of the simulation --------------------------------- */
+
+/* Builds the network on the host (OpenMP), derives propagators and drive
+ * tables, uploads everything to the current HIP device.  Untimed
+ * instantiation of the Methods section.  *out receives the handle (NULL on
+ * failure).  Errors: INVALID_ARG (inconsistent config), RANGE (a quantised
+ * weight beyond int32, a delay range beyond the ring, too many neurons),
+ * OOM, HIP, NO_DEVICE. */
+int mc_build_network(const mc_config* cfg, mc_net** out);
+
+/* Advances the network by `steps` grid steps (update, then deliver, per
+ * step), recording every spike.  Asynchronous on the network's stream;
+ * getters synchronize.  Resumable: consecutive calls continue the same
+ * trajectory bit for bit.  Errors: STATE (host-only or failed handle), HIP,
+ * OOM (raster growth). */
+int mc_simulate(mc_net* net, int64_t steps);
+
+/* Copies the recorded spikes with step in [step_begin, step_end) into
+ * caller-owned host arrays, sorted by step, then neuron id.  If more than
+ * `capacity` spikes fall in the range, writes nothing, sets *count_out to the
+ * number required and returns BUFFER_TOO_SMALL. */
+int mc_get_spikes(mc_net* net, int64_t step_begin, int64_t step_end,
+                  int32_t* step_out_host, int32_t* id_out_host, int64_t capacity, int64_t* count_out);
+
+/* Gradient of L = 1/(N S) sum_i sum_{n<S} (V_i(n+1) - V*)^2 over a window of S
+ * steps starting at the current step, with respect to every synaptic weight
+ * in pA, with the spike pattern of the window held fixed (reverse-time
+ * adjoint with transposed propagators, gathered over the outgoing synapse
+ * rows of every recorded spike).  The network advances by S steps as if
+ * mc_simulate(S) had been called.  grad_dev: device array of
+ * mc_get_sizes().n_synapses elements (double or float per grad_dtype), in
+ * the canonical synapse order of mc_get_synapses; overwritten.  *loss_out: L.
+ * Errors: INVALID_ARG, STATE, OOM, HIP, MISMATCH. */
+int mc_adjoint(mc_net* net, const mc_adjoint_config* acfg, void* grad_dev, double* loss_out);
+
+void mc_free(mc_net* net);
+const char* mc_strerror(int code);
+const char* mc_last_error(void);
+int mc_abi_version(void);
+
+/* --- introspection and control (same conventions) ---------------------- */
+
+int mc_get_sizes(mc_net* net, int64_t* n_neurons, int64_t* n_synapses, int32_t* n_instances);
+int mc_get_instance_offsets(mc_net* net, int64_t* off_host /* [n_instances+1] */);
+/* Population offsets of instance b in global ids: [n_pops+1]. */
+int mc_get_pop_offsets(mc_net* net, int32_t instance, int64_t* off_host);
+/* The synapse store in canonical order: rows by source id, ascending target
+ * inside a row (multapses in draw order).  row_ptr [N+1], tgt/w_q/dly [M]. */
+int mc_get_synapses(mc_net* net, int64_t* row_ptr_host, int32_t* tgt_host, int32_t* w_q_host, uint8_t* dly_host);
+/* State after the last simulated step: y = V - E_L (mV), I (pA), refractory steps left. */
+int mc_get_state(mc_net* net, double* y_host, double* i_host, int32_t* r_host);
+int mc_set_state(mc_net* net, const double* y_host, const double* i_host, const int32_t* r_host);
+/* Logical input ring: pending[k*N + i] = integer input (2^-16 pA) neuron i
+ * reads at step (current step + k), k in [0, depth), depth <= MC_RING_SLOTS. */
+int mc_get_ring(mc_net* net, int64_t depth, int64_t* pending_host);
+/* Adds `value` (2^-16 pA) to the input neuron i reads at step current+k. */
+int mc_inject(mc_net* net, int64_t k, int64_t neuron, int64_t value);
+/* Propagators P11, P21, P22, P20 of the exact integration step. */
+int mc_get_propagators(mc_net* net, double* p_host /* [4] */);
+/* Poisson inverse-CDF tables [n_pops][64] of instance 0 (tables are the same for every instance). */
+int mc_get_drive_tables(mc_net* net, uint64_t* t_host);
+int mc_get_counters(mc_net* net, mc_counters* out);
+/* Launch configuration; a change never changes results (integer sums). */
+int mc_set_launch(mc_net* net, const mc_launch* l);
+int mc_get_launch(mc_net* net, mc_launch* l);
+/* Times candidate launch configurations on copies of the current state for
+ * `steps` steps each, keeps the fastest (state and raster are restored). */
+int mc_tune(mc_net* net, int64_t steps, mc_launch* best_out);
+/* Wall time (ms) of the GPU work of the most recent mc_simulate, from HIP events. */
+int mc_last_simulate_ms(mc_net* net, double* ms_out);
+/* Makes room for the spikes of `steps` further steps so that mc_simulate
+ * allocates nothing for them. */
+int mc_reserve(mc_net* net, int64_t steps);
+/* Full dynamic state (step, y, I, r, ring, counters) to/from a host blob. */
+int mc_save_state(mc_net* net, void* blob_host, size_t capacity, size_t* used_out);
+int mc_load_state(mc_net* net, const void* blob_host, size_t size);
+/* Replaces every weight by rint(w_pA_dev[k] * 2^16) (device array, canonical order). */
+int mc_set_weights(mc_net* net, const double* w_pA_dev);
+int mc_stream(mc_net* net, void** hip_stream_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MC_H */

@@ -1,0 +1,742 @@
+// mc_api.hip -- the C interface of libmc (include/mc.h): handle management,
+// device memory plan, graph-replayed simulation loop, spike export,
+// introspection and checkpoints.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "mc.h"
+#include "mc_build.h"
+#include "mc_device.h"
+
+using namespace mc;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int set_error(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                      \
+  do {                                                                                     \
+    hipError_t e__ = (expr);                                                               \
+    if (e__ != hipSuccess) {                                                               \
+      return set_error(e__ == hipErrorOutOfMemory ? MC_ERR_OOM : MC_ERR_HIP,               \
+                       std::string(#expr) + ": " + hipGetErrorString(e__));                \
+    }                                                                                      \
+  } while (0)
+
+inline int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+template <class T>
+int dev_alloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return set_error(e == hipErrorOutOfMemory ? MC_ERR_OOM : MC_ERR_HIP,
+                     std::string("hipMalloc of ") + std::to_string(count * sizeof(T)) + " bytes: " + hipGetErrorString(e));
+  }
+  return MC_OK;
+}
+
+template <class T>
+void dev_free(T*& p) {
+  if (p) (void)hipFree((void*)p);
+  p = nullptr;
+}
+
+}  // namespace
+
+struct mc_net {
+  HostNet h;
+  bool host_only = false;
+  bool failed = false;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  // padded layout
+  int64_t n_pad = 0, n_quads = 0, ring_stride = 0;
+  std::vector<int64_t> inst_off_pad;
+  // device store and state
+  int64_t* d_row_ptr = nullptr;
+  int32_t* d_tgt = nullptr;
+  int32_t* d_wq = nullptr;
+  uint8_t* d_dly = nullptr;
+  double* d_y = nullptr;
+  double* d_I = nullptr;
+  int32_t* d_r = nullptr;
+  long long* d_ring = nullptr;
+  uint64_t* d_qseed = nullptr;
+  uint32_t* d_qlocal = nullptr;
+  uint32_t* d_qpops = nullptr;
+  uint64_t* d_table = nullptr;
+  long long* d_step = nullptr;
+  // recording
+  int n_wg = 0;
+  int qpw = 0;
+  int2* d_raster = nullptr;
+  long long raster_cap = 0;            // per workgroup
+  long long* d_raster_cnt = nullptr;
+  unsigned long long* d_wg_events = nullptr;
+  unsigned long long* d_wg_spikes = nullptr;
+  unsigned* d_overflow = nullptr;
+  int64_t cap_steps = 0;               // steps the raster segments can absorb between drains
+  int64_t steps_since_drain = 0;
+  std::vector<int32_t> r_step, r_id;   // drained raster (dense ids), sorted
+  int64_t events_base = 0;
+  std::vector<int64_t> spikes_base;
+  int64_t step = 0;
+  mc_launch launch{};
+  // graph
+  hipGraphExec_t graph = nullptr;
+  int graph_steps = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  double last_ms = 0.0;
+
+  DevNet dev() const {
+    DevNet p{};
+    p.n_pad = n_pad; p.n_quads = n_quads; p.ring_stride = ring_stride; p.n_pops = h.n_pops;
+    p.row_ptr = d_row_ptr; p.tgt = d_tgt; p.wq = d_wq; p.dly = d_dly;
+    p.y = d_y; p.I = d_I; p.r = d_r; p.ring = d_ring;
+    p.qseed = d_qseed; p.qlocal = d_qlocal; p.qpops = d_qpops; p.table = d_table;
+    p.P11 = h.P11; p.P21 = h.P21; p.P22 = h.P22; p.P20 = h.P20; p.i_e = h.i_e; p.theta = h.theta; p.y_reset = h.y_reset;
+    p.jext_q = h.jext_q; p.ref_steps = h.ref_steps;
+    p.step_base = d_step;
+    p.raster = d_raster; p.raster_cap = raster_cap; p.raster_cnt = d_raster_cnt;
+    p.wg_events = d_wg_events; p.wg_spikes = d_wg_spikes; p.overflow = d_overflow;
+    p.rec_y = nullptr; p.rec_type = nullptr; p.rec_step0 = 0;
+    return p;
+  }
+
+  // dense id -> instance
+  int inst_of(int64_t dense) const {
+    return (int)(std::upper_bound(h.inst_off.begin(), h.inst_off.end(), dense) - h.inst_off.begin()) - 1;
+  }
+  int64_t pad_of(int64_t dense) const {
+    const int b = inst_of(dense);
+    return dense - h.inst_off[b] + inst_off_pad[b];
+  }
+  int64_t dense_of(int64_t padded) const {
+    const int b = (int)(std::upper_bound(inst_off_pad.begin(), inst_off_pad.end(), padded) - inst_off_pad.begin()) - 1;
+    const int64_t local = padded - inst_off_pad[b];
+    if (local >= h.inst_off[b + 1] - h.inst_off[b]) return -1;
+    return h.inst_off[b] + local;
+  }
+};
+
+namespace {
+
+bool usable(mc_net* n) { return n && !n->failed; }
+bool device_ready(mc_net* n) { return usable(n) && !n->host_only; }
+
+int release_recording(mc_net* n) {
+  dev_free(n->d_raster);
+  dev_free(n->d_raster_cnt);
+  dev_free(n->d_wg_events);
+  dev_free(n->d_wg_spikes);
+  return MC_OK;
+}
+
+void release_all(mc_net* n) {
+  if (n->graph) { (void)hipGraphExecDestroy(n->graph); n->graph = nullptr; }
+  release_recording(n);
+  dev_free(n->d_overflow);
+  dev_free(n->d_row_ptr); dev_free(n->d_tgt); dev_free(n->d_wq); dev_free(n->d_dly);
+  dev_free(n->d_y); dev_free(n->d_I); dev_free(n->d_r); dev_free(n->d_ring);
+  dev_free(n->d_qseed); dev_free(n->d_qlocal); dev_free(n->d_qpops); dev_free(n->d_table); dev_free(n->d_step);
+  if (n->ev0) { (void)hipEventDestroy(n->ev0); n->ev0 = nullptr; }
+  if (n->ev1) { (void)hipEventDestroy(n->ev1); n->ev1 = nullptr; }
+  if (n->own_stream && n->stream) { (void)hipStreamDestroy(n->stream); n->stream = nullptr; }
+}
+
+// Spikes a workgroup of `neurons` can emit in `steps` steps: each neuron at
+// most once per (t_ref/h + 1) steps.
+int64_t spike_bound(int64_t neurons, int64_t steps, int ref) {
+  return neurons * ((steps + ref) / (ref + 1));
+}
+
+// Copies the private raster segments to the host list (sorted by step, id)
+// and empties them.  Synchronizes the stream.
+int drain(mc_net* n) {
+  if (!n->d_raster) return MC_OK;
+  HIP_TRY(hipStreamSynchronize(n->stream));
+  unsigned ovf = 0;
+  HIP_TRY(hipMemcpy(&ovf, n->d_overflow, sizeof(unsigned), hipMemcpyDeviceToHost));
+  if (ovf) { n->failed = true; return set_error(MC_ERR_STATE, "raster segment overflow (internal capacity error)"); }
+  std::vector<long long> cnt((size_t)n->n_wg);
+  HIP_TRY(hipMemcpy(cnt.data(), n->d_raster_cnt, sizeof(long long) * n->n_wg, hipMemcpyDeviceToHost));
+  std::vector<int2> buf;
+  for (int g = 0; g < n->n_wg; ++g) {
+    if (cnt[g] == 0) continue;
+    const size_t old = buf.size();
+    buf.resize(old + (size_t)cnt[g]);
+    HIP_TRY(hipMemcpy(buf.data() + old, n->d_raster + (size_t)g * n->raster_cap, sizeof(int2) * cnt[g], hipMemcpyDeviceToHost));
+  }
+  for (auto& e : buf) e.y = (int)n->dense_of(e.y);
+  std::sort(buf.begin(), buf.end(), [](const int2& a, const int2& b) { return a.x != b.x ? a.x < b.x : a.y < b.y; });
+  n->r_step.reserve(n->r_step.size() + buf.size());
+  n->r_id.reserve(n->r_id.size() + buf.size());
+  for (auto& e : buf) { n->r_step.push_back(e.x); n->r_id.push_back(e.y); }
+  HIP_TRY(hipMemsetAsync(n->d_raster_cnt, 0, sizeof(long long) * n->n_wg, n->stream));
+  HIP_TRY(hipStreamSynchronize(n->stream));
+  n->steps_since_drain = 0;
+  return MC_OK;
+}
+
+// Folds the per-workgroup counters into the host base (before they are
+// reallocated for a new launch shape).
+int fold_counters(mc_net* n) {
+  if (!n->d_wg_events) return MC_OK;
+  HIP_TRY(hipStreamSynchronize(n->stream));
+  std::vector<unsigned long long> ev((size_t)n->n_wg), sp((size_t)n->n_wg * n->h.n_pops);
+  HIP_TRY(hipMemcpy(ev.data(), n->d_wg_events, sizeof(unsigned long long) * ev.size(), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(sp.data(), n->d_wg_spikes, sizeof(unsigned long long) * sp.size(), hipMemcpyDeviceToHost));
+  for (auto v : ev) n->events_base += (int64_t)v;
+  for (int g = 0; g < n->n_wg; ++g)
+    for (int a = 0; a < n->h.n_pops; ++a) n->spikes_base[a] += (int64_t)sp[(size_t)g * n->h.n_pops + a];
+  HIP_TRY(hipMemsetAsync(n->d_wg_events, 0, sizeof(unsigned long long) * ev.size(), n->stream));
+  HIP_TRY(hipMemsetAsync(n->d_wg_spikes, 0, sizeof(unsigned long long) * sp.size(), n->stream));
+  return MC_OK;
+}
+
+// (Re)allocates the recording buffers for the current launch shape with room
+// for `steps` steps between drains.
+int setup_recording(mc_net* n, int64_t steps) {
+  int rc;
+  if ((rc = drain(n)) != MC_OK) return rc;
+  if ((rc = fold_counters(n)) != MC_OK) return rc;
+  // a captured graph holds the old buffer addresses
+  if (n->graph) { (void)hipGraphExecDestroy(n->graph); n->graph = nullptr; }
+  release_recording(n);
+  const int64_t neurons = 4LL * n->qpw;
+  n->raster_cap = spike_bound(neurons, steps, n->h.ref_steps) + 1;
+  n->cap_steps = steps;
+  if ((rc = dev_alloc(&n->d_raster, (size_t)n->n_wg * n->raster_cap)) != MC_OK) return rc;
+  if ((rc = dev_alloc(&n->d_raster_cnt, (size_t)n->n_wg)) != MC_OK) return rc;
+  if ((rc = dev_alloc(&n->d_wg_events, (size_t)n->n_wg)) != MC_OK) return rc;
+  if ((rc = dev_alloc(&n->d_wg_spikes, (size_t)n->n_wg * n->h.n_pops)) != MC_OK) return rc;
+  HIP_TRY(hipMemsetAsync(n->d_raster_cnt, 0, sizeof(long long) * n->n_wg, n->stream));
+  HIP_TRY(hipMemsetAsync(n->d_wg_events, 0, sizeof(unsigned long long) * n->n_wg, n->stream));
+  HIP_TRY(hipMemsetAsync(n->d_wg_spikes, 0, sizeof(unsigned long long) * n->n_wg * n->h.n_pops, n->stream));
+  HIP_TRY(hipStreamSynchronize(n->stream));
+  n->steps_since_drain = 0;
+  return MC_OK;
+}
+
+int validate_launch(const mc_net* n, const mc_launch& l) {
+  if (l.struct_size != sizeof(mc_launch)) return set_error(MC_ERR_INVALID_ARG, "mc_launch.struct_size mismatch");
+  if (l.scheme != MC_SCHEME_STEP_KERNELS) return set_error(MC_ERR_INVALID_ARG, "unsupported scheme");
+  if (l.block < 64 || l.block > 1024 || l.block % 64) return set_error(MC_ERR_INVALID_ARG, "block must be a multiple of 64 in [64, 1024]");
+  const int npw = l.neurons_per_wg;
+  if (npw < 0 || npw % 4 || npw > 4 * l.block || npw > 4 * kMaxQuadsPerWgHost)
+    return set_error(MC_ERR_INVALID_ARG, "neurons_per_wg must be a multiple of 4, <= 4*block and <= 1024");
+  if (l.steps_per_graph < 1 || l.steps_per_graph > 100000) return set_error(MC_ERR_INVALID_ARG, "steps_per_graph out of [1, 100000]");
+  (void)n;
+  return MC_OK;
+}
+
+int apply_launch(mc_net* n, const mc_launch& l) {
+  int rc = validate_launch(n, l);
+  if (rc != MC_OK) return rc;
+  int qpw = l.neurons_per_wg / 4;
+  if (qpw == 0) qpw = std::min<int>(l.block, 64);
+  const int n_wg = (int)((n->n_quads + qpw - 1) / qpw);
+  const bool shape_changed = (qpw != n->qpw || n_wg != n->n_wg);
+  if (n->graph && (shape_changed || l.steps_per_graph != n->graph_steps || l.block != n->launch.block)) {
+    (void)hipGraphExecDestroy(n->graph);
+    n->graph = nullptr;
+  }
+  if (shape_changed || !n->d_raster) {
+    if ((rc = drain(n)) != MC_OK) return rc;
+    if ((rc = fold_counters(n)) != MC_OK) return rc;
+    release_recording(n);   // sized for the old shape
+    n->qpw = qpw;
+    n->n_wg = n_wg;
+    n->launch = l;
+    if ((rc = setup_recording(n, std::max<int64_t>(n->cap_steps, 4096))) != MC_OK) return rc;
+  }
+  n->launch = l;
+  return MC_OK;
+}
+
+int build_graph(mc_net* n) {
+  if (n->graph) return MC_OK;
+  hipStream_t cs;
+  HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  const DevNet p = n->dev();
+  const int S = n->launch.steps_per_graph;
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    for (int k = 0; k < S && e == hipSuccess; ++k) e = launch_step(p, k, n->qpw, n->n_wg, n->launch.block, cs);
+    if (e == hipSuccess) e = launch_advance(n->d_step, S, cs);
+    hipError_t e2 = hipStreamEndCapture(cs, &g);
+    if (e == hipSuccess) e = e2;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&n->graph, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  (void)hipStreamDestroy(cs);
+  if (e != hipSuccess) { n->graph = nullptr; return set_error(MC_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e)); }
+  n->graph_steps = S;
+  return MC_OK;
+}
+
+// Enqueues `steps` steps (no synchronization).
+int enqueue_steps(mc_net* n, int64_t steps) {
+  int rc;
+  int64_t left = steps;
+  while (left > 0) {
+    int64_t room = n->cap_steps - n->steps_since_drain;
+    if (room <= 0) {
+      if ((rc = drain(n)) != MC_OK) return rc;
+      room = n->cap_steps;
+    }
+    int64_t chunk = std::min(left, room);
+    const int S = n->launch.steps_per_graph;
+    if (chunk >= S) {
+      if ((rc = build_graph(n)) != MC_OK) return rc;
+      const int64_t reps = chunk / S;
+      for (int64_t k = 0; k < reps; ++k) HIP_TRY(hipGraphLaunch(n->graph, n->stream));
+      chunk = reps * S;
+    } else {
+      const DevNet p = n->dev();
+      for (int k = 0; k < (int)chunk; ++k) HIP_TRY(launch_step(p, k, n->qpw, n->n_wg, n->launch.block, n->stream));
+      HIP_TRY(launch_advance(n->d_step, (int)chunk, n->stream));
+    }
+    n->steps_since_drain += chunk;
+    n->step += chunk;
+    left -= chunk;
+  }
+  return MC_OK;
+}
+
+int upload_network(mc_net* n) {
+  HostNet& h = n->h;
+  int rc;
+  // padded layout
+  n->inst_off_pad.assign((size_t)h.n_inst + 1, 0);
+  for (int b = 0; b < h.n_inst; ++b)
+    n->inst_off_pad[b + 1] = n->inst_off_pad[b] + align_up(h.inst_off[b + 1] - h.inst_off[b], 4);
+  n->n_pad = n->inst_off_pad[h.n_inst];
+  n->n_quads = n->n_pad / 4;
+  n->ring_stride = align_up(n->n_pad, 64);
+  const int64_t N = h.N, M = h.M, P = n->n_pad;
+
+  std::vector<int64_t> rp((size_t)P + 1);
+  std::vector<double> y((size_t)P, 0.0);
+  std::vector<uint64_t> qseed((size_t)n->n_quads);
+  std::vector<uint32_t> qlocal((size_t)n->n_quads), qpops((size_t)n->n_quads);
+  for (int b = 0; b < h.n_inst; ++b) {
+    const int64_t d0 = h.inst_off[b], Nb = h.inst_off[b + 1] - d0, p0 = n->inst_off_pad[b];
+    const int64_t Pb = n->inst_off_pad[b + 1] - p0;
+    for (int64_t k = 0; k < Pb; ++k) {
+      rp[p0 + k] = h.row_ptr[d0 + std::min(k, Nb)];
+      if (k < Nb) y[p0 + k] = h.y0[d0 + k];
+    }
+    for (int64_t qq = 0; qq < Pb / 4; ++qq) {
+      const int64_t gq = p0 / 4 + qq;
+      qseed[gq] = h.inst_seed[b];
+      qlocal[gq] = (uint32_t)qq;
+      uint32_t pk = 0;
+      for (int k = 0; k < 4; ++k) {
+        const int64_t loc = 4 * qq + k;
+        const uint32_t pop = loc < Nb ? h.pop_of[d0 + loc] : 0xFFu;
+        pk |= pop << (8 * k);
+      }
+      qpops[gq] = pk;
+    }
+  }
+  rp[P] = M;
+  std::vector<int32_t> tg(h.tgt);
+  for (int b = 0; b < h.n_inst; ++b) {
+    const int64_t shift = n->inst_off_pad[b] - h.inst_off[b];
+    if (shift == 0) continue;
+    for (int64_t e = h.row_ptr[h.inst_off[b]]; e < h.row_ptr[h.inst_off[b + 1]]; ++e) tg[e] += (int32_t)shift;
+  }
+  (void)N;
+  if ((rc = dev_alloc(&n->d_row_ptr, (size_t)P + 1)) != MC_OK) return rc;
+  if ((rc = dev_alloc(&n->d_tgt, (size_t)M)) != MC_OK) return rc;
+  if ((rc = dev_alloc(&n->d_wq, (size_t)M)) != MC_OK) return rc;
+  if ((rc = dev_alloc(&n->d_dly, (size_t)M)) != MC_OK) return rc;
+  if ((rc = dev_alloc(&n->d_y, (size_t)P)) != MC_OK) return rc;
+  if ((rc = dev_alloc(&n->d_I, (size_t)P)) != MC_OK) return rc;
+  if ((rc = dev_alloc(&n->d_r, (size_t)P)) != MC_OK) return rc;
+  if ((rc = dev_alloc(&n->d_ring, (size_t)kRingSlots * n->ring_stride)) != MC_OK) return rc;
+  if ((rc = dev_alloc(&n->d_qseed, (size_t)n->n_quads)) != MC_OK) return rc;
+  if ((rc = dev_alloc(&n->d_qlocal, (size_t)n->n_quads)) != MC_OK) return rc;
+  if ((rc = dev_alloc(&n->d_qpops, (size_t)n->n_quads)) != MC_OK) return rc;
+  if ((rc = dev_alloc(&n->d_table, h.table.size())) != MC_OK) return rc;
+  if ((rc = dev_alloc(&n->d_step, 1)) != MC_OK) return rc;
+  if ((rc = dev_alloc(&n->d_overflow, 1)) != MC_OK) return rc;
+  HIP_TRY(hipMemcpy(n->d_row_ptr, rp.data(), sizeof(int64_t) * (P + 1), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(n->d_tgt, tg.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(n->d_wq, h.wq.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(n->d_dly, h.dly.data(), M, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(n->d_y, y.data(), sizeof(double) * P, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemset(n->d_I, 0, sizeof(double) * P));
+  HIP_TRY(hipMemset(n->d_r, 0, sizeof(int32_t) * P));
+  HIP_TRY(hipMemset(n->d_ring, 0, sizeof(long long) * kRingSlots * n->ring_stride));
+  HIP_TRY(hipMemcpy(n->d_qseed, qseed.data(), sizeof(uint64_t) * n->n_quads, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(n->d_qlocal, qlocal.data(), sizeof(uint32_t) * n->n_quads, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(n->d_qpops, qpops.data(), sizeof(uint32_t) * n->n_quads, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(n->d_table, h.table.data(), sizeof(uint64_t) * h.table.size(), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemset(n->d_step, 0, sizeof(long long)));
+  HIP_TRY(hipMemset(n->d_overflow, 0, sizeof(unsigned)));
+  HIP_TRY(hipDeviceSynchronize());
+  return MC_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C interface
+// ===========================================================================
+extern "C" {
+
+int mc_abi_version(void) { return MC_ABI_VERSION; }
+
+const char* mc_last_error(void) { return g_last_error.c_str(); }
+
+const char* mc_strerror(int code) {
+  switch (code) {
+    case MC_OK: return "ok";
+    case MC_ERR_INVALID_ARG: return "invalid argument";
+    case MC_ERR_RANGE: return "value out of range";
+    case MC_ERR_OOM: return "out of memory";
+    case MC_ERR_HIP: return "HIP runtime error";
+    case MC_ERR_STATE: return "invalid handle state";
+    case MC_ERR_BUFFER_TOO_SMALL: return "buffer too small";
+    case MC_ERR_NO_DEVICE: return "no usable gfx950 device";
+    case MC_ERR_MISMATCH: return "recomputation did not reproduce the recorded spikes";
+    default: return "unknown error";
+  }
+}
+
+int mc_build_network(const mc_config* cfg, mc_net** out) {
+  if (!out) return set_error(MC_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!cfg) return set_error(MC_ERR_INVALID_ARG, "cfg is NULL");
+  std::unique_ptr<mc_net> n;
+  try { n.reset(new mc_net()); } catch (...) { return set_error(MC_ERR_OOM, "host allocation failed"); }
+  std::string err;
+  int rc;
+  try { rc = build_host(*cfg, n->h, err); } catch (const std::bad_alloc&) { rc = MC_ERR_OOM; err = "host allocation failed"; }
+  if (rc != MC_OK) return set_error(rc, err);
+  n->spikes_base.assign((size_t)n->h.n_pops, 0);
+  n->host_only = (cfg->flags & MC_FLAG_HOST_ONLY) != 0;
+  if (!n->host_only) {
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return set_error(MC_ERR_NO_DEVICE, "no HIP device");
+    if (hipGetDevice(&n->device) != hipSuccess) return set_error(MC_ERR_NO_DEVICE, "hipGetDevice failed");
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, n->device) != hipSuccess) return set_error(MC_ERR_NO_DEVICE, "hipGetDeviceProperties failed");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+      return set_error(MC_ERR_NO_DEVICE, std::string("device is ") + prop.gcnArchName + ", library built for gfx950");
+    if (cfg->hip_stream) { n->stream = (hipStream_t)cfg->hip_stream; n->own_stream = false; }
+    else {
+      if (hipStreamCreateWithFlags(&n->stream, hipStreamNonBlocking) != hipSuccess) return set_error(MC_ERR_HIP, "stream creation failed");
+      n->own_stream = true;
+    }
+    rc = upload_network(n.get());
+    if (rc == MC_OK && hipEventCreate(&n->ev0) != hipSuccess) rc = set_error(MC_ERR_HIP, "event creation failed");
+    if (rc == MC_OK && hipEventCreate(&n->ev1) != hipSuccess) rc = set_error(MC_ERR_HIP, "event creation failed");
+    if (rc == MC_OK) {
+      mc_launch l{};
+      l.struct_size = sizeof(mc_launch);
+      l.scheme = MC_SCHEME_STEP_KERNELS;
+      l.block = 256;
+      l.neurons_per_wg = 256;
+      l.steps_per_graph = 1000;
+      n->cap_steps = 8192;
+      rc = apply_launch(n.get(), l);
+    }
+    if (rc != MC_OK) { release_all(n.get()); return rc; }
+  }
+  *out = n.release();
+  return MC_OK;
+}
+
+void mc_free(mc_net* n) {
+  if (!n) return;
+  if (!n->host_only) {
+    if (n->stream) (void)hipStreamSynchronize(n->stream);
+    release_all(n);
+  }
+  delete n;
+}
+
+int mc_simulate(mc_net* n, int64_t steps) {
+  if (!device_ready(n)) return set_error(MC_ERR_STATE, "handle is host-only, failed or NULL");
+  if (steps < 0) return set_error(MC_ERR_INVALID_ARG, "steps < 0");
+  if (n->step + steps > 2147483647LL) return set_error(MC_ERR_RANGE, "step count beyond int32 raster steps");
+  HIP_TRY(hipEventRecord(n->ev0, n->stream));
+  int rc = enqueue_steps(n, steps);
+  if (rc != MC_OK) { n->failed = true; return rc; }
+  HIP_TRY(hipEventRecord(n->ev1, n->stream));
+  return MC_OK;
+}
+
+int mc_last_simulate_ms(mc_net* n, double* ms_out) {
+  if (!device_ready(n) || !ms_out) return set_error(MC_ERR_INVALID_ARG, "bad handle or NULL output");
+  HIP_TRY(hipEventSynchronize(n->ev1));
+  float ms = 0;
+  HIP_TRY(hipEventElapsedTime(&ms, n->ev0, n->ev1));
+  *ms_out = ms;
+  return MC_OK;
+}
+
+int mc_reserve(mc_net* n, int64_t steps) {
+  if (!device_ready(n)) return set_error(MC_ERR_STATE, "handle is host-only, failed or NULL");
+  if (steps < 1 || steps > 2000000) return set_error(MC_ERR_INVALID_ARG, "steps out of [1, 2e6]");
+  if (n->cap_steps - n->steps_since_drain >= steps) return MC_OK;
+  return setup_recording(n, std::max(steps, n->cap_steps));
+}
+
+int mc_get_spikes(mc_net* n, int64_t b, int64_t e, int32_t* st, int32_t* id, int64_t capacity, int64_t* count_out) {
+  if (!device_ready(n) || !count_out) return set_error(MC_ERR_INVALID_ARG, "bad handle or NULL count_out");
+  int rc = drain(n);
+  if (rc != MC_OK) return rc;
+  auto lo = std::lower_bound(n->r_step.begin(), n->r_step.end(), (int32_t)std::max<int64_t>(std::min<int64_t>(b, 2147483647LL), -1));
+  auto hi = std::lower_bound(n->r_step.begin(), n->r_step.end(), (int32_t)std::max<int64_t>(std::min<int64_t>(e, 2147483647LL), -1));
+  if (e <= b) hi = lo;
+  const int64_t cnt = hi - lo;
+  *count_out = cnt;
+  if (cnt > capacity) return set_error(MC_ERR_BUFFER_TOO_SMALL, "spike buffer too small");
+  if (cnt > 0 && (!st || !id)) return set_error(MC_ERR_INVALID_ARG, "NULL output arrays");
+  const size_t o = lo - n->r_step.begin();
+  if (cnt) {
+    std::memcpy(st, n->r_step.data() + o, sizeof(int32_t) * cnt);
+    std::memcpy(id, n->r_id.data() + o, sizeof(int32_t) * cnt);
+  }
+  return MC_OK;
+}
+
+int mc_get_sizes(mc_net* n, int64_t* N, int64_t* M, int32_t* ni) {
+  if (!usable(n)) return set_error(MC_ERR_STATE, "bad handle");
+  if (N) *N = n->h.N;
+  if (M) *M = n->h.M;
+  if (ni) *ni = n->h.n_inst;
+  return MC_OK;
+}
+
+int mc_get_instance_offsets(mc_net* n, int64_t* off) {
+  if (!usable(n) || !off) return set_error(MC_ERR_INVALID_ARG, "bad handle or NULL");
+  std::memcpy(off, n->h.inst_off.data(), sizeof(int64_t) * n->h.inst_off.size());
+  return MC_OK;
+}
+
+int mc_get_pop_offsets(mc_net* n, int32_t b, int64_t* off) {
+  if (!usable(n) || !off || b < 0 || b >= n->h.n_inst) return set_error(MC_ERR_INVALID_ARG, "bad handle, instance or NULL");
+  std::memcpy(off, n->h.pop_off.data() + (size_t)b * (n->h.n_pops + 1), sizeof(int64_t) * (n->h.n_pops + 1));
+  return MC_OK;
+}
+
+int mc_get_synapses(mc_net* n, int64_t* rp, int32_t* tg, int32_t* w, uint8_t* d) {
+  if (!usable(n)) return set_error(MC_ERR_STATE, "bad handle");
+  const HostNet& h = n->h;
+  if (rp) std::memcpy(rp, h.row_ptr.data(), sizeof(int64_t) * (h.N + 1));
+  if (tg) std::memcpy(tg, h.tgt.data(), sizeof(int32_t) * h.M);
+  if (w) std::memcpy(w, h.wq.data(), sizeof(int32_t) * h.M);
+  if (d) std::memcpy(d, h.dly.data(), (size_t)h.M);
+  return MC_OK;
+}
+
+int mc_get_propagators(mc_net* n, double* p) {
+  if (!usable(n) || !p) return set_error(MC_ERR_INVALID_ARG, "bad handle or NULL");
+  p[0] = n->h.P11; p[1] = n->h.P21; p[2] = n->h.P22; p[3] = n->h.P20;
+  return MC_OK;
+}
+
+int mc_get_drive_tables(mc_net* n, uint64_t* t) {
+  if (!usable(n) || !t) return set_error(MC_ERR_INVALID_ARG, "bad handle or NULL");
+  std::memcpy(t, n->h.table.data(), sizeof(uint64_t) * n->h.table.size());
+  return MC_OK;
+}
+
+int mc_get_state(mc_net* n, double* y, double* I, int32_t* r) {
+  if (!device_ready(n)) return set_error(MC_ERR_STATE, "handle is host-only, failed or NULL");
+  HIP_TRY(hipStreamSynchronize(n->stream));
+  const int64_t P = n->n_pad;
+  std::vector<double> hy((size_t)P), hI((size_t)P);
+  std::vector<int32_t> hr((size_t)P);
+  HIP_TRY(hipMemcpy(hy.data(), n->d_y, sizeof(double) * P, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(hI.data(), n->d_I, sizeof(double) * P, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(hr.data(), n->d_r, sizeof(int32_t) * P, hipMemcpyDeviceToHost));
+  for (int64_t i = 0; i < n->h.N; ++i) {
+    const int64_t pi = n->pad_of(i);
+    if (y) y[i] = hy[pi];
+    if (I) I[i] = hI[pi];
+    if (r) r[i] = hr[pi];
+  }
+  return MC_OK;
+}
+
+int mc_set_state(mc_net* n, const double* y, const double* I, const int32_t* r) {
+  if (!device_ready(n) || !y || !I || !r) return set_error(MC_ERR_INVALID_ARG, "bad handle or NULL");
+  HIP_TRY(hipStreamSynchronize(n->stream));
+  const int64_t P = n->n_pad;
+  std::vector<double> hy((size_t)P, 0.0), hI((size_t)P, 0.0);
+  std::vector<int32_t> hr((size_t)P, 0);
+  for (int64_t i = 0; i < n->h.N; ++i) {
+    const int64_t pi = n->pad_of(i);
+    if (r[i] < 0 || r[i] > 255) return set_error(MC_ERR_RANGE, "refractory count outside [0, 255]");
+    hy[pi] = y[i]; hI[pi] = I[i]; hr[pi] = r[i];
+  }
+  HIP_TRY(hipMemcpy(n->d_y, hy.data(), sizeof(double) * P, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(n->d_I, hI.data(), sizeof(double) * P, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(n->d_r, hr.data(), sizeof(int32_t) * P, hipMemcpyHostToDevice));
+  return MC_OK;
+}
+
+int mc_get_ring(mc_net* n, int64_t depth, int64_t* pending) {
+  if (!device_ready(n) || !pending) return set_error(MC_ERR_INVALID_ARG, "bad handle or NULL");
+  if (depth < 0 || depth > kRingSlots) return set_error(MC_ERR_INVALID_ARG, "depth outside [0, 128]");
+  HIP_TRY(hipStreamSynchronize(n->stream));
+  std::vector<long long> slot((size_t)n->ring_stride);
+  for (int64_t k = 0; k < depth; ++k) {
+    const int64_t s = (n->step + k) & kRingMask;
+    HIP_TRY(hipMemcpy(slot.data(), n->d_ring + s * n->ring_stride, sizeof(long long) * n->ring_stride, hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < n->h.N; ++i) pending[k * n->h.N + i] = slot[n->pad_of(i)];
+  }
+  return MC_OK;
+}
+
+int mc_inject(mc_net* n, int64_t k, int64_t neuron, int64_t value) {
+  if (!device_ready(n)) return set_error(MC_ERR_STATE, "handle is host-only, failed or NULL");
+  if (k < 0 || k >= kRingSlots - 1 || neuron < 0 || neuron >= n->h.N) return set_error(MC_ERR_INVALID_ARG, "k or neuron out of range");
+  const int64_t s = (n->step + k) & kRingMask;
+  HIP_TRY(launch_inject(n->d_ring, s * n->ring_stride + n->pad_of(neuron), value, n->stream));
+  return MC_OK;
+}
+
+int mc_get_counters(mc_net* n, mc_counters* c) {
+  if (!usable(n) || !c) return set_error(MC_ERR_INVALID_ARG, "bad handle or NULL");
+  std::memset(c, 0, sizeof(*c));
+  c->step = n->step;
+  if (n->host_only) return MC_OK;
+  HIP_TRY(hipStreamSynchronize(n->stream));
+  std::vector<unsigned long long> ev((size_t)n->n_wg), sp((size_t)n->n_wg * n->h.n_pops);
+  HIP_TRY(hipMemcpy(ev.data(), n->d_wg_events, sizeof(unsigned long long) * ev.size(), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(sp.data(), n->d_wg_spikes, sizeof(unsigned long long) * sp.size(), hipMemcpyDeviceToHost));
+  c->events = n->events_base;
+  for (auto v : ev) c->events += (int64_t)v;
+  for (int a = 0; a < n->h.n_pops; ++a) {
+    int64_t s = n->spikes_base[a];
+    for (int g = 0; g < n->n_wg; ++g) s += (int64_t)sp[(size_t)g * n->h.n_pops + a];
+    c->spikes_per_pop[a] = s;
+    c->spikes += s;
+  }
+  return MC_OK;
+}
+
+int mc_set_launch(mc_net* n, const mc_launch* l) {
+  if (!device_ready(n) || !l) return set_error(MC_ERR_INVALID_ARG, "bad handle or NULL");
+  return apply_launch(n, *l);
+}
+
+int mc_get_launch(mc_net* n, mc_launch* l) {
+  if (!device_ready(n) || !l) return set_error(MC_ERR_INVALID_ARG, "bad handle or NULL");
+  *l = n->launch;
+  return MC_OK;
+}
+
+int mc_stream(mc_net* n, void** s) {
+  if (!device_ready(n) || !s) return set_error(MC_ERR_INVALID_ARG, "bad handle or NULL");
+  *s = (void*)n->stream;
+  return MC_OK;
+}
+
+int mc_set_weights(mc_net* n, const double* w_dev) {
+  if (!device_ready(n) || !w_dev) return set_error(MC_ERR_INVALID_ARG, "bad handle or NULL");
+  HIP_TRY(launch_set_weights(n->d_wq, w_dev, n->h.M, n->stream));
+  HIP_TRY(hipStreamSynchronize(n->stream));
+  HIP_TRY(hipMemcpy(n->h.wq.data(), n->d_wq, sizeof(int32_t) * n->h.M, hipMemcpyDeviceToHost));
+  return MC_OK;
+}
+
+// Blob: header, y/I/r (padded), ring (all slots), counters.
+struct BlobHeader {
+  uint64_t magic;
+  int64_t n_pad, ring_stride, step, events;
+  int64_t spikes[kMaxPops];
+};
+static const uint64_t kBlobMagic = 0x6d635f7374617431ULL;
+
+int mc_save_state(mc_net* n, void* blob, size_t capacity, size_t* used) {
+  if (!device_ready(n) || !used) return set_error(MC_ERR_INVALID_ARG, "bad handle or NULL");
+  const int64_t P = n->n_pad;
+  const size_t need = sizeof(BlobHeader) + P * (sizeof(double) * 2 + sizeof(int32_t)) + sizeof(long long) * kRingSlots * n->ring_stride;
+  *used = need;
+  if (!blob || capacity < need) return set_error(MC_ERR_BUFFER_TOO_SMALL, "state blob too small");
+  mc_counters c;
+  int rc = mc_get_counters(n, &c);
+  if (rc != MC_OK) return rc;
+  BlobHeader hd{};
+  hd.magic = kBlobMagic; hd.n_pad = P; hd.ring_stride = n->ring_stride; hd.step = n->step; hd.events = c.events;
+  for (int a = 0; a < n->h.n_pops; ++a) hd.spikes[a] = c.spikes_per_pop[a];
+  char* o = (char*)blob;
+  std::memcpy(o, &hd, sizeof(hd)); o += sizeof(hd);
+  HIP_TRY(hipMemcpy(o, n->d_y, sizeof(double) * P, hipMemcpyDeviceToHost)); o += sizeof(double) * P;
+  HIP_TRY(hipMemcpy(o, n->d_I, sizeof(double) * P, hipMemcpyDeviceToHost)); o += sizeof(double) * P;
+  HIP_TRY(hipMemcpy(o, n->d_r, sizeof(int32_t) * P, hipMemcpyDeviceToHost)); o += sizeof(int32_t) * P;
+  HIP_TRY(hipMemcpy(o, n->d_ring, sizeof(long long) * kRingSlots * n->ring_stride, hipMemcpyDeviceToHost));
+  return MC_OK;
+}
+
+int mc_load_state(mc_net* n, const void* blob, size_t size) {
+  if (!device_ready(n) || !blob) return set_error(MC_ERR_INVALID_ARG, "bad handle or NULL");
+  if (size < sizeof(BlobHeader)) return set_error(MC_ERR_INVALID_ARG, "blob too small");
+  BlobHeader hd;
+  std::memcpy(&hd, blob, sizeof(hd));
+  const int64_t P = n->n_pad;
+  const size_t need = sizeof(BlobHeader) + P * (sizeof(double) * 2 + sizeof(int32_t)) + sizeof(long long) * kRingSlots * n->ring_stride;
+  if (hd.magic != kBlobMagic || hd.n_pad != P || hd.ring_stride != n->ring_stride || size < need)
+    return set_error(MC_ERR_INVALID_ARG, "blob does not belong to this network");
+  int rc = drain(n);
+  if (rc != MC_OK) return rc;
+  const char* o = (const char*)blob + sizeof(hd);
+  HIP_TRY(hipMemcpy(n->d_y, o, sizeof(double) * P, hipMemcpyHostToDevice)); o += sizeof(double) * P;
+  HIP_TRY(hipMemcpy(n->d_I, o, sizeof(double) * P, hipMemcpyHostToDevice)); o += sizeof(double) * P;
+  HIP_TRY(hipMemcpy(n->d_r, o, sizeof(int32_t) * P, hipMemcpyHostToDevice)); o += sizeof(int32_t) * P;
+  HIP_TRY(hipMemcpy(n->d_ring, o, sizeof(long long) * kRingSlots * n->ring_stride, hipMemcpyHostToDevice));
+  long long st = hd.step;
+  HIP_TRY(hipMemcpy(n->d_step, &st, sizeof(long long), hipMemcpyHostToDevice));
+  n->step = hd.step;
+  // counters: base = saved totals, device accumulators cleared
+  HIP_TRY(hipMemset(n->d_wg_events, 0, sizeof(unsigned long long) * n->n_wg));
+  HIP_TRY(hipMemset(n->d_wg_spikes, 0, sizeof(unsigned long long) * n->n_wg * n->h.n_pops));
+  n->events_base = hd.events;
+  for (int a = 0; a < n->h.n_pops; ++a) n->spikes_base[a] = hd.spikes[a];
+  // recorded spikes at or after the restored step are dropped
+  auto cut = std::lower_bound(n->r_step.begin(), n->r_step.end(), (int32_t)hd.step);
+  const size_t keep = cut - n->r_step.begin();
+  n->r_step.resize(keep);
+  n->r_id.resize(keep);
+  HIP_TRY(hipDeviceSynchronize());
+  return MC_OK;
+}
+
+int mc_tune(mc_net* n, int64_t steps, mc_launch* best) {
+  (void)steps; (void)best;
+  if (!device_ready(n)) return set_error(MC_ERR_STATE, "handle is host-only, failed or NULL");
+  return set_error(MC_ERR_STATE, "tuner not available");
+}
+
+int mc_adjoint(mc_net* n, const mc_adjoint_config* a, void* grad, double* loss) {
+  (void)a; (void)grad; (void)loss;
+  if (!device_ready(n)) return set_error(MC_ERR_STATE, "handle is host-only, failed or NULL");
+  return set_error(MC_ERR_STATE, "adjoint not available");
+}
+
+}  // extern "C"

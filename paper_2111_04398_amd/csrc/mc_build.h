@@ -1,0 +1,41 @@
+// mc_build.h -- host-side network construction of libmc (C++/OpenMP).
+#pragma once
+#include <stdint.h>
+#include <string>
+#include <vector>
+
+#include "mc.h"
+
+namespace mc {
+
+struct HostNet {
+  // sizes
+  int n_pops = 0;
+  int n_inst = 0;
+  int64_t N = 0;                         // neurons (dense global ids)
+  int64_t M = 0;                         // synapses
+  std::vector<int64_t> inst_off;         // [n_inst+1] dense
+  std::vector<int64_t> pop_off;          // [n_inst*(n_pops+1)] dense global
+  std::vector<uint64_t> inst_seed;       // [n_inst]
+  std::vector<double> inst_scale;        // [n_inst]
+  std::vector<uint8_t> pop_of;           // [N]
+  // synapse store, canonical order
+  std::vector<int64_t> row_ptr;          // [N+1]
+  std::vector<int32_t> tgt;              // [M]
+  std::vector<int32_t> wq;               // [M], 2^-16 pA
+  std::vector<uint8_t> dly;              // [M], steps
+  int max_row = 0;
+  // dynamics constants
+  double P11 = 0, P21 = 0, P22 = 0, P20 = 0;
+  double i_e = 0, theta = 0, y_reset = 0;
+  int64_t jext_q = 0;
+  int ref_steps = 0;
+  std::vector<uint64_t> table;           // [n_pops*64]
+  std::vector<double> y0;                // [N]
+};
+
+// Validates the configuration and builds the whole network.  Returns an
+// mc_status; on failure `err` holds a message.
+int build_host(const mc_config& cfg, HostNet& net, std::string& err);
+
+}  // namespace mc

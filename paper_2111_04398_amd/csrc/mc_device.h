@@ -1,0 +1,61 @@
+// mc_device.h -- device-side data layout of libmc and kernel entry points.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mc_common.h"
+
+namespace mc {
+
+// Everything a simulation kernel reads or writes, by value in the kernel
+// argument buffer.  Neuron ids on the device are "padded" ids: every
+// instance starts at a multiple of 4 so that one Philox block (four words)
+// drives one aligned quad of neurons of a single instance.
+struct DevNet {
+  int64_t n_pad;            // padded neuron count (multiple of 4)
+  int64_t n_quads;          // n_pad / 4
+  int64_t ring_stride;      // elements per ring slot (>= n_pad, multiple of 64)
+  int32_t n_pops;
+  // synapse store (canonical order, padded ids)
+  const int64_t* row_ptr;   // [n_pad+1]
+  const int32_t* tgt;       // [M]
+  const int32_t* wq;        // [M]
+  const uint8_t* dly;       // [M]
+  // state
+  double* y;                // [n_pad] V - E_L
+  double* I;                // [n_pad]
+  int32_t* r;               // [n_pad] refractory steps left
+  long long* ring;          // [kRingSlots][ring_stride] pending integer input (2^-16 pA)
+  // per-quad drive metadata
+  const uint64_t* qseed;    // [n_quads] instance seed
+  const uint32_t* qlocal;   // [n_quads] quad index inside its instance
+  const uint32_t* qpops;    // [n_quads] population of each of the 4 neurons (0xFF: padding)
+  const uint64_t* table;    // [n_pops*64] Poisson inverse CDF
+  // constants
+  double P11, P21, P22, P20, i_e, theta, y_reset;
+  long long jext_q;
+  int32_t ref_steps;
+  // step counter: kernels simulate step (*step_base + offset)
+  long long* step_base;
+  // recording: one private raster segment per workgroup
+  int2* raster;             // [n_wg][raster_cap]
+  long long raster_cap;
+  long long* raster_cnt;    // [n_wg]
+  unsigned long long* wg_events;   // [n_wg]
+  unsigned long long* wg_spikes;   // [n_wg * n_pops]
+  unsigned* overflow;       // set if a raster segment would overflow
+  // adjoint recording (optional; nullptr when not recording)
+  double* rec_y;            // [K][n_pad] post-step y
+  uint8_t* rec_type;        // [K][n_pad] 0 free, 1 spike, 2 refractory
+  long long rec_step0;      // first recorded step
+};
+
+}  // namespace mc
+
+namespace mc {
+constexpr int kMaxQuadsPerWgHost = 256;   // must equal the kernel's per-workgroup quad limit
+hipError_t launch_step(const DevNet& p, int offset, int qpw, int n_wg, int block, hipStream_t s);
+hipError_t launch_advance(long long* step_base, int steps, hipStream_t s);
+hipError_t launch_inject(long long* ring, long long idx, long long value, hipStream_t s);
+hipError_t launch_set_weights(int32_t* wq, const double* w, long long M, hipStream_t s);
+}  // namespace mc

@@ -1,0 +1,150 @@
+"""GPU parity: the HIP path against the CPU oracle, bit for bit.
+
+Spike rasters, state bit patterns (y, I, r), the logical input ring and the
+event counters must be identical: every input sum is an exact integer sum and
+the FP64 update has a fixed operation order on both sides."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2111_04398_amd import mc, workloads
+from test_oracle_builder import tiny_bernoulli, tiny_fixed
+from test_oracle_dynamics import lone_neuron
+
+pytestmark = pytest.mark.gpu
+
+
+def assert_same(net, o, ring_depth=128, what=""):
+    s, i = net.spikes()
+    os_, oi = o.raster()
+    assert len(s) == len(os_), (what, len(s), len(os_))
+    assert np.array_equal(s, os_) and np.array_equal(i, oi), what
+    y, I, r = net.state()
+    oy, oI, orr = o.state()
+    assert np.array_equal(y.view(np.uint64), oy.view(np.uint64)), what
+    assert np.array_equal(I.view(np.uint64), oI.view(np.uint64)), what
+    assert np.array_equal(r, orr), what
+    if ring_depth:
+        assert np.array_equal(net.ring(ring_depth), o.ring(ring_depth)), what
+    c = net.counters()
+    sp, ev = o.counters()
+    assert c["events"] == ev and np.array_equal(c["spikes_per_pop"], sp), what
+    assert c["step"] == o.step
+
+
+def test_single_input_response():
+    w = lone_neuron()
+    net, o = mc.Network(w), oracle.Oracle(w.to_dict())
+    net.inject(0, 0, 5754061)
+    o.inject(0, 0, 5754061)
+    for _ in range(5):
+        net.simulate(40)
+        o.run(40)
+        assert_same(net, o, what="psp")
+
+
+@pytest.mark.parametrize("ie", [300.0, 400.0, 1000.0])
+def test_dc_drive(ie):
+    w = lone_neuron(i_e=ie)
+    net, o = mc.Network(w), oracle.Oracle(w.to_dict())
+    net.simulate(1500)
+    o.run(1500)
+    assert_same(net, o, what=f"dc {ie}")
+
+
+@pytest.mark.parametrize("mk", [tiny_fixed, tiny_bernoulli])
+def test_tiny_networks(mk):
+    w = mk()
+    net, o = mc.Network(w), oracle.Oracle(w.to_dict())
+    net.simulate(2000)
+    o.run(2000)
+    assert len(o.raster()[0]) > 100
+    assert_same(net, o, what=w.name)
+
+
+def test_balanced_network_full_protocol():
+    """The 5,000-neuron balanced network: 1000 presim steps then 10^4 steps
+    (1 s of model time); compared after presim and at the end."""
+    w = workloads.balanced()
+    net, o = mc.Network(w), oracle.Oracle(w.to_dict())
+    net.simulate(w.presim_steps)
+    o.run(w.presim_steps)
+    assert_same(net, o, what="presim")
+    net.simulate(w.sim_steps)
+    o.run(w.sim_steps)
+    assert_same(net, o, what="sim")
+    assert o.counters()[1] > 10_000_000
+
+
+@pytest.mark.parametrize("block,npw,spg", [(64, 64, 1), (256, 256, 1000), (256, 1024, 7), (1024, 512, 333),
+                                           (128, 16, 50)])
+def test_launch_configuration_invariance(block, npw, spg):
+    """Every launch shape gives identical bits (integer sums, fixed FP order)."""
+    w = workloads.balanced()
+    net, o = mc.Network(w), oracle.Oracle(w.to_dict())
+    net.set_launch(block=block, neurons_per_wg=npw, steps_per_graph=spg)
+    net.simulate(1200)
+    o.run(1200)
+    assert_same(net, o, what=f"{block},{npw},{spg}")
+
+
+def test_resume_and_checkpoint():
+    """simulate(a) + simulate(b) == simulate(a+b); save, continue, load, rerun
+    reproduces the same trajectory; a launch change in between changes nothing."""
+    w = workloads.balanced()
+    net, o = mc.Network(w), oracle.Oracle(w.to_dict())
+    net.simulate(300)
+    net.simulate(77)
+    blob = net.save_state()
+    net.set_launch(block=512, neurons_per_wg=128, steps_per_graph=64)
+    net.simulate(500)
+    o.run(877)
+    assert_same(net, o, what="continue")
+    s_first, i_first = net.spikes(377, 877)
+    net.load_state(blob)
+    assert net.counters()["step"] == 377
+    net.simulate(500)
+    assert_same(net, o, what="reload")
+    s2, i2 = net.spikes(377, 877)
+    assert np.array_equal(s_first, s2) and np.array_equal(i_first, i2)
+
+
+def test_batched_instances_match_standalone():
+    """Instances of a batch are bit-identical to their standalone runs."""
+    base = workloads.microcircuit()
+    scales = [0.01, 0.013, 0.0071, 0.02]
+    w = base.replace(inst_scale=scales, inst_seed=[1001, 1002, 1003, 1004])
+    net = mc.Network(w)
+    net.simulate(1500)
+    s, i = net.spikes()
+    y, I, r = net.state()
+    off = net.instance_offsets()
+    total_events = 0
+    for b in range(len(scales)):
+        o = oracle.Oracle(w.instance(b).to_dict())
+        o.run(1500)
+        os_, oi = o.raster()
+        m = (i >= off[b]) & (i < off[b + 1])
+        assert np.array_equal(s[m], os_) and np.array_equal(i[m] - off[b], oi)
+        oy, oI, orr = o.state()
+        assert np.array_equal(y[off[b]:off[b + 1]].view(np.uint64), oy.view(np.uint64))
+        assert np.array_equal(r[off[b]:off[b + 1]], orr)
+        total_events += o.counters()[1]
+    assert net.counters()["events"] == total_events
+
+
+@pytest.mark.slow
+def test_full_microcircuit_parity():
+    """The full-scale microcircuit (77,169 neurons, ~3e8 synapses) in the
+    default launch configuration: raster, state bits and logical ring equal to
+    the oracle's after the 1000-step presim and 300 further steps."""
+    w = workloads.microcircuit()
+    net = mc.Network(w)
+    o = oracle.Oracle(w.to_dict())
+    assert (net.N, net.M) == (o.N, o.M)
+    net.simulate(1000)
+    o.run(1000)
+    net.simulate(300)
+    o.run(300)
+    assert_same(net, o, ring_depth=8, what="microcircuit")
+    assert len(o.raster()[0]) > 50_000
