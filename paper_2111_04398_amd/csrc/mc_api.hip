@@ -82,9 +82,17 @@ struct mc_net {
   uint32_t* d_qpops = nullptr;
   uint64_t* d_table = nullptr;
   long long* d_step = nullptr;
+  // persistent LDS scheme
+  int n_cu = 0;
+  int lds_max = 65536;
+  int pG = 0, pB = 0, pDL = 0;
+  long long* d_blk = nullptr;
+  unsigned long long* d_flags = nullptr;
+  int* d_pub = nullptr;
   // recording
   int n_wg = 0;
   int qpw = 0;
+  int wg_neurons = 0;                  // neurons updated by one workgroup (raster bound)
   int2* d_raster = nullptr;
   long long raster_cap = 0;            // per workgroup
   long long* d_raster_cnt = nullptr;
@@ -119,6 +127,14 @@ struct mc_net {
     return p;
   }
 
+  PersistArgs persist() const {
+    PersistArgs a{};
+    a.G = pG; a.B = pB; a.DL = pDL; a.BW = (pB + 31) / 32;
+    a.blk = d_blk; a.flags = d_flags; a.pub = d_pub;
+    a.spin_limit = 1LL << 24;
+    return a;
+  }
+
   // dense id -> instance
   int inst_of(int64_t dense) const {
     return (int)(std::upper_bound(h.inst_off.begin(), h.inst_off.end(), dense) - h.inst_off.begin()) - 1;
@@ -151,6 +167,7 @@ int release_recording(mc_net* n) {
 void release_all(mc_net* n) {
   if (n->graph) { (void)hipGraphExecDestroy(n->graph); n->graph = nullptr; }
   release_recording(n);
+  dev_free(n->d_blk); dev_free(n->d_flags); dev_free(n->d_pub);
   dev_free(n->d_overflow);
   dev_free(n->d_row_ptr); dev_free(n->d_tgt); dev_free(n->d_wq); dev_free(n->d_dly);
   dev_free(n->d_y); dev_free(n->d_I); dev_free(n->d_r); dev_free(n->d_ring);
@@ -219,7 +236,7 @@ int setup_recording(mc_net* n, int64_t steps) {
   // a captured graph holds the old buffer addresses
   if (n->graph) { (void)hipGraphExecDestroy(n->graph); n->graph = nullptr; }
   release_recording(n);
-  const int64_t neurons = 4LL * n->qpw;
+  const int64_t neurons = n->wg_neurons;
   n->raster_cap = spike_bound(neurons, steps, n->h.ref_steps) + 1;
   n->cap_steps = steps;
   if ((rc = dev_alloc(&n->d_raster, (size_t)n->n_wg * n->raster_cap)) != MC_OK) return rc;
@@ -236,23 +253,60 @@ int setup_recording(mc_net* n, int64_t steps) {
 
 int validate_launch(const mc_net* n, const mc_launch& l) {
   if (l.struct_size != sizeof(mc_launch)) return set_error(MC_ERR_INVALID_ARG, "mc_launch.struct_size mismatch");
-  if (l.scheme != MC_SCHEME_STEP_KERNELS) return set_error(MC_ERR_INVALID_ARG, "unsupported scheme");
+  if (l.scheme != MC_SCHEME_STEP_KERNELS && l.scheme != MC_SCHEME_PERSISTENT_LDS)
+    return set_error(MC_ERR_INVALID_ARG, "unknown scheme");
   if (l.block < 64 || l.block > 1024 || l.block % 64) return set_error(MC_ERR_INVALID_ARG, "block must be a multiple of 64 in [64, 1024]");
   const int npw = l.neurons_per_wg;
-  if (npw < 0 || npw % 4 || npw > 4 * l.block || npw > 4 * kMaxQuadsPerWgHost)
+  const int npw_max = l.scheme == MC_SCHEME_STEP_KERNELS ? 4 * kMaxQuadsPerWgHost : kPersistMaxB;
+  if (npw < 0 || npw % 4 || npw > 4 * l.block || npw > npw_max)
     return set_error(MC_ERR_INVALID_ARG, "neurons_per_wg must be a multiple of 4, <= 4*block and <= 1024");
-  if (l.steps_per_graph < 1 || l.steps_per_graph > 100000) return set_error(MC_ERR_INVALID_ARG, "steps_per_graph out of [1, 100000]");
+  if (l.steps_per_graph < 0 || l.steps_per_graph > 100000) return set_error(MC_ERR_INVALID_ARG, "steps_per_graph out of [0, 100000]");
   (void)n;
+  return MC_OK;
+}
+
+// Shape of the persistent scheme: G co-resident workgroups owning B targets
+// each, DL near steps of input in LDS (as many as the LDS holds, <= 101).
+int persist_shape(mc_net* n, const mc_launch& l, int* G, int* B, int* DL) {
+  int b = l.neurons_per_wg;
+  if (b == 0) {
+    const int g = std::max(1, std::min(n->n_cu, l.block));
+    b = (int)align_up((n->n_pad + g - 1) / g, 4);
+  }
+  if (b > kPersistMaxB || b > 4 * l.block)
+    return set_error(MC_ERR_RANGE, "network too large for the persistent LDS scheme at this block size");
+  const int g = (int)((n->n_pad + b - 1) / b);
+  if (g > l.block) return set_error(MC_ERR_RANGE, "persistent scheme needs workgroups <= threads per workgroup");
+  size_t stat = 0;
+  HIP_TRY(persist_static_lds(&stat));
+  const size_t base = persist_lds_bytes(g, b, 0);
+  if (stat + base + 2 * (size_t)b * 8 > (size_t)n->lds_max) return set_error(MC_ERR_RANGE, "LDS too small for the persistent scheme");
+  const int dl = (int)std::min<size_t>(101, (n->lds_max - stat - base) / ((size_t)b * 8));
+  const size_t lds = persist_lds_bytes(g, b, dl);
+  HIP_TRY(persist_set_lds_limit(lds));
+  int occ = 0;
+  HIP_TRY(persist_occupancy(l.block, lds, &occ));
+  if (occ < 1 || g > n->n_cu * occ)
+    return set_error(MC_ERR_RANGE, "persistent workgroups would not all be co-resident");
+  *G = g; *B = b; *DL = dl;
   return MC_OK;
 }
 
 int apply_launch(mc_net* n, const mc_launch& l) {
   int rc = validate_launch(n, l);
   if (rc != MC_OK) return rc;
-  int qpw = l.neurons_per_wg / 4;
-  if (qpw == 0) qpw = std::min<int>(l.block, 64);
-  const int n_wg = (int)((n->n_quads + qpw - 1) / qpw);
-  const bool shape_changed = (qpw != n->qpw || n_wg != n->n_wg);
+  int qpw = 0, n_wg = 0, wg_neurons = 0, G = 0, B = 0, DL = 0;
+  if (l.scheme == MC_SCHEME_STEP_KERNELS) {
+    qpw = l.neurons_per_wg / 4;
+    if (qpw == 0) qpw = std::min<int>(l.block, 64);
+    n_wg = (int)((n->n_quads + qpw - 1) / qpw);
+    wg_neurons = 4 * qpw;
+  } else {
+    if ((rc = persist_shape(n, l, &G, &B, &DL)) != MC_OK) return rc;
+    n_wg = G;
+    wg_neurons = B;
+  }
+  const bool shape_changed = (l.scheme != n->launch.scheme || n_wg != n->n_wg || wg_neurons != n->wg_neurons);
   if (n->graph && (shape_changed || l.steps_per_graph != n->graph_steps || l.block != n->launch.block)) {
     (void)hipGraphExecDestroy(n->graph);
     n->graph = nullptr;
@@ -261,8 +315,19 @@ int apply_launch(mc_net* n, const mc_launch& l) {
     if ((rc = drain(n)) != MC_OK) return rc;
     if ((rc = fold_counters(n)) != MC_OK) return rc;
     release_recording(n);   // sized for the old shape
+    if (l.scheme == MC_SCHEME_PERSISTENT_LDS) {
+      dev_free(n->d_blk); dev_free(n->d_flags); dev_free(n->d_pub);
+      if ((rc = dev_alloc(&n->d_blk, (size_t)n->n_pad * (G + 1))) != MC_OK) return rc;
+      if ((rc = dev_alloc(&n->d_flags, (size_t)G * kPersistFlagStride)) != MC_OK) return rc;
+      if ((rc = dev_alloc(&n->d_pub, (size_t)G * 2 * B)) != MC_OK) return rc;
+      HIP_TRY(launch_build_blk(n->d_row_ptr, n->d_tgt, n->n_pad, G, B, n->d_blk, n->stream));
+      HIP_TRY(hipMemsetAsync(n->d_flags, 0, sizeof(unsigned long long) * G * kPersistFlagStride, n->stream));
+      HIP_TRY(hipStreamSynchronize(n->stream));
+    }
     n->qpw = qpw;
     n->n_wg = n_wg;
+    n->wg_neurons = wg_neurons;
+    n->pG = G; n->pB = B; n->pDL = DL;
     n->launch = l;
     if ((rc = setup_recording(n, std::max<int64_t>(n->cap_steps, 4096))) != MC_OK) return rc;
   }
@@ -270,17 +335,28 @@ int apply_launch(mc_net* n, const mc_launch& l) {
   return MC_OK;
 }
 
+// Enqueues `count` steps directly (no graph) on stream s.
+hipError_t enqueue_direct(mc_net* n, int count, hipStream_t s) {
+  const DevNet p = n->dev();
+  hipError_t e = hipSuccess;
+  if (n->launch.scheme == MC_SCHEME_STEP_KERNELS) {
+    for (int k = 0; k < count && e == hipSuccess; ++k) e = launch_step(p, k, n->qpw, n->n_wg, n->launch.block, s);
+  } else {
+    e = launch_persist(p, n->persist(), count, n->launch.block, s);
+  }
+  if (e == hipSuccess) e = launch_advance(n->d_step, count, s);
+  return e;
+}
+
 int build_graph(mc_net* n) {
   if (n->graph) return MC_OK;
   hipStream_t cs;
   HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-  const DevNet p = n->dev();
   const int S = n->launch.steps_per_graph;
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    for (int k = 0; k < S && e == hipSuccess; ++k) e = launch_step(p, k, n->qpw, n->n_wg, n->launch.block, cs);
-    if (e == hipSuccess) e = launch_advance(n->d_step, S, cs);
+    e = enqueue_direct(n, S, cs);
     hipError_t e2 = hipStreamEndCapture(cs, &g);
     if (e == hipSuccess) e = e2;
   }
@@ -292,7 +368,8 @@ int build_graph(mc_net* n) {
   return MC_OK;
 }
 
-// Enqueues `steps` steps (no synchronization).
+// Enqueues `steps` steps (no synchronization).  Steps are replayed from a
+// graph of steps_per_graph steps where possible (0: never).
 int enqueue_steps(mc_net* n, int64_t steps) {
   int rc;
   int64_t left = steps;
@@ -304,15 +381,14 @@ int enqueue_steps(mc_net* n, int64_t steps) {
     }
     int64_t chunk = std::min(left, room);
     const int S = n->launch.steps_per_graph;
-    if (chunk >= S) {
+    if (S > 0 && chunk >= S) {
       if ((rc = build_graph(n)) != MC_OK) return rc;
       const int64_t reps = chunk / S;
       for (int64_t k = 0; k < reps; ++k) HIP_TRY(hipGraphLaunch(n->graph, n->stream));
       chunk = reps * S;
     } else {
-      const DevNet p = n->dev();
-      for (int k = 0; k < (int)chunk; ++k) HIP_TRY(launch_step(p, k, n->qpw, n->n_wg, n->launch.block, n->stream));
-      HIP_TRY(launch_advance(n->d_step, (int)chunk, n->stream));
+      chunk = std::min<int64_t>(chunk, 1 << 20);
+      HIP_TRY(enqueue_direct(n, (int)chunk, n->stream));
     }
     n->steps_since_drain += chunk;
     n->step += chunk;
@@ -443,6 +519,12 @@ int mc_build_network(const mc_config* cfg, mc_net** out) {
     if (hipGetDeviceProperties(&prop, n->device) != hipSuccess) return set_error(MC_ERR_NO_DEVICE, "hipGetDeviceProperties failed");
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
       return set_error(MC_ERR_NO_DEVICE, std::string("device is ") + prop.gcnArchName + ", library built for gfx950");
+    n->n_cu = prop.multiProcessorCount;
+    int optin = 0;
+    if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, n->device) == hipSuccess && optin > 0)
+      n->lds_max = optin;
+    else
+      n->lds_max = (int)prop.sharedMemPerBlock;
     if (cfg->hip_stream) { n->stream = (hipStream_t)cfg->hip_stream; n->own_stream = false; }
     else {
       if (hipStreamCreateWithFlags(&n->stream, hipStreamNonBlocking) != hipSuccess) return set_error(MC_ERR_HIP, "stream creation failed");

@@ -53,6 +53,28 @@ struct DevNet {
 }  // namespace mc
 
 namespace mc {
+
+// Arguments of the persistent LDS kernel (target-owner delivery).
+struct PersistArgs {
+  int G;                       // workgroups (all co-resident, G <= block)
+  int B;                       // target neurons per workgroup (multiple of 4, <= 1024)
+  int DL;                      // near slots held in LDS (2..101)
+  int BW;                      // 32-bit words per far-bitmap row: ceil(B/32)
+  const long long* blk;        // [n_pad][G+1] absolute synapse offsets of each target block
+  unsigned long long* flags;   // [G * 8]  (tag << 32) | count, 64 bytes apart
+  int* pub;                    // [G][2][B] published spike ids
+  long long spin_limit;        // polls before giving up
+};
+constexpr int kPersistFlagStride = 8;
+constexpr int kPersistMaxB = 1024;
+size_t persist_lds_bytes(int G, int B, int DL);
+hipError_t persist_static_lds(size_t* bytes);
+hipError_t persist_occupancy(int block, size_t lds, int* blocks_per_cu);
+hipError_t persist_set_lds_limit(size_t lds);
+hipError_t launch_persist(const DevNet& p, const PersistArgs& a, int steps, int block, hipStream_t s);
+hipError_t launch_build_blk(const int64_t* row_ptr, const int32_t* tgt, long long n_pad, int G, int B, long long* blk,
+                            hipStream_t s);
+
 constexpr int kMaxQuadsPerWgHost = 256;   // must equal the kernel's per-workgroup quad limit
 hipError_t launch_step(const DevNet& p, int offset, int qpw, int n_wg, int block, hipStream_t s);
 hipError_t launch_advance(long long* step_base, int steps, hipStream_t s);

@@ -76,16 +76,41 @@ def test_balanced_network_full_protocol():
     assert o.counters()[1] > 10_000_000
 
 
-@pytest.mark.parametrize("block,npw,spg", [(64, 64, 1), (256, 256, 1000), (256, 1024, 7), (1024, 512, 333),
-                                           (128, 16, 50)])
-def test_launch_configuration_invariance(block, npw, spg):
-    """Every launch shape gives identical bits (integer sums, fixed FP order)."""
+@pytest.mark.parametrize("scheme,block,npw,spg", [
+    (0, 64, 64, 1), (0, 256, 256, 1000), (0, 256, 1024, 7), (0, 1024, 512, 333), (0, 128, 16, 50), (0, 256, 256, 0),
+    (1, 1024, 0, 1000), (1, 256, 0, 100), (1, 512, 64, 7), (1, 1024, 1024, 250), (1, 1024, 200, 0)])
+def test_launch_configuration_invariance(scheme, block, npw, spg):
+    """Every launch shape of both schemes gives identical bits (integer sums,
+    fixed FP order).  neurons_per_wg = 1024 leaves room for only ~15 delay
+    steps in LDS, so most events take the far (global) path."""
     w = workloads.balanced()
     net, o = mc.Network(w), oracle.Oracle(w.to_dict())
-    net.set_launch(block=block, neurons_per_wg=npw, steps_per_graph=spg)
+    net.set_launch(scheme=scheme, block=block, neurons_per_wg=npw, steps_per_graph=spg)
     net.simulate(1200)
     o.run(1200)
-    assert_same(net, o, what=f"{block},{npw},{spg}")
+    assert_same(net, o, what=f"{scheme},{block},{npw},{spg}")
+
+
+@pytest.mark.parametrize("mk", [tiny_fixed, tiny_bernoulli])
+def test_tiny_networks_persistent(mk):
+    w = mk()
+    net, o = mc.Network(w), oracle.Oracle(w.to_dict())
+    net.set_launch(scheme=1, block=256, neurons_per_wg=0, steps_per_graph=500)
+    net.simulate(2000)
+    o.run(2000)
+    assert_same(net, o, what=w.name)
+
+
+def test_scheme_switch_midway():
+    """Switching between the schemes in the middle of a run changes nothing."""
+    w = workloads.balanced()
+    net, o = mc.Network(w), oracle.Oracle(w.to_dict())
+    for k, sch in enumerate([1, 0, 1, 1, 0]):
+        net.set_launch(scheme=sch, block=1024 if sch else 256, neurons_per_wg=0 if sch else 256,
+                       steps_per_graph=97 + k)
+        net.simulate(311)
+    o.run(5 * 311)
+    assert_same(net, o, what="switch")
 
 
 def test_resume_and_checkpoint():
@@ -133,18 +158,39 @@ def test_batched_instances_match_standalone():
     assert net.counters()["events"] == total_events
 
 
-@pytest.mark.slow
-def test_full_microcircuit_parity():
-    """The full-scale microcircuit (77,169 neurons, ~3e8 synapses) in the
-    default launch configuration: raster, state bits and logical ring equal to
-    the oracle's after the 1000-step presim and 300 further steps."""
+@pytest.fixture(scope="module")
+def micro_oracle_runs():
+    """Oracle trajectory of the full microcircuit: after 1000 and 1300 steps."""
     w = workloads.microcircuit()
-    net = mc.Network(w)
     o = oracle.Oracle(w.to_dict())
-    assert (net.N, net.M) == (o.N, o.M)
-    net.simulate(1000)
     o.run(1000)
-    net.simulate(300)
+    a = (o.raster(), o.state(), o.ring(8), o.counters())
     o.run(300)
-    assert_same(net, o, ring_depth=8, what="microcircuit")
-    assert len(o.raster()[0]) > 50_000
+    b = (o.raster(), o.state(), o.ring(8), o.counters())
+    return w, o.N, o.M, a, b
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_full_microcircuit_parity(micro_oracle_runs, scheme):
+    """The full-scale microcircuit (77,169 neurons, ~3e8 synapses): raster,
+    state bits and the first logical ring slots equal to the oracle's after
+    the 1000-step presim and after 300 further steps, in both schemes (the
+    benchmark's launch configuration is the default of the scheme)."""
+    w, N, M, a, b = micro_oracle_runs
+    net = mc.Network(w)
+    if scheme == 1:
+        net.set_launch(scheme=1, block=1024, neurons_per_wg=0, steps_per_graph=1000)
+    assert (net.N, net.M) == (N, M)
+    for steps, (ras, st, ring, cnt) in ((1000, a), (300, b)):
+        net.simulate(steps)
+        s, i = net.spikes()
+        assert np.array_equal(s, ras[0]) and np.array_equal(i, ras[1])
+        y, I, r = net.state()
+        assert np.array_equal(y.view(np.uint64), st[0].view(np.uint64))
+        assert np.array_equal(I.view(np.uint64), st[1].view(np.uint64))
+        assert np.array_equal(r, st[2])
+        assert np.array_equal(net.ring(8), ring)
+        c = net.counters()
+        assert c["events"] == cnt[1] and np.array_equal(c["spikes_per_pop"], cnt[0])
+    assert len(b[0][0]) > 50_000
