@@ -64,6 +64,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=1500)
     ap.add_argument("--launch", default="", help="scheme,block,neurons_per_wg,steps_per_graph")
+    ap.add_argument("--phases", type=int, default=0, help="after timing, profile this many steps per phase")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -134,6 +135,8 @@ def main() -> int:
         },
         "paper_context": {"rtf_2x64_core_epyc_node": 0.67, "rtf_2_nodes": 0.53},
     }
+    if args.phases and launch["scheme"] == mc.SCHEME_PERSISTENT_LDS:
+        out["phases_us_per_step"] = net.profile_phases(args.phases)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, presim=1000, steps=args.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -201,6 +201,15 @@ int mc_get_launch(mc_net* net, mc_launch* l);
 /* Times candidate launch configurations on copies of the current state for
  * `steps` steps each, keeps the fastest (state and raster are restored). */
 int mc_tune(mc_net* net, int64_t steps, mc_launch* best_out);
+/* Simulates `steps` steps with per-phase device timestamps (persistent
+ * scheme only) and returns the mean time per step in microseconds, averaged
+ * over workgroups: us_out[0] update, [1] compaction+publication, [2] wait
+ * for every workgroup's spikes, [3] spike-list gather, [4] delay-1
+ * delivery, [5] the sum of [0..4]; overlapping parts of [2]: [6] drive of
+ * the next step and pending delivery of the previous one (first wavefront),
+ * [7] polling (first polling thread).  The trajectory is the one
+ * mc_simulate would produce. */
+int mc_profile_phases(mc_net* net, int64_t steps, double* us_out_host);
 /* Wall time (ms) of the GPU work of the most recent mc_simulate, from HIP events. */
 int mc_last_simulate_ms(mc_net* net, double* ms_out);
 /* Makes room for the spikes of `steps` further steps so that mc_simulate

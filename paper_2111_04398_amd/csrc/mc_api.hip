@@ -89,6 +89,10 @@ struct mc_net {
   long long* d_blk = nullptr;
   unsigned long long* d_flags = nullptr;
   int* d_pub = nullptr;
+  unsigned long long* d_phase = nullptr;
+  bool phase_on = false;
+  unsigned long long* d_d1 = nullptr;
+  int d1_cap = 0, nsb = 1, wg_per_sb = 1;
   // recording
   int n_wg = 0;
   int qpw = 0;
@@ -132,6 +136,8 @@ struct mc_net {
     a.G = pG; a.B = pB; a.DL = pDL; a.BW = (pB + 31) / 32;
     a.blk = d_blk; a.flags = d_flags; a.pub = d_pub;
     a.spin_limit = 1LL << 24;
+    a.phase = phase_on ? d_phase : nullptr;
+    a.d1 = d_d1; a.d1_cap = d1_cap; a.nsb = nsb; a.wg_per_sb = wg_per_sb;
     return a;
   }
 
@@ -167,7 +173,7 @@ int release_recording(mc_net* n) {
 void release_all(mc_net* n) {
   if (n->graph) { (void)hipGraphExecDestroy(n->graph); n->graph = nullptr; }
   release_recording(n);
-  dev_free(n->d_blk); dev_free(n->d_flags); dev_free(n->d_pub);
+  dev_free(n->d_blk); dev_free(n->d_flags); dev_free(n->d_pub); dev_free(n->d_phase); dev_free(n->d_d1);
   dev_free(n->d_overflow);
   dev_free(n->d_row_ptr); dev_free(n->d_tgt); dev_free(n->d_wq); dev_free(n->d_dly);
   dev_free(n->d_y); dev_free(n->d_I); dev_free(n->d_r); dev_free(n->d_ring);
@@ -256,10 +262,14 @@ int validate_launch(const mc_net* n, const mc_launch& l) {
   if (l.scheme != MC_SCHEME_STEP_KERNELS && l.scheme != MC_SCHEME_PERSISTENT_LDS)
     return set_error(MC_ERR_INVALID_ARG, "unknown scheme");
   if (l.block < 64 || l.block > 1024 || l.block % 64) return set_error(MC_ERR_INVALID_ARG, "block must be a multiple of 64 in [64, 1024]");
+  if (l.scheme == MC_SCHEME_PERSISTENT_LDS && l.block > kPersistMaxBlock)
+    return set_error(MC_ERR_INVALID_ARG, "the persistent scheme runs at most 512 threads per workgroup");
   const int npw = l.neurons_per_wg;
-  const int npw_max = l.scheme == MC_SCHEME_STEP_KERNELS ? 4 * kMaxQuadsPerWgHost : kPersistMaxB;
-  if (npw < 0 || npw % 4 || npw > 4 * l.block || npw > npw_max)
-    return set_error(MC_ERR_INVALID_ARG, "neurons_per_wg must be a multiple of 4, <= 4*block and <= 1024");
+  const int npw_max = l.scheme == MC_SCHEME_STEP_KERNELS ? std::min(4 * l.block, 4 * kMaxQuadsPerWgHost)
+                                                         : std::min(l.block, kPersistMaxB);
+  if (npw < 0 || npw % 4 || npw > npw_max)
+    return set_error(MC_ERR_INVALID_ARG, "neurons_per_wg must be a multiple of 4, <= min(4*block, 1024) (step "
+                                         "kernels) or <= block (persistent)");
   if (l.steps_per_graph < 0 || l.steps_per_graph > 100000) return set_error(MC_ERR_INVALID_ARG, "steps_per_graph out of [0, 100000]");
   (void)n;
   return MC_OK;
@@ -273,7 +283,7 @@ int persist_shape(mc_net* n, const mc_launch& l, int* G, int* B, int* DL) {
     const int g = std::max(1, std::min(n->n_cu, l.block));
     b = (int)align_up((n->n_pad + g - 1) / g, 4);
   }
-  if (b > kPersistMaxB || b > 4 * l.block)
+  if (b > kPersistMaxB || b > l.block)
     return set_error(MC_ERR_RANGE, "network too large for the persistent LDS scheme at this block size");
   const int g = (int)((n->n_pad + b - 1) / b);
   if (g > l.block) return set_error(MC_ERR_RANGE, "persistent scheme needs workgroups <= threads per workgroup");
@@ -318,10 +328,28 @@ int apply_launch(mc_net* n, const mc_launch& l) {
     if (l.scheme == MC_SCHEME_PERSISTENT_LDS) {
       dev_free(n->d_blk); dev_free(n->d_flags); dev_free(n->d_pub);
       if ((rc = dev_alloc(&n->d_blk, (size_t)n->n_pad * (G + 1))) != MC_OK) return rc;
-      if ((rc = dev_alloc(&n->d_flags, (size_t)G * kPersistFlagStride)) != MC_OK) return rc;
+      if ((rc = dev_alloc(&n->d_flags, (size_t)G * 2 * kPersistFlagStride)) != MC_OK) return rc;
       if ((rc = dev_alloc(&n->d_pub, (size_t)G * 2 * B)) != MC_OK) return rc;
       HIP_TRY(launch_build_blk(n->d_row_ptr, n->d_tgt, n->n_pad, G, B, n->d_blk, n->stream));
-      HIP_TRY(hipMemsetAsync(n->d_flags, 0, sizeof(unsigned long long) * G * kPersistFlagStride, n->stream));
+      HIP_TRY(hipMemsetAsync(n->d_flags, 0, sizeof(unsigned long long) * G * 2 * kPersistFlagStride, n->stream));
+      // delay-1 table: per (source, superblock of wg_per_sb target blocks)
+      dev_free(n->d_d1);
+      n->nsb = std::min(8, G);
+      n->wg_per_sb = (G + n->nsb - 1) / n->nsb;
+      const long long sb_size = (long long)n->wg_per_sb * B;
+      const size_t slots = (size_t)n->n_pad * n->nsb;
+      int* d_cnt = nullptr;
+      if ((rc = dev_alloc(&d_cnt, slots)) != MC_OK) return rc;
+      std::vector<int> hcnt(slots);
+      hipError_t e = launch_d1_count(n->d_row_ptr, n->d_tgt, n->d_dly, n->n_pad, n->nsb, sb_size, d_cnt, n->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(n->stream);
+      if (e == hipSuccess) e = hipMemcpy(hcnt.data(), d_cnt, sizeof(int) * slots, hipMemcpyDeviceToHost);
+      dev_free(d_cnt);
+      if (e != hipSuccess) return set_error(MC_ERR_HIP, std::string("delay-1 table: ") + hipGetErrorString(e));
+      n->d1_cap = std::max(1, *std::max_element(hcnt.begin(), hcnt.end()));
+      if ((rc = dev_alloc(&n->d_d1, slots * (size_t)(n->d1_cap + 1))) != MC_OK) return rc;
+      HIP_TRY(launch_d1_fill(n->d_row_ptr, n->d_tgt, n->d_wq, n->d_dly, n->n_pad, n->nsb, sb_size, n->d1_cap, n->d_d1,
+                             n->stream));
       HIP_TRY(hipStreamSynchronize(n->stream));
     }
     n->qpw = qpw;
@@ -806,6 +834,40 @@ int mc_load_state(mc_net* n, const void* blob, size_t size) {
   n->r_step.resize(keep);
   n->r_id.resize(keep);
   HIP_TRY(hipDeviceSynchronize());
+  return MC_OK;
+}
+
+int mc_profile_phases(mc_net* n, int64_t steps, double* us) {
+  if (!device_ready(n) || !us) return set_error(MC_ERR_INVALID_ARG, "bad handle or NULL");
+  if (n->launch.scheme != MC_SCHEME_PERSISTENT_LDS) return set_error(MC_ERR_STATE, "phase timing needs the persistent scheme");
+  if (steps < 1 || n->step + steps > 2147483647LL) return set_error(MC_ERR_INVALID_ARG, "steps out of range");
+  int rc;
+  dev_free(n->d_phase);
+  if ((rc = dev_alloc(&n->d_phase, (size_t)n->pG * 8)) != MC_OK) return rc;
+  HIP_TRY(hipMemsetAsync(n->d_phase, 0, sizeof(unsigned long long) * n->pG * 8, n->stream));
+  // direct launches: a captured graph would carry the timing-off arguments
+  if (n->graph) { (void)hipGraphExecDestroy(n->graph); n->graph = nullptr; }
+  const int spg = n->launch.steps_per_graph;
+  n->launch.steps_per_graph = 0;
+  n->phase_on = true;
+  rc = enqueue_steps(n, steps);
+  n->phase_on = false;
+  n->launch.steps_per_graph = spg;
+  if (rc != MC_OK) return rc;
+  HIP_TRY(hipStreamSynchronize(n->stream));
+  std::vector<unsigned long long> h((size_t)n->pG * 8);
+  HIP_TRY(hipMemcpy(h.data(), n->d_phase, sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost));
+  int khz = 100000;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, n->device) != hipSuccess || khz <= 0) khz = 100000;
+  const double tick_us = 1e3 / (double)khz;
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int g = 0; g < n->pG; ++g)
+    for (int k = 0; k < 7; ++k) acc[k] += (double)h[(size_t)g * 8 + k];
+  const double norm = tick_us / ((double)n->pG * (double)steps);
+  us[5] = 0;
+  for (int k = 0; k < 5; ++k) { us[k] = acc[k] * norm; us[5] += us[k]; }
+  us[6] = acc[5] * norm;   // drive + pending delivery of wavefront 0 while waiting
+  us[7] = acc[6] * norm;   // polling of the first poller thread
   return MC_OK;
 }
 

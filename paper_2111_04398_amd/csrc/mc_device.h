@@ -61,13 +61,26 @@ struct PersistArgs {
   int DL;                      // near slots held in LDS (2..101)
   int BW;                      // 32-bit words per far-bitmap row: ceil(B/32)
   const long long* blk;        // [n_pad][G+1] absolute synapse offsets of each target block
-  unsigned long long* flags;   // [G * 8]  (tag << 32) | count, 64 bytes apart
+  unsigned long long* flags;   // [G][2][8] spike records: (tag << 32) | count, (tag << 32) | id x7
   int* pub;                    // [G][2][B] published spike ids
   long long spin_limit;        // polls before giving up
+  unsigned long long* phase;   // optional [G*8]: summed wall_clock64 ticks per phase (nullptr: off)
+  // delay-1 table: for source i and target superblock sb, word 0 = count,
+  // words 1..count = (target << 32) | (uint32)weight of its delay-1 synapses
+  const unsigned long long* d1;   // [n_pad][nsb][d1_cap+1]
+  int d1_cap;                  // entries per (source, superblock) slot
+  int nsb;                     // superblocks
+  int wg_per_sb;               // workgroups per superblock (superblock = wg_per_sb*B targets)
 };
 constexpr int kPersistFlagStride = 8;
-constexpr int kPersistMaxB = 1024;
+constexpr int kPersistMaxB = 512;       // owned targets per workgroup (one per thread)
+constexpr int kPersistMaxBlock = 512;   // threads per workgroup: 256 VGPRs per lane, no scratch spills
 size_t persist_lds_bytes(int G, int B, int DL);
+// Delay-1 table: counts per (source, superblock), then the fill.
+hipError_t launch_d1_count(const int64_t* row_ptr, const int32_t* tgt, const uint8_t* dly, long long n_pad, int nsb,
+                           long long sb_size, int* counts, hipStream_t s);
+hipError_t launch_d1_fill(const int64_t* row_ptr, const int32_t* tgt, const int32_t* wq, const uint8_t* dly,
+                          long long n_pad, int nsb, long long sb_size, int cap, unsigned long long* d1, hipStream_t s);
 hipError_t persist_static_lds(size_t* bytes);
 hipError_t persist_occupancy(int block, size_t lds, int* blocks_per_cu);
 hipError_t persist_set_lds_limit(size_t lds);

@@ -5,23 +5,36 @@
 // at about 20e9 per second for the whole chip, whatever the footprint of the
 // table, so a step of the full microcircuit (~2.5e5 synaptic events) cannot
 // drop below ~12 us if every event is a global atomic.  Here every workgroup
-// owns a contiguous block of B target neurons and keeps their pending input
-// for the next D_L steps in LDS (int64, LDS atomics); it delivers, for every
-// spike of the step, only the part of the source row that targets its own
-// block (rows are sorted by target, so that part is contiguous and an index
-// blk[i][g] gives its bounds).  Events with a delay >= D_L (rare: the delay
-// distribution's tail) go to the global ring with device atomics, into
-// entries only the owner reads.  The only cross-workgroup traffic per step
-// is the spike list: each workgroup publishes its spikes and a tagged flag,
-// and every workgroup waits for all flags of the step before delivering.
+// owns a contiguous block of B target neurons (one per thread) and keeps
+// their pending input for the next D_L steps in LDS (int64, LDS atomics); it
+// delivers, for every spike, only the part of the source row that targets its
+// own block (rows are sorted by target, so that part is contiguous and an
+// index blk[i][g] gives its bounds).  Events with a delay >= D_L (the tail of
+// the delay distribution) go to the global ring with device atomics, into
+// entries only the owner reads.  The only cross-workgroup traffic per step is
+// the spike list.
 //
-// Memory ordering: all cross-workgroup data (spike ids, flags, global ring
-// entries touched during the launch) is written and read with device-scope
-// atomic operations (coherent at the memory side on this chip), and the
-// producer waits for its id stores to complete (s_waitcnt) before it stores
-// the flag.  No L2 writeback/invalidate fences are needed on the step path.
-// Every wait is bounded; on timeout the kernel sets an error bit and all
-// workgroups leave the loop.
+// Critical path.  Only the events of step n with delay 1 must be in place
+// before the update of step n+1, and those with delay 2 before step n+2.
+// Both come from a "near" table (per source and target superblock, fixed
+// capacity, so one load finds them), delivered right after the spike list of
+// step n is known.  The other events are pipelined over the two following
+// steps, while the workgroup waits for the next spike lists: in step n+1 the
+// block bounds blk[i][g] of step n's spikes are loaded, in step n+2 their
+// entries (delay >= 3, landing at step n+3 or later) are added.
+//
+// Spike exchange: workgroup g publishes a 64-byte record per step (two
+// records per workgroup, alternating by step parity, so a record is never
+// rewritten while a slower consumer may still be reading it): word 0 =
+// (tag << 32) | count, words 1..7 = (tag << 32) | id of its first seven
+// spikes, tag = step + 1.  Every word carries the tag, so a consumer accepts
+// a record when all the words it needs show the current tag, whatever order
+// the stores became visible in.  Spikes beyond the seventh are written to a
+// side array before word 0 (with a wait for their completion), so they are
+// visible once word 0 is.  All of these are device-scope atomic accesses
+// (coherent at the memory side), so the step needs no L2 writeback or
+// invalidate.  Every wait is bounded; on timeout the kernel sets an error bit
+// and every workgroup leaves the loop.
 #pragma clang fp contract(off)
 
 #include "mc_device.h"
@@ -30,8 +43,11 @@ namespace mc {
 
 namespace {
 
-constexpr int kListCap = 1024;       // spikes gathered into LDS per pass
-constexpr int kFlagStride = 8;       // flags 64 bytes apart (u64 units)
+constexpr int kListCap = 1024;       // spikes of one step kept in LDS (more: delivered at once)
+constexpr int kRecWords = 8;         // record words (64 bytes)
+constexpr int kInline = kRecWords - 1;
+constexpr int kUnroll = 4;           // entries in flight per lane
+constexpr unsigned kNearD2 = 0x80000000u;   // near-table flag: delay 2 (else 1)
 
 __device__ __forceinline__ int poisson_inv(const uint64_t* T, uint32_t u) {
   int k = 0;
@@ -39,18 +55,18 @@ __device__ __forceinline__ int poisson_inv(const uint64_t* T, uint32_t u) {
   return k;
 }
 
-__device__ __forceinline__ long long ld_dev(const long long* p) {
+template <class T>
+__device__ __forceinline__ T ld_dev(const T* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ unsigned long long ld_dev(const unsigned long long* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ int ld_dev(const int* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+template <class T>
+__device__ __forceinline__ void st_dev(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Block-wide exclusive scan of v (one value per thread); returns the
-// thread's exclusive prefix, *total the block sum.  s_tmp: one int per wave.
+// thread's exclusive prefix, *total the block sum.  s_tmp: one int per wave,
+// alternated by the caller between consecutive scans (one barrier each).
 __device__ __forceinline__ int block_exscan(int v, int* s_tmp, int* total) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   int x = v;
@@ -63,35 +79,180 @@ __device__ __forceinline__ int block_exscan(int v, int* s_tmp, int* total) {
   __syncthreads();
   int woff = 0, tot = 0;
   for (int w = 0; w < nw; ++w) { const int t = s_tmp[w]; woff += (w < wave) ? t : 0; tot += t; }
-  __syncthreads();
   *total = tot;
   return woff + x - v;
 }
 
+// Poisson counts of the four neurons of a quad at step n, packed in bytes.
+__device__ __forceinline__ uint32_t drive_counts(long long n, uint32_t qlocal, uint64_t seed, uint32_t pops,
+                                                 const uint64_t* s_table) {
+  const U64x4 v = philox4x64_10((uint64_t)n, (uint64_t)qlocal, 0, kTagDrive, seed, 0);
+  uint32_t out = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const unsigned pop = (pops >> (8 * k)) & 0xFFu;
+    if (pop == 0xFFu) continue;
+    out |= (uint32_t)poisson_inv(s_table + pop * kTableLen, hi32(pick(v, k))) << (8 * k);
+  }
+  return out;
+}
+
+// Per-workgroup view of the LDS ring and where events of a step go.
+struct Block {
+  long long* acc;        // [DL][B]
+  unsigned* fbits;       // [128][BW]
+  int B, BW, DL;
+  long long j0;          // first owned (padded) target
+};
+
+// Adds one event (target t, weight w, delay d) of a spike at step ns, whose
+// LDS slot is sns = ns mod DL, to the owned block.
+__device__ __forceinline__ void add_event(const DevNet& p, const Block& b, int t, int w, int d, long long ns, int sns) {
+  const int jl = (int)(t - b.j0);
+  if (d < b.DL) {
+    int s = sns + d;
+    if (s >= b.DL) s -= b.DL;
+    atomicAdd(reinterpret_cast<unsigned long long*>(&b.acc[(size_t)s * b.B + jl]), (unsigned long long)(long long)w);
+  } else {
+    const int fs = (int)((ns + d) & kRingMask);
+    atomicAdd(reinterpret_cast<unsigned long long*>(p.ring + (size_t)fs * p.ring_stride + t), (unsigned long long)(long long)w);
+    atomicOr(&b.fbits[fs * b.BW + (jl >> 5)], 1u << (jl & 31));
+  }
+}
+
+// One wavefront walks the entries of spikes k0..k1 of step ns, given each
+// spike's block bounds (lo, len) through `bounds(k, &lo, &len)`, and adds the
+// events with delay >= dmin.  Lanes hold the bounds of 64 spikes, scan their
+// lengths, and walk the concatenated entries kUnroll at a time.
+template <class Bounds>
+__device__ __forceinline__ void wave_entries(const DevNet& p, const Block& b, int k0, int k1, long long ns, int sns,
+                                             int dmin, Bounds bounds) {
+  const int lane = threadIdx.x & 63;
+  for (int base = k0; base < k1; base += 64) {
+    long long lo = 0;
+    int len = 0;
+    if (base + lane < k1) bounds(base + lane, &lo, &len);
+    int x = len;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    const int total = __shfl(x, 63, 64);
+    const int excl = x - len;
+    for (int f0 = 0; f0 < total; f0 += 64 * kUnroll) {
+      int tt[kUnroll], ww[kUnroll], dd[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int f = f0 + u * 64 + lane;
+        dd[u] = 0;
+        int lo_l = 0, hi_l = 64;              // lane j holding entry f: excl_j <= f < excl_{j+1}
+#pragma unroll
+        for (int s = 0; s < 6; ++s) {
+          const int mid = (lo_l + hi_l) >> 1;
+          const int em = __shfl(excl, mid, 64);
+          if (em <= f) lo_l = mid; else hi_l = mid;
+        }
+        const long long lo_j = __shfl(lo, lo_l, 64);
+        const int ex_j = __shfl(excl, lo_l, 64);
+        if (f < total) {
+          const long long e = lo_j + (f - ex_j);
+          tt[u] = p.tgt[e];
+          ww[u] = p.wq[e];
+          dd[u] = p.dly[e];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u)
+        if (dd[u] >= dmin) add_event(p, b, tt[u], ww[u], dd[u], ns, sns);
+    }
+  }
+}
+
+// One wavefront adds the delay-1 and delay-2 events of spikes list[k]
+// (k = k0, k0+stride, ...) from the near table: slots slot1 (step n+1) and
+// slot2 (step n+2).  Lanes walk a table slot's entries.
+__device__ void wave_near(const PersistArgs& a, const Block& b, const int* list, int k0, int k1, int stride, int sb,
+                          int Bg, int slot1, int slot2) {
+  const int lane = threadIdx.x & 63;
+  const int rowlen = a.d1_cap + 1;
+  for (int k = k0; k < k1; k += stride * kUnroll) {
+    unsigned long long v[kUnroll][2];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int kk = k + u * stride;
+      v[u][0] = v[u][1] = 0;
+      if (kk < k1) {
+        const unsigned long long* row = a.d1 + ((size_t)list[kk] * a.nsb + sb) * rowlen;
+        if (lane < rowlen) v[u][0] = row[lane];
+        if (lane + 64 < rowlen) v[u][1] = row[lane + 64];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int kk = k + u * stride;
+      if (kk >= k1) continue;
+      const unsigned long long* row = a.d1 + ((size_t)list[kk] * a.nsb + sb) * rowlen;
+      const int cnt = (int)__shfl((long long)v[u][0], 0, 64);   // wave-uniform
+      for (int e0 = 0; e0 < cnt; e0 += 64) {
+        // entry e sits in word e+1; every lane takes part in the shuffles
+        const int e = e0 + lane;
+        const int wi = e + 1;
+        const long long s0 = __shfl((long long)v[u][0], wi & 63, 64);
+        const long long s1 = __shfl((long long)v[u][1], wi & 63, 64);
+        if (e >= cnt) continue;
+        const unsigned long long wv = wi < 64 ? (unsigned long long)s0 : wi < 128 ? (unsigned long long)s1 : row[wi];
+        const unsigned hi = (unsigned)(wv >> 32);
+        const int jl = (int)((long long)(hi & ~kNearD2) - b.j0);
+        if (jl >= 0 && jl < Bg) {
+          const int slot = (hi & kNearD2) ? slot2 : slot1;
+          atomicAdd(reinterpret_cast<unsigned long long*>(&b.acc[(size_t)slot * b.B + jl]),
+                    (unsigned long long)(long long)(int)(wv & 0xFFFFFFFFu));
+        }
+      }
+    }
+  }
+}
+
 }  // namespace
 
-// LDS layout (dynamic): acc[DL*B] i64 | fbits[128*BW] u32 | s_cnt[G+1] | s_list[kListCap] | s_lo/len[kListCap]...
-__global__ __launch_bounds__(1024) void k_persist(DevNet p, PersistArgs a, int steps) {
+// LDS (dynamic): acc[DL*B] i64 | fbits[128*BW] u32 | s_pre[G+1] | s_inl[G*7] | s_ids[2][kListCap]
+//                | s_len[2][kListCap] | s_lo[2][kListCap] i64
+__global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistArgs a, int steps) {
   extern __shared__ __align__(16) unsigned char s_raw[];
   __shared__ uint64_t s_table[kMaxPops * kTableLen];
-  __shared__ int s_tmp[16];
-  __shared__ int s_local[4 * 256];
+  __shared__ int s_tmp[2][16];
+  __shared__ int s_local[kPersistMaxB];
   __shared__ int s_abort;
   __shared__ unsigned long long s_events;
   __shared__ unsigned long long s_popcnt[kMaxPops];
   long long* acc = reinterpret_cast<long long*>(s_raw);
   unsigned* fbits = reinterpret_cast<unsigned*>(acc + (size_t)a.DL * a.B);
   int* s_pre = reinterpret_cast<int*>(fbits + 128 * a.BW);        // [G+1]
-  int* s_list = s_pre + (a.G + 1);                                  // [kListCap]
-  int* s_len = s_list + kListCap;                                   // [kListCap]
-  long long* s_lo = reinterpret_cast<long long*>(((uintptr_t)(s_len + kListCap) + 15) & ~(uintptr_t)15);  // [kListCap]
+  int* s_inl = s_pre + (a.G + 1);                                   // [G*7] inline ids per producer
+  int* s_ids = s_inl + a.G * kInline;                               // [2][kListCap] spike ids by step parity
+  int* s_len = s_ids + 2 * kListCap;                                // [2][kListCap] block sub-row lengths
+  long long* s_lo = reinterpret_cast<long long*>(((uintptr_t)(s_len + 2 * kListCap) + 15) & ~(uintptr_t)15);
 
   const int g = blockIdx.x, tid = threadIdx.x, nthr = blockDim.x;
+  const int wave = tid >> 6, nw = nthr >> 6;
   const long long j0 = (long long)g * a.B;                          // first owned target (padded id)
   const int Bg = (int)max(0LL, min((long long)a.B, p.n_pad - j0));  // owned targets (multiple of 4)
-  const int qw = Bg / 4;
   const long long n0 = *p.step_base;
   const int DL = a.DL;
+  // Polling: one thread per producer workgroup.  If the workgroup has
+  // wavefronts to spare, the pollers are the last ceil(G/64) whole wavefronts
+  // and the others work on the pipelined delivery meanwhile.
+  const int nwp = (a.G + 63) / 64;
+  const bool overlap = nw > nwp;
+  const int nwd = overlap ? nw - nwp : nw;                           // wavefronts working while polling
+  const int pbase = overlap ? 64 * nwd : 0;
+  const int poller = (tid >= pbase && tid - pbase < a.G) ? tid - pbase : -1;
+  const int sb = g / a.wg_per_sb;
+  const Block blk{acc, fbits, a.B, a.BW, DL, j0};
+  auto bounds_of = [&](int par_) {
+    return [=](int k, long long* lo, int* len) { *lo = s_lo[par_ * kListCap + k]; *len = s_len[par_ * kListCap + k]; };
+  };
 
   for (int k = tid; k < p.n_pops * kTableLen; k += nthr) s_table[k] = p.table[k];
   for (int k = tid; k < DL * a.B; k += nthr) acc[k] = 0;
@@ -111,159 +272,245 @@ __global__ __launch_bounds__(1024) void k_persist(DevNet p, PersistArgs a, int s
       if (ld_dev(e) != 0) atomicOr(&fbits[(step & kRingMask) * a.BW + (jl >> 5)], 1u << (jl & 31));
     }
   }
-  // neuron state into registers: thread t < qw owns quad t of the block
-  double y[4] = {0, 0, 0, 0}, I[4] = {0, 0, 0, 0};
-  int r[4] = {0, 0, 0, 0};
-  uint32_t pops = 0xFFFFFFFFu, qlocal = 0;
+  // neuron state into registers: thread t < Bg owns neuron j0+t; the four
+  // threads of a quad draw the same Philox block and take their own word
+  double y = 0.0, I = 0.0;
+  int r = 0;
+  unsigned pop = 0xFFu;
+  uint32_t qlocal = 0, qpops = 0xFFFFFFFFu;
+  int kdrive = 0;
   uint64_t seed = 0;
-  const long long q = j0 / 4 + tid;
-  if (tid < qw) {
-    pops = p.qpops[q]; qlocal = p.qlocal[q]; seed = p.qseed[q];
-    for (int k = 0; k < 4; ++k) { y[k] = p.y[4 * q + k]; I[k] = p.I[4 * q + k]; r[k] = p.r[4 * q + k]; }
+  const bool upd = tid < Bg;
+  const long long q = (j0 + tid) >> 2;
+  const int qk = tid & 3;
+  __syncthreads();
+  if (upd) {
+    qpops = p.qpops[q]; qlocal = p.qlocal[q]; seed = p.qseed[q];
+    pop = (qpops >> (8 * qk)) & 0xFFu;
+    y = p.y[j0 + tid]; I = p.I[j0 + tid]; r = p.r[j0 + tid];
+    if (steps > 0) kdrive = (int)((drive_counts(n0, qlocal, seed, qpops, s_table) >> (8 * qk)) & 0xFFu);
   }
   long long rcnt = p.raster_cnt[g];
+  long long ph[7] = {0, 0, 0, 0, 0, 0, 0};
+  int S1 = 0;                           // spikes of step n-1: ids kept, block bounds due
+  int S2 = 0;                           // spikes of step n-2: bounds kept, entries due
+  int sn = (int)(n0 % DL);              // LDS slot of the current step
   __syncthreads();
 
   for (int it = 0; it < steps; ++it) {
     const long long n = n0 + it;
-    const int sn = (int)(n % DL);
+    const bool timing = (a.phase != nullptr) && tid == 0;
+    long long tp0 = timing ? wall_clock64() : 0;
+    const int sn1 = (sn + 1 == DL) ? 0 : sn + 1;
+    const int sn2 = (sn1 + 1 == DL) ? 0 : sn1 + 1;
+    const int snm2 = (sn >= 2) ? sn - 2 : sn - 2 + DL;   // slot of step n-2
+    const int par = (int)(n & 1);
     // ---- update -----------------------------------------------------------
-    unsigned mask = 0;
-    if (tid < qw) {
-      const U64x4 v = philox4x64_10((uint64_t)n, (uint64_t)qlocal, 0, kTagDrive, seed, 0);
+    int spiked = 0;
+    if (upd) {
       const int fslot = (int)(n & kRingMask);
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const unsigned pop = (pops >> (8 * k)) & 0xFFu;
-        const int jl = 4 * tid + k;
-        long long x_int = acc[(size_t)sn * a.B + jl];
-        acc[(size_t)sn * a.B + jl] = 0;
-        unsigned* fb = &fbits[fslot * a.BW + (jl >> 5)];
-        if (*fb & (1u << (jl & 31))) {
-          atomicAnd(fb, ~(1u << (jl & 31)));
-          x_int += (long long)__hip_atomic_exchange(
-              reinterpret_cast<unsigned long long*>(p.ring + (size_t)fslot * p.ring_stride + j0 + jl), 0ull,
-              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        if (pop == 0xFFu) continue;
-        x_int += (long long)poisson_inv(s_table + pop * kTableLen, hi32(pick(v, k))) * p.jext_q;
+      const int jl = tid;
+      long long x_int = acc[(size_t)sn * a.B + jl];
+      acc[(size_t)sn * a.B + jl] = 0;
+      unsigned* fb = &fbits[fslot * a.BW + (jl >> 5)];
+      if (*fb & (1u << (jl & 31))) {
+        atomicAnd(fb, ~(1u << (jl & 31)));
+        x_int += (long long)__hip_atomic_exchange(
+            reinterpret_cast<unsigned long long*>(p.ring + (size_t)fslot * p.ring_stride + j0 + jl), 0ull,
+            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      if (pop != 0xFFu) {
+        x_int += (long long)kdrive * p.jext_q;
         const double x = (double)x_int * 0x1p-16;
-        const bool free_ = (r[k] == 0);
+        const bool free_ = (r == 0);
         if (free_) {
-          double yn = p.P22 * y[k] + p.P21 * I[k];
+          double yn = p.P22 * y + p.P21 * I;
           if (p.i_e != 0.0) yn = yn + p.P20 * p.i_e;
-          y[k] = yn;
+          y = yn;
         } else {
-          r[k] = r[k] - 1;
+          r = r - 1;
         }
-        I[k] = p.P11 * I[k] + x;
-        if (free_ && y[k] >= p.theta) {
-          y[k] = p.y_reset;
-          r[k] = p.ref_steps;
-          mask |= 1u << k;
+        I = p.P11 * I + x;
+        if (free_ && y >= p.theta) {
+          y = p.y_reset;
+          r = p.ref_steps;
+          spiked = 1;
           atomicAdd(&s_popcnt[pop], 1ull);
         }
       }
     }
+    if (timing) { const long long t = wall_clock64(); ph[0] += t - tp0; tp0 = t; }
     // ---- compaction (ascending ids) and publication --------------------------
     int nloc;
-    const int c = __popc(mask);
-    const int pre = block_exscan(c, s_tmp, &nloc);
-    if (mask) {
-      int pos = pre;
-      for (int k = 0; k < 4; ++k)
-        if (mask & (1u << k)) s_local[pos++] = (int)(j0 + 4 * tid + k);
-    }
+    const int pre = block_exscan(spiked, s_tmp[0], &nloc);
+    if (spiked) s_local[pre] = (int)(j0 + tid);
     __syncthreads();
-    const int par = (int)(n & 1);
-    int* mypub = a.pub + ((size_t)g * 2 + par) * a.B;
+    const unsigned long long tag = (unsigned long long)(n + 1) << 32;
+    unsigned long long* myrec = a.flags + ((size_t)g * 2 + par) * kPersistFlagStride;   // double-buffered by parity
     for (int k = tid; k < nloc; k += nthr) {
-      __hip_atomic_store(&mypub[k], s_local[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (rcnt + nloc <= p.raster_cap) p.raster[(size_t)g * p.raster_cap + rcnt + k] = make_int2((int)n, s_local[k]);
+      const int id = s_local[k];
+      if (k >= kInline) st_dev(&a.pub[((size_t)g * 2 + par) * a.B + k], id);
+      if (rcnt + nloc <= p.raster_cap) p.raster[(size_t)g * p.raster_cap + rcnt + k] = make_int2((int)n, id);
     }
+    if (nloc > kInline) {                 // side-array ids complete before word 0
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+    }
+    if (tid < min(nloc, kInline)) st_dev(&myrec[1 + tid], tag | (unsigned)s_local[tid]);
+    if (tid == 0) st_dev(&myrec[0], tag | (unsigned)nloc);
     if (rcnt + nloc <= p.raster_cap) rcnt += nloc;
     else if (tid == 0) atomicOr(p.overflow, 1u);
-    __builtin_amdgcn_s_waitcnt(0);  // ids complete before the flag
-    __syncthreads();
-    const unsigned long long tag = (unsigned long long)(n + 1);
-    if (tid == 0)
-      __hip_atomic_store(&a.flags[(size_t)g * kFlagStride], (tag << 32) | (unsigned)nloc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    // ---- wait for every workgroup's step-n flag; per-workgroup counts -------
+    if (timing) { const long long t = wall_clock64(); ph[1] += t - tp0; tp0 = t; }
+    // ---- while the records of step n arrive: drive of step n+1 (updaters);
+    //      block bounds of step n-1 and entries of step n-2 (working
+    //      wavefronts); polling (poller wavefronts) -----------------------------
+    const long long tp_wait = (a.phase != nullptr) ? wall_clock64() : 0;
+    if (upd && it + 1 < steps) kdrive = (int)((drive_counts(n + 1, qlocal, seed, qpops, s_table) >> (8 * qk)) & 0xFFu);
     int cnt_h = 0;
-    if (tid < a.G) {
+    const bool work_now = overlap ? (tid < pbase) : false;
+    if (poller >= 0) {
+      const unsigned long long* rec = a.flags + ((size_t)poller * 2 + par) * kPersistFlagStride;
       long long spins = 0;
-      unsigned long long f;
+      int ids[kInline];
       while (true) {
-        f = ld_dev(&a.flags[(size_t)tid * kFlagStride]);
-        if ((f >> 32) >= tag) break;
+        const unsigned long long w0 = ld_dev(&rec[0]);
+        bool ok = (w0 & 0xFFFFFFFF00000000ull) == tag;
+        cnt_h = (int)(w0 & 0xFFFFFFFFu);
+        if (ok) {
+#pragma unroll
+          for (int k = 0; k < kInline; ++k) {
+            if (k < cnt_h) {
+              const unsigned long long wk = ld_dev(&rec[1 + k]);
+              ok = ok && ((wk & 0xFFFFFFFF00000000ull) == tag);
+              ids[k] = (int)(wk & 0xFFFFFFFFu);
+            }
+          }
+        }
+        if (ok) break;
         __builtin_amdgcn_s_sleep(1);
-        if (++spins > a.spin_limit) { atomicOr(p.overflow, 2u); s_abort = 1; break; }
+        if (++spins > a.spin_limit) { atomicOr(p.overflow, 2u); s_abort = 1; cnt_h = 0; break; }
       }
-      cnt_h = (int)(f & 0xFFFFFFFFu);
+#pragma unroll
+      for (int k = 0; k < kInline; ++k)
+        if (k < cnt_h) s_inl[poller * kInline + k] = ids[k];
+      if (a.phase != nullptr && poller == 0) ph[6] += wall_clock64() - tp_wait;
+    }
+    if (work_now || !overlap) {
+      if (!overlap) __syncthreads();      // no spare wavefronts: after the poll, all wavefronts
+      const int nwork = overlap ? nwd : nw;
+      const int pn1 = par ^ 1, pn2 = par;  // parity of steps n-1 and n-2
+      // block bounds of this wavefront's share of step n-1 (loads in flight ...)
+      const int kb0 = (int)((long long)S1 * wave / nwork), kb1 = (int)((long long)S1 * (wave + 1) / nwork);
+      long long blo[2] = {0, 0}, bhi[2] = {0, 0};
+      const int lane = tid & 63;
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int k = kb0 + u * 64 + lane;
+        if (k < kb1) {
+          const long long* bi = a.blk + (size_t)s_ids[pn1 * kListCap + k] * (a.G + 1) + g;
+          blo[u] = bi[0];
+          bhi[u] = bi[1];
+        }
+      }
+      // ... while the entries of step n-2 (delay >= 3) are added
+      const int ka0 = (int)((long long)S2 * wave / nwork), ka1 = (int)((long long)S2 * (wave + 1) / nwork);
+      wave_entries(p, blk, ka0, ka1, n - 2, snm2, 3, bounds_of(pn2));
+      unsigned long long ev = 0;
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int k = kb0 + u * 64 + lane;
+        if (k < kb1) {
+          s_lo[pn1 * kListCap + k] = blo[u];
+          s_len[pn1 * kListCap + k] = (int)(bhi[u] - blo[u]);
+          ev += (unsigned long long)(bhi[u] - blo[u]);
+        }
+      }
+      for (int k = kb0 + 128 + lane; k < kb1; k += 64) {   // more than 128 spikes for one wavefront
+        const long long* bi = a.blk + (size_t)s_ids[pn1 * kListCap + k] * (a.G + 1) + g;
+        const long long b0 = bi[0], b1 = bi[1];
+        s_lo[pn1 * kListCap + k] = b0;
+        s_len[pn1 * kListCap + k] = (int)(b1 - b0);
+        ev += (unsigned long long)(b1 - b0);
+      }
+      if (ev) atomicAdd(&s_events, ev);
+      if (timing) ph[5] += wall_clock64() - tp_wait;
     }
     int S;
-    const int pre_h = block_exscan(cnt_h, s_tmp, &S);   // also a barrier
+    const int pre_h = block_exscan(cnt_h, s_tmp[1], &S);   // also a barrier
     if (s_abort) break;
-    if (tid < a.G) s_pre[tid] = pre_h;
+    if (poller >= 0) s_pre[poller] = pre_h;
     if (tid == 0) s_pre[a.G] = S;
     __syncthreads();
-    // ---- deliver the step's spikes into my block, kListCap at a time --------
+    if (timing) { const long long t = wall_clock64(); ph[2] += t - tp0; tp0 = t; }
+    // ---- the spikes of step n: ids into LDS, then their near events ---------
+    int* ids_n = s_ids + par * kListCap;
     for (int base = 0; base < S; base += kListCap) {
       const int cnt = min(kListCap, S - base);
       for (int k = tid; k < cnt; k += nthr) {
         const int gk = base + k;
-        int lo = 0, hi = a.G;                 // owner workgroup h: s_pre[h] <= gk < s_pre[h+1]
+        int lo = 0, hi = a.G;                 // producer h: s_pre[h] <= gk < s_pre[h+1]
         while (hi - lo > 1) { const int mid = (lo + hi) >> 1; if (s_pre[mid] <= gk) lo = mid; else hi = mid; }
-        const int i = ld_dev(&a.pub[((size_t)lo * 2 + par) * a.B + (gk - s_pre[lo])]);
-        s_list[k] = i;
-        const long long* bi = a.blk + (size_t)i * (a.G + 1) + g;
-        const long long b0 = bi[0], b1 = bi[1];
-        s_lo[k] = b0;
-        s_len[k] = (int)(b1 - b0);
+        const int kk = gk - s_pre[lo];
+        ids_n[k] = (kk < kInline) ? s_inl[lo * kInline + kk] : ld_dev(&a.pub[((size_t)lo * 2 + par) * a.B + kk]);
       }
       __syncthreads();
-      int E;
-      const int mylen = (tid < cnt) ? s_len[tid] : 0;
-      int ex = block_exscan(mylen, s_tmp, &E);
-      // s_len <- exclusive prefix (entries of spikes beyond blockDim handled below)
-      if (cnt > nthr) {
-        // serial fallback for long lists: thread 0 scans
-        __syncthreads();
-        if (tid == 0) { int acc_ = 0; for (int k = 0; k < cnt; ++k) { const int l = s_len[k]; s_len[k] = acc_; acc_ += l; } s_tmp[0] = acc_; }
-        __syncthreads();
-        E = s_tmp[0];
+      if (timing) { const long long t = wall_clock64(); ph[3] += t - tp0; tp0 = t; }
+      if (S <= kListCap) {
+        wave_near(a, blk, ids_n, wave, cnt, nw, sb, Bg, sn1, sn2);
       } else {
-        if (tid < cnt) s_len[tid] = ex;
-        __syncthreads();
-      }
-      if (tid == 0) s_events += (unsigned long long)E;
-      for (int f = tid; f < E; f += nthr) {
-        int lo = 0, hi = cnt;                 // spike k: s_len[k] <= f < s_len[k+1]
-        while (hi - lo > 1) { const int mid = (lo + hi) >> 1; if (s_len[mid] <= f) lo = mid; else hi = mid; }
-        const long long e = s_lo[lo] + (f - s_len[lo]);
-        const int t = p.tgt[e];
-        const int w = p.wq[e];
-        const int d = p.dly[e];
-        const int jl = (int)(t - j0);
-        if (d < DL) {
-          int s = sn + d;
-          if (s >= DL) s -= DL;
-          atomicAdd(reinterpret_cast<unsigned long long*>(&acc[(size_t)s * a.B + jl]), (unsigned long long)(long long)w);
-        } else {
-          const int fs = (int)((n + d) & kRingMask);
-          atomicAdd(reinterpret_cast<unsigned long long*>(p.ring + (size_t)fs * p.ring_stride + t), (unsigned long long)(long long)w);
-          atomicOr(&fbits[fs * a.BW + (jl >> 5)], 1u << (jl & 31));
-        }
+        // too many spikes to keep: deliver all events of this chunk now
+        const int k0 = (int)((long long)cnt * wave / nw), k1 = (int)((long long)cnt * (wave + 1) / nw);
+        unsigned long long ev = 0;
+        auto direct = [&](int k, long long* lo, int* len) {
+          const long long* bi = a.blk + (size_t)ids_n[k] * (a.G + 1) + g;
+          *lo = bi[0];
+          *len = (int)(bi[1] - *lo);
+          ev += (unsigned long long)*len;
+        };
+        wave_entries(p, blk, k0, k1, n, sn, 1, direct);
+        if (ev) atomicAdd(&s_events, ev);
       }
       __syncthreads();
+      if (timing) { const long long t = wall_clock64(); ph[4] += t - tp0; tp0 = t; }
+    }
+    S2 = S1;
+    S1 = (S <= kListCap) ? S : 0;
+    sn = sn1;
+  }
+  // ---- pipelined events still due: entries of step n_end-2, bounds and
+  //      entries of step n_end-1 --------------------------------------------
+  const long long n_end = n0 + steps;
+  if (!s_abort && steps > 0) {
+    const int pl = (int)((n_end - 1) & 1), pl2 = pl ^ 1;
+    const int sl = (sn == 0) ? DL - 1 : sn - 1;          // slot of step n_end-1
+    const int sl2 = (sl == 0) ? DL - 1 : sl - 1;         // slot of step n_end-2
+    if (S2 > 0) {
+      const int k0 = (int)((long long)S2 * wave / nw), k1 = (int)((long long)S2 * (wave + 1) / nw);
+      wave_entries(p, blk, k0, k1, n_end - 2, sl2, 3, bounds_of(pl2));
+    }
+    if (S1 > 0) {
+      const int k0 = (int)((long long)S1 * wave / nw), k1 = (int)((long long)S1 * (wave + 1) / nw);
+      unsigned long long ev = 0;
+      const int* ids_l = s_ids + pl * kListCap;
+      auto direct = [&](int k, long long* lo, int* len) {
+        const long long* bi = a.blk + (size_t)ids_l[k] * (a.G + 1) + g;
+        *lo = bi[0];
+        *len = (int)(bi[1] - *lo);
+        ev += (unsigned long long)*len;
+      };
+      wave_entries(p, blk, k0, k1, n_end - 1, sl, 3, direct);
+      if (ev) atomicAdd(&s_events, ev);
     }
   }
+  __syncthreads();
   // ---- epilogue: state, counters, LDS window back into the global ring ------
-  const long long n_end = n0 + steps;
-  if (tid < qw) {
-    for (int k = 0; k < 4; ++k) { p.y[4 * q + k] = y[k]; p.I[4 * q + k] = I[k]; p.r[4 * q + k] = r[k]; }
-  }
+  if (upd) { p.y[j0 + tid] = y; p.I[j0 + tid] = I; p.r[j0 + tid] = r; }
   if (tid < p.n_pops) p.wg_spikes[(size_t)g * p.n_pops + tid] += s_popcnt[tid];
+  if (tid == 0 && a.phase) {
+    for (int k = 0; k < 6; ++k) a.phase[(size_t)g * 8 + k] += (unsigned long long)ph[k];
+    a.phase[(size_t)g * 8 + 7] += (unsigned long long)steps;
+  }
+  if (a.phase && poller == 0) a.phase[(size_t)g * 8 + 6] += (unsigned long long)ph[6];
   if (tid == 0) {
     p.raster_cnt[g] = rcnt;
     p.wg_events[g] += s_events;
@@ -294,12 +541,52 @@ __global__ void k_build_blk(const int64_t* row_ptr, const int32_t* tgt, long lon
   blk[idx] = lo;
 }
 
+// Range of row i with targets in [t0, t1) (rows sorted by target).
+__device__ __forceinline__ void row_range(const int64_t* row_ptr, const int32_t* tgt, long long i, long long t0,
+                                          long long t1, long long* b, long long* e) {
+  long long lo = row_ptr[i], hi = row_ptr[i + 1];
+  while (lo < hi) { const long long mid = (lo + hi) >> 1; if (tgt[mid] < t0) lo = mid + 1; else hi = mid; }
+  *b = lo;
+  hi = row_ptr[i + 1];
+  while (lo < hi) { const long long mid = (lo + hi) >> 1; if (tgt[mid] < t1) lo = mid + 1; else hi = mid; }
+  *e = lo;
+}
+
+__global__ void k_d1_count(const int64_t* row_ptr, const int32_t* tgt, const uint8_t* dly, long long n_pad, int nsb,
+                           long long sb_size, int* counts) {
+  const long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (idx >= n_pad * nsb) return;
+  const long long i = idx / nsb;
+  const int s = (int)(idx - i * nsb);
+  long long b, e;
+  row_range(row_ptr, tgt, i, s * sb_size, (s + 1) * sb_size, &b, &e);
+  int c = 0;
+  for (long long k = b; k < e; ++k) c += (dly[k] <= 2);
+  counts[idx] = c;
+}
+
+__global__ void k_d1_fill(const int64_t* row_ptr, const int32_t* tgt, const int32_t* wq, const uint8_t* dly,
+                          long long n_pad, int nsb, long long sb_size, int cap, unsigned long long* d1) {
+  const long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (idx >= n_pad * nsb) return;
+  const long long i = idx / nsb;
+  const int s = (int)(idx - i * nsb);
+  long long b, e;
+  row_range(row_ptr, tgt, i, s * sb_size, (s + 1) * sb_size, &b, &e);
+  unsigned long long* row = d1 + (size_t)idx * (cap + 1);
+  int c = 0;
+  for (long long k = b; k < e && c < cap; ++k)
+    if (dly[k] <= 2)
+      row[1 + c++] = ((unsigned long long)((unsigned)tgt[k] | (dly[k] == 2 ? kNearD2 : 0u)) << 32) | (unsigned)wq[k];
+  row[0] = (unsigned long long)c;
+}
+
 size_t persist_lds_bytes(int G, int B, int DL) {
   const int BW = (B + 31) / 32;
-  size_t b = (size_t)DL * B * 8 + (size_t)128 * BW * 4 + (size_t)(G + 1) * 4 + (size_t)kListCap * 4 * 2;
+  size_t b = (size_t)DL * B * 8 + (size_t)128 * BW * 4 + (size_t)(G + 1) * 4 + (size_t)G * kInline * 4 +
+             (size_t)kListCap * 4 * 4;
   b = (b + 15) & ~(size_t)15;
-  b += (size_t)kListCap * 8 + 16;
-  return b;
+  return b + (size_t)2 * kListCap * 8;
 }
 
 hipError_t persist_static_lds(size_t* bytes) {
@@ -315,7 +602,7 @@ hipError_t persist_occupancy(int block, size_t lds, int* blocks_per_cu) {
 
 hipError_t launch_persist(const DevNet& p, const PersistArgs& a, int steps, int block, hipStream_t s) {
   const size_t lds = persist_lds_bytes(a.G, a.B, a.DL);
-  hipLaunchKernelGGL(k_zero_flags, dim3(1), dim3(256), 0, s, a.flags, a.G * kFlagStride);
+  hipLaunchKernelGGL(k_zero_flags, dim3(1), dim3(256), 0, s, a.flags, a.G * 2 * kPersistFlagStride);
   hipLaunchKernelGGL(k_persist, dim3(a.G), dim3(block), lds, s, p, a, steps);
   return hipGetLastError();
 }
@@ -324,6 +611,22 @@ hipError_t launch_build_blk(const int64_t* row_ptr, const int32_t* tgt, long lon
                             hipStream_t s) {
   const long long total = n_pad * (G + 1);
   hipLaunchKernelGGL(k_build_blk, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, row_ptr, tgt, n_pad, G, B, blk);
+  return hipGetLastError();
+}
+
+hipError_t launch_d1_count(const int64_t* row_ptr, const int32_t* tgt, const uint8_t* dly, long long n_pad, int nsb,
+                           long long sb_size, int* counts, hipStream_t s) {
+  const long long total = n_pad * nsb;
+  hipLaunchKernelGGL(k_d1_count, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, row_ptr, tgt, dly, n_pad, nsb,
+                     sb_size, counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_d1_fill(const int64_t* row_ptr, const int32_t* tgt, const int32_t* wq, const uint8_t* dly,
+                          long long n_pad, int nsb, long long sb_size, int cap, unsigned long long* d1, hipStream_t s) {
+  const long long total = n_pad * nsb;
+  hipLaunchKernelGGL(k_d1_fill, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, row_ptr, tgt, wq, dly, n_pad,
+                     nsb, sb_size, cap, d1);
   return hipGetLastError();
 }
 

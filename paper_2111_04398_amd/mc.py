@@ -74,7 +74,7 @@ EXPORTS = [
     "mc_abi_version", "mc_get_sizes", "mc_get_instance_offsets", "mc_get_pop_offsets", "mc_get_synapses",
     "mc_get_state", "mc_set_state", "mc_get_ring", "mc_inject", "mc_get_propagators", "mc_get_drive_tables",
     "mc_get_counters", "mc_set_launch", "mc_get_launch", "mc_tune", "mc_last_simulate_ms", "mc_reserve",
-    "mc_save_state", "mc_load_state", "mc_set_weights", "mc_stream",
+    "mc_save_state", "mc_load_state", "mc_set_weights", "mc_stream", "mc_profile_phases",
 ]
 
 _lib = None
@@ -121,6 +121,7 @@ def lib() -> C.CDLL:
     L.mc_load_state.argtypes = [vp, vp, C.c_size_t]
     L.mc_set_weights.argtypes = [vp, vp]
     L.mc_stream.argtypes = [vp, C.POINTER(vp)]
+    L.mc_profile_phases.argtypes = [vp, i64, P(np.float64)]
     _lib = L
     return L
 
@@ -284,6 +285,12 @@ class Network:
         _check(lib().mc_tune(self.h, steps, C.byref(l)), "mc_tune")
         return {"scheme": l.scheme, "block": l.block, "neurons_per_wg": l.neurons_per_wg,
                 "steps_per_graph": l.steps_per_graph}
+
+    def profile_phases(self, steps: int) -> dict:
+        us = np.zeros(8, np.float64)
+        _check(lib().mc_profile_phases(self.h, steps, us), "mc_profile_phases")
+        return dict(zip(["update", "publish", "wait", "gather", "deliver_d1", "total", "pending_delivery",
+                         "poll"], us.tolist()))
 
     def last_simulate_ms(self) -> float:
         ms = C.c_double()

@@ -78,10 +78,10 @@ def test_balanced_network_full_protocol():
 
 @pytest.mark.parametrize("scheme,block,npw,spg", [
     (0, 64, 64, 1), (0, 256, 256, 1000), (0, 256, 1024, 7), (0, 1024, 512, 333), (0, 128, 16, 50), (0, 256, 256, 0),
-    (1, 1024, 0, 1000), (1, 256, 0, 100), (1, 512, 64, 7), (1, 1024, 1024, 250), (1, 1024, 200, 0)])
+    (1, 512, 0, 1000), (1, 256, 0, 100), (1, 512, 64, 7), (1, 512, 512, 250), (1, 512, 200, 0)])
 def test_launch_configuration_invariance(scheme, block, npw, spg):
     """Every launch shape of both schemes gives identical bits (integer sums,
-    fixed FP order).  neurons_per_wg = 1024 leaves room for only ~15 delay
+    fixed FP order).  neurons_per_wg = 512 leaves room for only ~30 delay
     steps in LDS, so most events take the far (global) path."""
     w = workloads.balanced()
     net, o = mc.Network(w), oracle.Oracle(w.to_dict())
@@ -106,7 +106,7 @@ def test_scheme_switch_midway():
     w = workloads.balanced()
     net, o = mc.Network(w), oracle.Oracle(w.to_dict())
     for k, sch in enumerate([1, 0, 1, 1, 0]):
-        net.set_launch(scheme=sch, block=1024 if sch else 256, neurons_per_wg=0 if sch else 256,
+        net.set_launch(scheme=sch, block=512 if sch else 256, neurons_per_wg=0 if sch else 256,
                        steps_per_graph=97 + k)
         net.simulate(311)
     o.run(5 * 311)
@@ -180,7 +180,7 @@ def test_full_microcircuit_parity(micro_oracle_runs, scheme):
     w, N, M, a, b = micro_oracle_runs
     net = mc.Network(w)
     if scheme == 1:
-        net.set_launch(scheme=1, block=1024, neurons_per_wg=0, steps_per_graph=1000)
+        net.set_launch(scheme=1, block=512, neurons_per_wg=0, steps_per_graph=1000)
     assert (net.N, net.M) == (N, M)
     for steps, (ras, st, ring, cnt) in ((1000, a), (300, b)):
         net.simulate(steps)
