@@ -63,7 +63,9 @@ def main() -> int:
     ap.add_argument("--workload", default="microcircuit", choices=["microcircuit", "balanced"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=1500)
-    ap.add_argument("--launch", default="", help="scheme,block,neurons_per_wg,steps_per_graph")
+    ap.add_argument("--launch", default="", help="scheme,block,neurons_per_wg,steps_per_graph (default: autotuned)")
+    ap.add_argument("--tune-steps", type=int, default=2000, help="steps per autotuner candidate")
+    ap.add_argument("--replay-steps", type=int, default=1000, help="steps of raster replayed in one launch")
     ap.add_argument("--phases", type=int, default=0, help="after timing, profile this many steps per phase")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -80,11 +82,15 @@ def main() -> int:
     t0 = time.perf_counter()
     net = mc.Network(w)
     build_s = time.perf_counter() - t0
+    net.simulate(args.warmup)                 # presimulation, discarded from timing
     if args.launch:
         s, b, npw, spg = (int(v) for v in args.launch.split(","))
         net.set_launch(scheme=s, block=b, neurons_per_wg=npw, steps_per_graph=spg)
-    net.reserve(args.warmup + args.steps)
-    net.simulate(args.warmup)
+        tuned = False
+    else:
+        net.tune(args.tune_steps)             # restores the state it started from
+        tuned = True
+    net.reserve(args.steps)
     c0 = net.counters()                       # synchronizes
     t0 = time.perf_counter()
     net.simulate(args.steps)
@@ -100,7 +106,7 @@ def main() -> int:
     per_step_s = wall_s / args.steps
     alg_bytes_per_step = algorithmic_bytes(events, spikes, net.N * args.steps) / args.steps
     achieved_gbs = alg_bytes_per_step / per_step_s / 1e9
-    kernel = "k_step" if launch["scheme"] == mc.SCHEME_STEP_KERNELS else "k_persistent"
+    kernel = "k_step" if launch["scheme"] == mc.SCHEME_STEP_KERNELS else "k_persist"
     out = {
         "metric": "realtime factor + synaptic events/s, full microcircuit 77k neurons/3e8 syn",
         "value": events / wall_s,
@@ -115,7 +121,7 @@ def main() -> int:
         "dtype": "f64+i64",
         "data": "synthetic",
         "config": {"workload": w.name, "neurons": net.N, "synapses": net.M, "h_ms": H_MS,
-                   "t_model_s": t_model, "presim_steps": args.warmup, "launch": launch},
+                   "t_model_s": t_model, "presim_steps": args.warmup, "launch": launch, "autotuned": tuned},
         "rtf": wall_s / t_model,
         "rtf_host_clock": (t1 - t0) / t_model,
         "events": events,
@@ -135,6 +141,18 @@ def main() -> int:
         },
         "paper_context": {"rtf_2x64_core_epyc_node": 0.67, "rtf_2_nodes": 0.53},
     }
+    # throughput form of the delivery: recorded spikes of replay-steps steps in one launch
+    rs = min(args.replay_steps, args.steps)
+    if rs > 0:
+        r_ms, r_ev, _ = net.replay_delivery(args.warmup, args.warmup + rs)
+        peak = net.atomic_rate(net.N * (rs + 101))
+        r_rate = r_ev / (r_ms * 1e-3)
+        r_gbs = r_ev * (9 + 16) / (r_ms * 1e-3) / 1e9
+        out["delivery_replay"] = {
+            "kernel": "k_replay", "steps": rs, "events": r_ev, "ms": r_ms,
+            "events_per_s": r_rate, "atomic_peak_per_s": peak * 1e9, "frac_atomic": r_rate / (peak * 1e9),
+            "achieved_gbs": r_gbs, "frac_hbm": r_gbs / HBM_PEAK_GBS,
+        }
     if args.phases and launch["scheme"] == mc.SCHEME_PERSISTENT_LDS:
         out["phases_us_per_step"] = net.profile_phases(args.phases)
     if not args.no_cpu_baseline:

@@ -210,6 +210,19 @@ int mc_tune(mc_net* net, int64_t steps, mc_launch* best_out);
  * [7] polling (first polling thread).  The trajectory is the one
  * mc_simulate would produce. */
 int mc_profile_phases(mc_net* net, int64_t steps, double* us_out_host);
+/* Throughput form of the delivery: every synapse of every recorded spike
+ * with step in [step_begin, step_end) (< current step) is delivered in ONE
+ * launch into a scratch ring of S = step_end - step_begin + 101 slots with
+ * device int64 atomics (slot k = input read at step step_begin + k).
+ * *ms_out: kernel time (HIP events); *events_out: synapses delivered.  If
+ * ring_out_host is not NULL it receives the ring as [S][N] int64 (capacity
+ * in elements; BUFFER_TOO_SMALL if < S*N).  The network state is untouched. */
+int mc_replay_delivery(mc_net* net, int64_t step_begin, int64_t step_end, int64_t* ring_out_host,
+                       int64_t ring_capacity, double* ms_out, int64_t* events_out);
+/* Measured rate (1e9 per second) of uniformly random device-scope int64
+ * atomic adds into a table of `entries` elements: the achievable peak the
+ * delivery's atomics are compared with. */
+int mc_atomic_rate(mc_net* net, int64_t entries, double* gops_out);
 /* Wall time (ms) of the GPU work of the most recent mc_simulate, from HIP events. */
 int mc_last_simulate_ms(mc_net* net, double* ms_out);
 /* Makes room for the spikes of `steps` further steps so that mc_simulate

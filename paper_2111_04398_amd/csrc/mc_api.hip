@@ -871,10 +871,127 @@ int mc_profile_phases(mc_net* n, int64_t steps, double* us) {
   return MC_OK;
 }
 
-int mc_tune(mc_net* n, int64_t steps, mc_launch* best) {
-  (void)steps; (void)best;
+int mc_replay_delivery(mc_net* n, int64_t b, int64_t e, int64_t* ring_out, int64_t ring_cap, double* ms_out,
+                       int64_t* events_out) {
   if (!device_ready(n)) return set_error(MC_ERR_STATE, "handle is host-only, failed or NULL");
-  return set_error(MC_ERR_STATE, "tuner not available");
+  if (b < 0 || e <= b || e > n->step) return set_error(MC_ERR_INVALID_ARG, "step range must lie in [0, current step)");
+  int rc = drain(n);
+  if (rc != MC_OK) return rc;
+  const int64_t slots = (e - b) + 101;
+  const int64_t N = n->h.N;
+  if (ring_out && ring_cap < slots * N) return set_error(MC_ERR_BUFFER_TOO_SMALL, "replay ring buffer too small");
+  auto lo = std::lower_bound(n->r_step.begin(), n->r_step.end(), (int32_t)b);
+  auto hi = std::lower_bound(n->r_step.begin(), n->r_step.end(), (int32_t)e);
+  const size_t o0 = lo - n->r_step.begin(), cnt = hi - lo;
+  std::vector<int2> sp(cnt);
+  std::vector<long long> first(cnt + 1, 0);
+  int64_t events = 0;
+  for (size_t k = 0; k < cnt; ++k) {
+    const int64_t dense = n->r_id[o0 + k];
+    const int64_t len = n->h.row_ptr[dense + 1] - n->h.row_ptr[dense];
+    sp[k] = make_int2(n->r_step[o0 + k], (int)n->pad_of(dense));
+    first[k + 1] = first[k] + (len + kReplayChunkHost - 1) / kReplayChunkHost;
+    events += len;
+  }
+  int2* d_sp = nullptr;
+  long long* d_first = nullptr;
+  long long* d_ring = nullptr;
+  if ((rc = dev_alloc(&d_sp, std::max<size_t>(cnt, 1))) != MC_OK) return rc;
+  if ((rc = dev_alloc(&d_first, cnt + 1)) != MC_OK) { dev_free(d_sp); return rc; }
+  if ((rc = dev_alloc(&d_ring, (size_t)slots * n->ring_stride)) != MC_OK) { dev_free(d_sp); dev_free(d_first); return rc; }
+  hipError_t err = hipSuccess;
+  if (cnt) err = hipMemcpy(d_sp, sp.data(), sizeof(int2) * cnt, hipMemcpyHostToDevice);
+  if (err == hipSuccess) err = hipMemcpy(d_first, first.data(), sizeof(long long) * (cnt + 1), hipMemcpyHostToDevice);
+  if (err == hipSuccess) err = hipMemsetAsync(d_ring, 0, sizeof(long long) * slots * n->ring_stride, n->stream);
+  if (err == hipSuccess) err = hipEventRecord(n->ev0, n->stream);
+  if (err == hipSuccess && cnt)
+    err = launch_replay(d_sp, d_first, (int)cnt, first[cnt], n->d_row_ptr, n->d_tgt, n->d_wq, n->d_dly, d_ring,
+                        n->ring_stride, b, n->n_cu * 8, n->stream);
+  if (err == hipSuccess) err = hipEventRecord(n->ev1, n->stream);
+  if (err == hipSuccess) err = hipEventSynchronize(n->ev1);
+  float ms = 0;
+  if (err == hipSuccess) err = hipEventElapsedTime(&ms, n->ev0, n->ev1);
+  if (err == hipSuccess && ring_out) {
+    std::vector<long long> slot((size_t)n->ring_stride);
+    for (int64_t k = 0; k < slots && err == hipSuccess; ++k) {
+      err = hipMemcpy(slot.data(), d_ring + k * n->ring_stride, sizeof(long long) * n->ring_stride, hipMemcpyDeviceToHost);
+      for (int64_t i = 0; i < N; ++i) ring_out[k * N + i] = slot[n->pad_of(i)];
+    }
+  }
+  dev_free(d_sp); dev_free(d_first); dev_free(d_ring);
+  if (err != hipSuccess) return set_error(MC_ERR_HIP, std::string("replay: ") + hipGetErrorString(err));
+  if (ms_out) *ms_out = ms;
+  if (events_out) *events_out = events;
+  return MC_OK;
+}
+
+int mc_atomic_rate(mc_net* n, int64_t entries, double* gops) {
+  if (!device_ready(n) || !gops) return set_error(MC_ERR_INVALID_ARG, "bad handle or NULL");
+  if (entries < 1 || entries > ((int64_t)1 << 32)) return set_error(MC_ERR_INVALID_ARG, "entries out of [1, 2^32]");
+  unsigned long long* t = nullptr;
+  int rc = dev_alloc(&t, (size_t)entries);
+  if (rc != MC_OK) return rc;
+  const int grid = n->n_cu * 8;
+  const long long per_thread = 256;
+  hipError_t err = hipMemsetAsync(t, 0, sizeof(unsigned long long) * entries, n->stream);
+  if (err == hipSuccess) err = launch_atomic_rate(t, entries, per_thread, grid, n->stream);   // warm-up
+  if (err == hipSuccess) err = hipEventRecord(n->ev0, n->stream);
+  if (err == hipSuccess) err = launch_atomic_rate(t, entries, per_thread, grid, n->stream);
+  if (err == hipSuccess) err = hipEventRecord(n->ev1, n->stream);
+  if (err == hipSuccess) err = hipEventSynchronize(n->ev1);
+  float ms = 0;
+  if (err == hipSuccess) err = hipEventElapsedTime(&ms, n->ev0, n->ev1);
+  dev_free(t);
+  if (err != hipSuccess) return set_error(MC_ERR_HIP, std::string("atomic rate: ") + hipGetErrorString(err));
+  *gops = (double)grid * 256.0 * per_thread / (ms * 1e-3) / 1e9;
+  return MC_OK;
+}
+
+// Autotuner: times candidate launch shapes of both schemes from a saved copy
+// of the current state and keeps the fastest.  Every candidate computes the
+// same bits (integer input sums, fixed floating-point order), so the choice
+// only affects speed; state, counters and the recorded raster are restored.
+int mc_tune(mc_net* n, int64_t steps, mc_launch* best) {
+  if (!device_ready(n)) return set_error(MC_ERR_STATE, "handle is host-only, failed or NULL");
+  if (steps < 1 || steps > 100000) return set_error(MC_ERR_INVALID_ARG, "steps out of [1, 1e5]");
+  if (n->step + 2 * steps + 1000 > 2147483647LL) return set_error(MC_ERR_RANGE, "step counter too large to tune");
+  size_t need = 0;
+  mc_save_state(n, nullptr, 0, &need);
+  std::vector<char> blob;
+  try { blob.resize(need); } catch (...) { return set_error(MC_ERR_OOM, "host allocation of the tuning checkpoint failed"); }
+  int rc = mc_save_state(n, blob.data(), blob.size(), &need);
+  if (rc != MC_OK) return rc;
+  const mc_launch original = n->launch;
+  const int spg = (int)std::min<int64_t>(steps, 1000);
+  const mc_launch cands[] = {
+      {sizeof(mc_launch), MC_SCHEME_PERSISTENT_LDS, 512, 0, (int)std::min<int64_t>(steps, 10000)},
+      {sizeof(mc_launch), MC_SCHEME_PERSISTENT_LDS, 256, 0, (int)std::min<int64_t>(steps, 10000)},
+      {sizeof(mc_launch), MC_SCHEME_PERSISTENT_LDS, 512, 256, (int)std::min<int64_t>(steps, 10000)},
+      {sizeof(mc_launch), MC_SCHEME_STEP_KERNELS, 256, 256, spg},
+      {sizeof(mc_launch), MC_SCHEME_STEP_KERNELS, 256, 1024, spg},
+      {sizeof(mc_launch), MC_SCHEME_STEP_KERNELS, 512, 512, spg},
+      {sizeof(mc_launch), MC_SCHEME_STEP_KERNELS, 128, 128, spg},
+  };
+  double best_ms = 1e300;
+  mc_launch chosen = original;
+  for (const mc_launch& c : cands) {
+    if (apply_launch(n, c) != MC_OK) continue;          // shape does not fit this network
+    const int64_t warm = c.steps_per_graph > 0 ? std::min<int64_t>(steps, c.steps_per_graph) : std::min<int64_t>(steps, 100);
+    if ((rc = mc_reserve(n, warm + steps)) != MC_OK) return rc;
+    if ((rc = mc_load_state(n, blob.data(), blob.size())) != MC_OK) return rc;
+    if ((rc = enqueue_steps(n, warm)) != MC_OK) return rc;   // warm-up (graph capture, caches)
+    HIP_TRY(hipEventRecord(n->ev0, n->stream));
+    if ((rc = enqueue_steps(n, steps)) != MC_OK) return rc;
+    HIP_TRY(hipEventRecord(n->ev1, n->stream));
+    HIP_TRY(hipEventSynchronize(n->ev1));
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, n->ev0, n->ev1));
+    if (ms < best_ms) { best_ms = ms; chosen = c; }
+  }
+  if ((rc = apply_launch(n, chosen)) != MC_OK) return rc;
+  if ((rc = mc_load_state(n, blob.data(), blob.size())) != MC_OK) return rc;
+  if (best) *best = chosen;
+  return MC_OK;
 }
 
 int mc_adjoint(mc_net* n, const mc_adjoint_config* a, void* grad, double* loss) {

@@ -88,6 +88,12 @@ hipError_t launch_persist(const DevNet& p, const PersistArgs& a, int steps, int 
 hipError_t launch_build_blk(const int64_t* row_ptr, const int32_t* tgt, long long n_pad, int G, int B, long long* blk,
                             hipStream_t s);
 
+constexpr int kReplayChunkHost = 256;     // must equal the replay kernel's chunk
+hipError_t launch_replay(const int2* spikes, const long long* first_item, int n_spikes, long long n_items,
+                         const int64_t* row_ptr, const int32_t* tgt, const int32_t* wq, const uint8_t* dly,
+                         long long* ring, long long stride, long long step0, int grid, hipStream_t s);
+hipError_t launch_atomic_rate(unsigned long long* table, long long n, long long per_thread, int grid, hipStream_t s);
+
 constexpr int kMaxQuadsPerWgHost = 256;   // must equal the kernel's per-workgroup quad limit
 hipError_t launch_step(const DevNet& p, int offset, int qpw, int n_wg, int block, hipStream_t s);
 hipError_t launch_advance(long long* step_base, int steps, hipStream_t s);

@@ -74,7 +74,8 @@ EXPORTS = [
     "mc_abi_version", "mc_get_sizes", "mc_get_instance_offsets", "mc_get_pop_offsets", "mc_get_synapses",
     "mc_get_state", "mc_set_state", "mc_get_ring", "mc_inject", "mc_get_propagators", "mc_get_drive_tables",
     "mc_get_counters", "mc_set_launch", "mc_get_launch", "mc_tune", "mc_last_simulate_ms", "mc_reserve",
-    "mc_save_state", "mc_load_state", "mc_set_weights", "mc_stream", "mc_profile_phases",
+    "mc_save_state", "mc_load_state", "mc_set_weights", "mc_stream", "mc_profile_phases", "mc_replay_delivery",
+    "mc_atomic_rate",
 ]
 
 _lib = None
@@ -122,6 +123,8 @@ def lib() -> C.CDLL:
     L.mc_set_weights.argtypes = [vp, vp]
     L.mc_stream.argtypes = [vp, C.POINTER(vp)]
     L.mc_profile_phases.argtypes = [vp, i64, P(np.float64)]
+    L.mc_replay_delivery.argtypes = [vp, i64, i64, vp, i64, C.POINTER(f64), C.POINTER(i64)]
+    L.mc_atomic_rate.argtypes = [vp, i64, C.POINTER(f64)]
     _lib = L
     return L
 
@@ -281,6 +284,7 @@ class Network:
                 "steps_per_graph": l.steps_per_graph}
 
     def tune(self, steps: int) -> dict:
+        """Times the candidate launch shapes and keeps the fastest (state restored)."""
         l = mc_launch()
         _check(lib().mc_tune(self.h, steps, C.byref(l)), "mc_tune")
         return {"scheme": l.scheme, "block": l.block, "neurons_per_wg": l.neurons_per_wg,
@@ -291,6 +295,23 @@ class Network:
         _check(lib().mc_profile_phases(self.h, steps, us), "mc_profile_phases")
         return dict(zip(["update", "publish", "wait", "gather", "deliver_d1", "total", "pending_delivery",
                          "poll"], us.tolist()))
+
+    def replay_delivery(self, begin: int, end: int, want_ring: bool = False):
+        """Delivers the recorded spikes of steps [begin, end) in one launch;
+        returns (ms, events, ring or None)."""
+        ms, ev = C.c_double(), C.c_int64()
+        ring = None
+        ptr, cap = None, 0
+        if want_ring:
+            ring = np.zeros((end - begin + 101, self.N), np.int64)
+            ptr, cap = ring.ctypes.data, ring.size
+        _check(lib().mc_replay_delivery(self.h, begin, end, ptr, cap, C.byref(ms), C.byref(ev)), "mc_replay_delivery")
+        return ms.value, ev.value, ring
+
+    def atomic_rate(self, entries: int) -> float:
+        g = C.c_double()
+        _check(lib().mc_atomic_rate(self.h, entries, C.byref(g)), "mc_atomic_rate")
+        return g.value
 
     def last_simulate_ms(self) -> float:
         ms = C.c_double()

@@ -194,3 +194,28 @@ def test_full_microcircuit_parity(micro_oracle_runs, scheme):
         c = net.counters()
         assert c["events"] == cnt[1] and np.array_equal(c["spikes_per_pop"], cnt[0])
     assert len(b[0][0]) > 50_000
+
+
+def test_delivery_replay_matches_independent_sum():
+    """The one-launch replay of the recorded spikes of steps [100, 400) puts
+    into slot k exactly the sum of w over all synapses (i -> j, d) of spikes
+    (t, i) with t - 100 + d = k -- recomputed here with numpy from the
+    oracle's store and raster."""
+    w = workloads.balanced()
+    net, o = mc.Network(w), oracle.Oracle(w.to_dict())
+    net.set_launch(scheme=1, block=512, neurons_per_wg=0, steps_per_graph=1000)
+    net.simulate(450)
+    o.run(450)
+    ms, ev, ring = net.replay_delivery(100, 400, want_ring=True)
+    rp, tg, wq, d = o.synapses()
+    s, i = o.raster()
+    sel = (s >= 100) & (s < 400)
+    expect = np.zeros_like(ring)
+    events = 0
+    for t, src in zip(s[sel], i[sel]):
+        lo, hi = rp[src], rp[src + 1]
+        np.add.at(expect, (t - 100 + d[lo:hi].astype(np.int64), tg[lo:hi]), wq[lo:hi].astype(np.int64))
+        events += hi - lo
+    assert ev == events > 0
+    assert np.array_equal(ring, expect)
+    assert ms > 0
