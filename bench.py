@@ -62,11 +62,13 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--workload", default="microcircuit", choices=["microcircuit", "balanced"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=1500)
+    ap.add_argument("--cpu-steps", type=int, default=15000)
     ap.add_argument("--launch", default="", help="scheme,block,neurons_per_wg,steps_per_graph (default: autotuned)")
     ap.add_argument("--tune-steps", type=int, default=2000, help="steps per autotuner candidate")
     ap.add_argument("--replay-steps", type=int, default=1000, help="steps of raster replayed in one launch")
     ap.add_argument("--phases", type=int, default=0, help="after timing, profile this many steps per phase")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="at the end, copy a MIB-MiB device buffer 3 times (scale for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -159,7 +161,31 @@ def main() -> int:
         out["cpu_baseline"] = cpu_baseline(w, presim=1000, steps=args.cpu_steps)
     print(json.dumps(out), flush=True)
     net.close()
+    if args.copy_calibration > 0:
+        copy_calibration(args.copy_calibration << 20)
     return 0
+
+
+def copy_calibration(nbytes: int) -> None:
+    """A plain device-to-device copy of known size (the HIP runtime's copy
+    kernel, called through the runtime libmc already loaded): reads nbytes
+    and writes nbytes per copy.  Its HBM byte counters give the scale of the
+    counters taken on the simulation kernels."""
+    import ctypes as C
+    hip = C.CDLL("libamdhip64.so.7")
+    src, dst = C.c_void_p(), C.c_void_p()
+    for p in (src, dst):
+        if hip.hipMalloc(C.byref(p), C.c_size_t(nbytes)) != 0:
+            raise RuntimeError("hipMalloc failed")
+    ok = hip.hipMemset(src, 1, C.c_size_t(nbytes)) == 0 and hip.hipDeviceSynchronize() == 0
+    for _ in range(3):
+        ok = ok and hip.hipMemcpy(dst, src, C.c_size_t(nbytes), 3) == 0   # hipMemcpyDeviceToDevice
+    ok = ok and hip.hipDeviceSynchronize() == 0
+    hip.hipFree(src)
+    hip.hipFree(dst)
+    if not ok:
+        raise RuntimeError("copy calibration failed")
+    print(json.dumps({"copy_calibration_bytes": nbytes, "copies": 3}), flush=True)
 
 
 if __name__ == "__main__":

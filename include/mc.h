@@ -157,15 +157,25 @@ int mc_simulate(mc_net* net, int64_t steps);
 int mc_get_spikes(mc_net* net, int64_t step_begin, int64_t step_end,
                   int32_t* step_out_host, int32_t* id_out_host, int64_t capacity, int64_t* count_out);
 
-/* Gradient of L = 1/(N S) sum_i sum_{n<S} (V_i(n+1) - V*)^2 over a window of S
- * steps starting at the current step, with respect to every synaptic weight
- * in pA, with the spike pattern of the window held fixed (reverse-time
- * adjoint with transposed propagators, gathered over the outgoing synapse
- * rows of every recorded spike).  The network advances by S steps as if
- * mc_simulate(S) had been called.  grad_dev: device array of
- * mc_get_sizes().n_synapses elements (double or float per grad_dtype), in
- * the canonical synapse order of mc_get_synapses; overwritten.  *loss_out: L.
- * Errors: INVALID_ARG, STATE, OOM, HIP, MISMATCH. */
+/* Gradient of L = 1/(N S) sum_i sum_{n0<=n<n0+S} (V_i(n+1) - V*)^2 over the
+ * window of S steps that starts at the current step n0, with respect to every
+ * synaptic weight in pA, with the spike pattern of the window held fixed
+ * (Discussion: explicit per-synapse weights; reverse-time adjoint with the
+ * transposed exact-integration propagators, gathered over the outgoing
+ * synapse rows of every recorded spike).  N counts real neurons of all
+ * instances.  The state at n0, including inputs still pending from spikes
+ * before n0, is the fixed initial condition.  The network advances by S
+ * steps exactly as mc_simulate(S) would (same spikes, same raster).  The
+ * forward state is kept every ckpt_every steps (y, I, r and the ring, about
+ * 8 B x 128 x N per checkpoint) and recomputed per segment from the recorded
+ * spikes; a recompute that does not reproduce the recorded spikes returns
+ * MISMATCH.  grad_dev: caller-owned device array of mc_get_sizes().n_synapses
+ * elements (double for MC_GRAD_F64; float for MC_GRAD_F32, accumulated as
+ * g = f32(g + f32(term)) from FP64 adjoint states), in the canonical synapse
+ * order of mc_get_synapses; overwritten.  *loss_out (host): L.
+ * Synchronizes the stream.  Errors: INVALID_ARG (NULL pointers, S outside
+ * [1, 1e6], ckpt_every outside [1, 4096], unknown grad_dtype), STATE, RANGE,
+ * OOM, HIP, MISMATCH. */
 int mc_adjoint(mc_net* net, const mc_adjoint_config* acfg, void* grad_dev, double* loss_out);
 
 void mc_free(mc_net* net);
@@ -225,6 +235,10 @@ int mc_replay_delivery(mc_net* net, int64_t step_begin, int64_t step_end, int64_
 int mc_atomic_rate(mc_net* net, int64_t entries, double* gops_out);
 /* Wall time (ms) of the GPU work of the most recent mc_simulate, from HIP events. */
 int mc_last_simulate_ms(mc_net* net, double* ms_out);
+/* GPU time (ms, HIP events) of the most recent mc_adjoint: its forward
+ * (S steps with checkpoints) and its reverse pass (recompute, adjoint,
+ * gather). */
+int mc_last_adjoint_ms(mc_net* net, double* forward_ms_out, double* reverse_ms_out);
 /* Makes room for the spikes of `steps` further steps so that mc_simulate
  * allocates nothing for them. */
 int mc_reserve(mc_net* net, int64_t steps);

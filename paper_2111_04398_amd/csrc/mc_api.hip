@@ -56,6 +56,20 @@ void dev_free(T*& p) {
   p = nullptr;
 }
 
+// Device buffers of one adjoint call, freed on every exit path.
+struct AdjBuffers {
+  std::vector<void*> ptrs;
+  template <class T>
+  int alloc(T** p, size_t count) {
+    int rc = dev_alloc(p, count);
+    if (rc == MC_OK) ptrs.push_back((void*)*p);
+    return rc;
+  }
+  ~AdjBuffers() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+};
+
 }  // namespace
 
 struct mc_net {
@@ -113,8 +127,9 @@ struct mc_net {
   // graph
   hipGraphExec_t graph = nullptr;
   int graph_steps = 0;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_mid = nullptr;
   double last_ms = 0.0;
+  double adj_forward_ms = 0.0, adj_reverse_ms = 0.0;
 
   DevNet dev() const {
     DevNet p{};
@@ -127,7 +142,6 @@ struct mc_net {
     p.step_base = d_step;
     p.raster = d_raster; p.raster_cap = raster_cap; p.raster_cnt = d_raster_cnt;
     p.wg_events = d_wg_events; p.wg_spikes = d_wg_spikes; p.overflow = d_overflow;
-    p.rec_y = nullptr; p.rec_type = nullptr; p.rec_step0 = 0;
     return p;
   }
 
@@ -180,6 +194,7 @@ void release_all(mc_net* n) {
   dev_free(n->d_qseed); dev_free(n->d_qlocal); dev_free(n->d_qpops); dev_free(n->d_table); dev_free(n->d_step);
   if (n->ev0) { (void)hipEventDestroy(n->ev0); n->ev0 = nullptr; }
   if (n->ev1) { (void)hipEventDestroy(n->ev1); n->ev1 = nullptr; }
+  if (n->ev_mid) { (void)hipEventDestroy(n->ev_mid); n->ev_mid = nullptr; }
   if (n->own_stream && n->stream) { (void)hipStreamDestroy(n->stream); n->stream = nullptr; }
 }
 
@@ -561,6 +576,7 @@ int mc_build_network(const mc_config* cfg, mc_net** out) {
     rc = upload_network(n.get());
     if (rc == MC_OK && hipEventCreate(&n->ev0) != hipSuccess) rc = set_error(MC_ERR_HIP, "event creation failed");
     if (rc == MC_OK && hipEventCreate(&n->ev1) != hipSuccess) rc = set_error(MC_ERR_HIP, "event creation failed");
+    if (rc == MC_OK && hipEventCreate(&n->ev_mid) != hipSuccess) rc = set_error(MC_ERR_HIP, "event creation failed");
     if (rc == MC_OK) {
       mc_launch l{};
       l.struct_size = sizeof(mc_launch);
@@ -770,6 +786,9 @@ int mc_stream(mc_net* n, void** s) {
 int mc_set_weights(mc_net* n, const double* w_dev) {
   if (!device_ready(n) || !w_dev) return set_error(MC_ERR_INVALID_ARG, "bad handle or NULL");
   HIP_TRY(launch_set_weights(n->d_wq, w_dev, n->h.M, n->stream));
+  if (n->d_d1)   // the persistent scheme's delay-1/2 table holds copies of those weights
+    HIP_TRY(launch_d1_fill(n->d_row_ptr, n->d_tgt, n->d_wq, n->d_dly, n->n_pad, n->nsb, (long long)n->wg_per_sb * n->pB,
+                           n->d1_cap, n->d_d1, n->stream));
   HIP_TRY(hipStreamSynchronize(n->stream));
   HIP_TRY(hipMemcpy(n->h.wq.data(), n->d_wq, sizeof(int32_t) * n->h.M, hipMemcpyDeviceToHost));
   return MC_OK;
@@ -995,9 +1014,189 @@ int mc_tune(mc_net* n, int64_t steps, mc_launch* best) {
 }
 
 int mc_adjoint(mc_net* n, const mc_adjoint_config* a, void* grad, double* loss) {
-  (void)a; (void)grad; (void)loss;
   if (!device_ready(n)) return set_error(MC_ERR_STATE, "handle is host-only, failed or NULL");
-  return set_error(MC_ERR_STATE, "adjoint not available");
+  if (!a || !grad || !loss) return set_error(MC_ERR_INVALID_ARG, "NULL config, gradient or loss pointer");
+  if (a->struct_size != sizeof(mc_adjoint_config)) return set_error(MC_ERR_INVALID_ARG, "mc_adjoint_config.struct_size mismatch");
+  const int64_t S = a->window_steps, K = a->ckpt_every;
+  if (S < 1 || S > 1000000) return set_error(MC_ERR_INVALID_ARG, "window_steps out of [1, 1e6]");
+  if (K < 1 || K > 4096) return set_error(MC_ERR_INVALID_ARG, "ckpt_every out of [1, 4096]");
+  if (a->grad_dtype != MC_GRAD_F64 && a->grad_dtype != MC_GRAD_F32) return set_error(MC_ERR_INVALID_ARG, "unknown grad_dtype");
+  if (n->step + S > 2147483647LL) return set_error(MC_ERR_RANGE, "step count beyond int32 raster steps");
+  const bool fp32 = a->grad_dtype == MC_GRAD_F32;
+  const int64_t n0 = n->step;
+  const int64_t nseg = (S + K - 1) / K;
+  const int64_t st = n->ring_stride;
+  const int64_t M = n->h.M;
+  const int64_t Kc = std::min(K, S);
+  int R = 1;
+  while (R < Kc + 101) R <<= 1;
+  int rc;
+  AdjBuffers B;
+  double *ck_y = nullptr, *ck_I = nullptr;
+  int32_t* ck_r = nullptr;
+  long long* ck_ring = nullptr;
+  const size_t ring_elems = (size_t)kRingSlots * st;
+  if ((rc = B.alloc(&ck_y, (size_t)nseg * st)) != MC_OK) return rc;
+  if ((rc = B.alloc(&ck_I, (size_t)nseg * st)) != MC_OK) return rc;
+  if ((rc = B.alloc(&ck_r, (size_t)nseg * st)) != MC_OK) return rc;
+  if ((rc = B.alloc(&ck_ring, (size_t)nseg * ring_elems)) != MC_OK) return rc;
+
+  // forward: checkpoint, then K steps, per segment
+  HIP_TRY(hipEventRecord(n->ev0, n->stream));
+  for (int64_t k = 0; k < nseg; ++k) {
+    const int64_t len = std::min(K, S - k * K);
+    HIP_TRY(hipMemcpyAsync(ck_y + k * st, n->d_y, sizeof(double) * n->n_pad, hipMemcpyDeviceToDevice, n->stream));
+    HIP_TRY(hipMemcpyAsync(ck_I + k * st, n->d_I, sizeof(double) * n->n_pad, hipMemcpyDeviceToDevice, n->stream));
+    HIP_TRY(hipMemcpyAsync(ck_r + k * st, n->d_r, sizeof(int32_t) * n->n_pad, hipMemcpyDeviceToDevice, n->stream));
+    HIP_TRY(hipMemcpyAsync(ck_ring + k * ring_elems, n->d_ring, sizeof(long long) * ring_elems, hipMemcpyDeviceToDevice,
+                           n->stream));
+    if ((rc = enqueue_steps(n, len)) != MC_OK) { n->failed = true; return rc; }
+  }
+  HIP_TRY(hipEventRecord(n->ev_mid, n->stream));
+  if ((rc = drain(n)) != MC_OK) return rc;
+
+  // recorded spikes of the window (dense ids sorted by step, id)
+  const auto lo = std::lower_bound(n->r_step.begin(), n->r_step.end(), (int32_t)n0) - n->r_step.begin();
+  const auto hi = std::lower_bound(n->r_step.begin(), n->r_step.end(), (int32_t)(n0 + S)) - n->r_step.begin();
+  auto spikes_in = [&](int64_t b, int64_t e, size_t* first, size_t* count) {
+    b = std::max(b, n0); e = std::min(e, n0 + S);
+    if (e <= b) { *first = (size_t)lo; *count = 0; return; }
+    const auto x = std::lower_bound(n->r_step.begin() + lo, n->r_step.begin() + hi, (int32_t)b) - n->r_step.begin();
+    const auto y = std::lower_bound(n->r_step.begin() + lo, n->r_step.begin() + hi, (int32_t)e) - n->r_step.begin();
+    *first = (size_t)x; *count = (size_t)(y - x);
+  };
+  // host work lists: per segment the spikes to deliver (t in [a, a+len-1)), to
+  // verify (t in [a, a+len)) and to gather (t in [a-2, a+len-2), t <= n0+S-3)
+  std::vector<int2> dl_sp, vf_sp;
+  std::vector<long long> dl_first;
+  std::vector<int4> items;
+  std::vector<int> times;
+  std::vector<size_t> dl_off(nseg + 1), vf_off(nseg + 1), it_off(nseg + 1);
+  std::vector<unsigned long long> want_count(nseg);
+  for (int64_t k = 0; k < nseg; ++k) {
+    const int64_t s0 = n0 + k * K, len = std::min(K, S - k * K);
+    size_t f, c;
+    dl_off[k] = dl_sp.size();
+    spikes_in(s0, s0 + len - 1, &f, &c);
+    long long acc = 0;
+    for (size_t q = f; q < f + c; ++q) {
+      const int64_t dense = n->r_id[q];
+      const int64_t rl = n->h.row_ptr[dense + 1] - n->h.row_ptr[dense];
+      dl_sp.push_back(make_int2(n->r_step[q], (int)n->pad_of(dense)));
+      dl_first.push_back(acc);
+      acc += (rl + kReplayChunkHost - 1) / kReplayChunkHost;
+    }
+    dl_first.push_back(acc);   // one terminator per segment
+    vf_off[k] = vf_sp.size();
+    spikes_in(s0, s0 + len, &f, &c);
+    want_count[k] = c;
+    for (size_t q = f; q < f + c; ++q) vf_sp.push_back(make_int2(n->r_step[q], (int)n->pad_of(n->r_id[q])));
+    // gather: group by source, times decreasing
+    it_off[k] = items.size();
+    spikes_in(s0 - 2, std::min(s0 + len - 2, n0 + S - 2), &f, &c);
+    std::vector<std::pair<int64_t, int32_t>> by_src(c);
+    for (size_t q = 0; q < c; ++q) by_src[q] = {n->r_id[f + q], n->r_step[f + q]};
+    std::sort(by_src.begin(), by_src.end(), [](const std::pair<int64_t, int32_t>& x, const std::pair<int64_t, int32_t>& y) {
+      return x.first != y.first ? x.first < y.first : x.second > y.second;
+    });
+    for (size_t q = 0; q < c;) {
+      size_t e = q;
+      while (e < c && by_src[e].first == by_src[q].first) ++e;
+      const int64_t dense = by_src[q].first;
+      const int64_t rl = n->h.row_ptr[dense + 1] - n->h.row_ptr[dense];
+      const int t0 = (int)times.size();
+      for (size_t z = q; z < e; ++z) times.push_back(by_src[z].second);
+      const int64_t chunks = (rl + kGatherChunkHost - 1) / kGatherChunkHost;
+      for (int64_t ch = 0; ch < chunks; ++ch) items.push_back(make_int4((int)n->pad_of(dense), (int)ch, t0, (int)(e - q)));
+      q = e;
+    }
+  }
+  dl_off[nseg] = dl_sp.size(); vf_off[nseg] = vf_sp.size(); it_off[nseg] = items.size();
+
+  // device work lists and reverse-pass buffers
+  int2 *d_dl = nullptr, *d_vf = nullptr;
+  long long* d_first = nullptr;
+  int4* d_items = nullptr;
+  int* d_times = nullptr;
+  long long* xseg = nullptr;
+  double *rec_y = nullptr, *li_ring = nullptr, *carry = nullptr, *loss_part = nullptr;
+  uint8_t* rec_t = nullptr;
+  unsigned long long* seg_count = nullptr;
+  unsigned* mismatch = nullptr;
+  if ((rc = B.alloc(&d_dl, dl_sp.size())) != MC_OK) return rc;
+  if ((rc = B.alloc(&d_vf, vf_sp.size())) != MC_OK) return rc;
+  if ((rc = B.alloc(&d_first, dl_first.size())) != MC_OK) return rc;
+  if ((rc = B.alloc(&d_items, items.size())) != MC_OK) return rc;
+  if ((rc = B.alloc(&d_times, times.size())) != MC_OK) return rc;
+  if ((rc = B.alloc(&xseg, (size_t)(Kc + 101) * st)) != MC_OK) return rc;
+  if ((rc = B.alloc(&rec_y, (size_t)Kc * st)) != MC_OK) return rc;
+  if ((rc = B.alloc(&rec_t, (size_t)Kc * st)) != MC_OK) return rc;
+  if ((rc = B.alloc(&li_ring, (size_t)R * st)) != MC_OK) return rc;
+  if ((rc = B.alloc(&carry, (size_t)3 * st)) != MC_OK) return rc;
+  if ((rc = B.alloc(&seg_count, (size_t)nseg)) != MC_OK) return rc;
+  if ((rc = B.alloc(&mismatch, 1)) != MC_OK) return rc;
+  loss_part = carry + 2 * st;
+  if (!dl_sp.empty()) HIP_TRY(hipMemcpy(d_dl, dl_sp.data(), sizeof(int2) * dl_sp.size(), hipMemcpyHostToDevice));
+  if (!vf_sp.empty()) HIP_TRY(hipMemcpy(d_vf, vf_sp.data(), sizeof(int2) * vf_sp.size(), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(d_first, dl_first.data(), sizeof(long long) * dl_first.size(), hipMemcpyHostToDevice));
+  if (!items.empty()) HIP_TRY(hipMemcpy(d_items, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice));
+  if (!times.empty()) HIP_TRY(hipMemcpy(d_times, times.data(), sizeof(int) * times.size(), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemsetAsync(carry, 0, sizeof(double) * 3 * st, n->stream));
+  HIP_TRY(hipMemsetAsync(seg_count, 0, sizeof(unsigned long long) * nseg, n->stream));
+  HIP_TRY(hipMemsetAsync(mismatch, 0, sizeof(unsigned), n->stream));
+  HIP_TRY(hipMemsetAsync(grad, 0, (fp32 ? sizeof(float) : sizeof(double)) * (size_t)M, n->stream));
+
+  const DevNet p = n->dev();
+  const double c = 2.0 / ((double)n->h.N * (double)S);
+  const double ystar = a->v_target_mV - n->h.e_l;
+  const int grid = n->n_cu * 8;
+  size_t dl_first_off = 0;
+  std::vector<size_t> first_off(nseg);
+  for (int64_t k = 0; k < nseg; ++k) { first_off[k] = dl_first_off; dl_first_off += (dl_off[k + 1] - dl_off[k]) + 1; }
+  for (int64_t k = nseg - 1; k >= 0; --k) {
+    const int64_t s0 = n0 + k * K, len = std::min(K, S - k * K);
+    HIP_TRY(launch_adj_seed(xseg, ck_ring + k * ring_elems, st, s0, (int)(len + 101), n->stream));
+    const size_t nd = dl_off[k + 1] - dl_off[k];
+    if (nd)
+      HIP_TRY(launch_replay(d_dl + dl_off[k], d_first + first_off[k], (int)nd, dl_first[first_off[k] + nd], n->d_row_ptr,
+                            n->d_tgt, n->d_wq, n->d_dly, xseg, st, s0, grid, n->stream));
+    AdjSeg sg{};
+    sg.a = s0; sg.len = (int)len; sg.R = R; sg.c = c; sg.ystar = ystar;
+    sg.ck_y = ck_y + k * st; sg.ck_I = ck_I + k * st; sg.ck_r = ck_r + k * st;
+    sg.xseg = xseg; sg.rec_y = rec_y; sg.rec_t = rec_t; sg.li_ring = li_ring;
+    sg.carry_ly = carry; sg.carry_li = carry + st; sg.loss_part = loss_part; sg.spike_count = seg_count + k;
+    HIP_TRY(launch_adj_segment(p, sg, n->stream));
+    HIP_TRY(launch_adj_verify(d_vf + vf_off[k], (int)(vf_off[k + 1] - vf_off[k]), rec_t, st, s0, mismatch, n->stream));
+    HIP_TRY(launch_adj_gather(d_items + it_off[k], (long long)(it_off[k + 1] - it_off[k]), d_times, n->d_row_ptr,
+                              n->d_tgt, n->d_dly, li_ring, st, R, n0 + S - 1, grad, fp32, grid, n->stream));
+  }
+  HIP_TRY(hipEventRecord(n->ev1, n->stream));
+  HIP_TRY(hipStreamSynchronize(n->stream));
+  float fwd_ms = 0, rev_ms = 0;
+  HIP_TRY(hipEventElapsedTime(&fwd_ms, n->ev0, n->ev_mid));
+  HIP_TRY(hipEventElapsedTime(&rev_ms, n->ev_mid, n->ev1));
+  n->adj_forward_ms = fwd_ms;
+  n->adj_reverse_ms = rev_ms;
+  unsigned mm = 0;
+  std::vector<unsigned long long> got(nseg);
+  HIP_TRY(hipMemcpy(&mm, mismatch, sizeof(unsigned), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(got.data(), seg_count, sizeof(unsigned long long) * nseg, hipMemcpyDeviceToHost));
+  for (int64_t k = 0; k < nseg && mm == 0; ++k)
+    if (got[k] != want_count[k]) mm = 1;
+  if (mm) return set_error(MC_ERR_MISMATCH, "recomputed segment does not reproduce the recorded spikes");
+  std::vector<double> lp((size_t)st);
+  HIP_TRY(hipMemcpy(lp.data(), loss_part, sizeof(double) * st, hipMemcpyDeviceToHost));
+  double sum = 0.0;
+  for (int64_t i = 0; i < n->n_pad; ++i) sum += lp[i];
+  *loss = sum / ((double)n->h.N * (double)S);
+  return MC_OK;
+}
+
+int mc_last_adjoint_ms(mc_net* n, double* forward_ms, double* reverse_ms) {
+  if (!device_ready(n) || !forward_ms || !reverse_ms) return set_error(MC_ERR_INVALID_ARG, "bad handle or NULL output");
+  *forward_ms = n->adj_forward_ms;
+  *reverse_ms = n->adj_reverse_ms;
+  return MC_OK;
 }
 
 }  // extern "C"

@@ -187,6 +187,7 @@ int build_host(const mc_config& c, HostNet& net, std::string& err) {
   net.i_e = c.i_e_pA;
   net.theta = c.v_th_mV - c.e_l_mV;
   net.y_reset = c.v_reset_mV - c.e_l_mV;
+  net.e_l = c.e_l_mV;
   net.ref_steps = (int)ref;
   {
     const double jq = c.w_ext_pA * 65536.0;

@@ -27,7 +27,7 @@ struct HostNet {
   int max_row = 0;
   // dynamics constants
   double P11 = 0, P21 = 0, P22 = 0, P20 = 0;
-  double i_e = 0, theta = 0, y_reset = 0;
+  double i_e = 0, theta = 0, y_reset = 0, e_l = 0;   // theta, y_reset relative to E_L
   int64_t jext_q = 0;
   int ref_steps = 0;
   std::vector<uint64_t> table;           // [n_pops*64]

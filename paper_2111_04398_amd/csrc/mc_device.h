@@ -44,10 +44,6 @@ struct DevNet {
   unsigned long long* wg_events;   // [n_wg]
   unsigned long long* wg_spikes;   // [n_wg * n_pops]
   unsigned* overflow;       // set if a raster segment would overflow
-  // adjoint recording (optional; nullptr when not recording)
-  double* rec_y;            // [K][n_pad] post-step y
-  uint8_t* rec_type;        // [K][n_pad] 0 free, 1 spike, 2 refractory
-  long long rec_step0;      // first recorded step
 };
 
 }  // namespace mc
@@ -93,6 +89,35 @@ hipError_t launch_replay(const int2* spikes, const long long* first_item, int n_
                          const int64_t* row_ptr, const int32_t* tgt, const int32_t* wq, const uint8_t* dly,
                          long long* ring, long long stride, long long step0, int grid, hipStream_t s);
 hipError_t launch_atomic_rate(unsigned long long* table, long long n, long long per_thread, int grid, hipStream_t s);
+
+// One segment of the adjoint's reverse pass (see mc_adjoint.hip).
+struct AdjSeg {
+  long long a;             // first step of the segment
+  int len;                 // steps in the segment
+  int R;                   // LI ring slots (power of two, >= len + 101)
+  double c;                // 2 / (N S)
+  double ystar;            // y* = V* - E_L
+  const double* ck_y;      // checkpoint state at step a
+  const double* ck_I;
+  const int32_t* ck_r;
+  const long long* xseg;   // [len][ring_stride] integer input without the drive
+  double* rec_y;           // [len][ring_stride] post-step y
+  uint8_t* rec_t;          // [len][ring_stride] step type
+  double* li_ring;         // [R][ring_stride] LI(m) at slot m & (R-1)
+  double* carry_ly;        // [ring_stride] Ly at step a+len on entry, at step a on exit
+  double* carry_li;        // [ring_stride] LI likewise
+  double* loss_part;       // [ring_stride] per-neuron sum of squared deviations
+  unsigned long long* spike_count;   // recomputed spikes of this segment (added to)
+};
+constexpr int kGatherChunkHost = 256;     // must equal the gather kernel's chunk
+hipError_t launch_adj_seed(long long* xseg, const long long* ring_ckpt, long long stride, long long a, int rows,
+                           hipStream_t s);
+hipError_t launch_adj_segment(const DevNet& p, const AdjSeg& a, hipStream_t s);
+hipError_t launch_adj_verify(const int2* spikes, int n, const uint8_t* rec_t, long long stride, long long a,
+                             unsigned* mismatch, hipStream_t s);
+hipError_t launch_adj_gather(const int4* items, long long n_items, const int* times, const int64_t* row_ptr,
+                             const int32_t* tgt, const uint8_t* dly, const double* li_ring, long long stride, int R,
+                             long long last_m, void* grad, bool fp32, int grid, hipStream_t s);
 
 constexpr int kMaxQuadsPerWgHost = 256;   // must equal the kernel's per-workgroup quad limit
 hipError_t launch_step(const DevNet& p, int offset, int qpw, int n_wg, int block, hipStream_t s);

@@ -19,7 +19,7 @@
 // n and the update of step n+1 (the smallest delay is one step).
 #pragma clang fp contract(off)
 
-#include "mc_device.h"
+#include "mc_lif.h"
 
 namespace mc {
 
@@ -34,35 +34,6 @@ constexpr int kMaxQuadsPerWg = 256;             // quads updated by one workgrou
 // Loads the Poisson tables of all populations into LDS.
 __device__ __forceinline__ void load_tables(const DevNet& p, uint64_t* s_table) {
   for (int k = threadIdx.x; k < p.n_pops * kTableLen; k += blockDim.x) s_table[k] = p.table[k];
-}
-
-// Inverse CDF: smallest k with u < T[k] (T[63] = 2^32 > u ends the search).
-__device__ __forceinline__ int poisson_from_u32(const uint64_t* T, uint32_t u) {
-  int k = 0;
-  while ((uint64_t)u >= T[k]) ++k;
-  return k;
-}
-
-// One neuron's exact-integration step.  Returns true on a spike.
-__device__ __forceinline__ bool lif_step(const DevNet& p, double& y, double& I, int& r, long long x_int, uint8_t& type) {
-  const double x = (double)x_int * 0x1p-16;
-  const bool free_ = (r == 0);
-  if (free_) {
-    double yn = p.P22 * y + p.P21 * I;
-    if (p.i_e != 0.0) yn = yn + p.P20 * p.i_e;
-    y = yn;
-  } else {
-    r = r - 1;
-  }
-  I = p.P11 * I + x;
-  type = free_ ? 0 : 2;
-  if (free_ && y >= p.theta) {
-    y = p.y_reset;
-    r = p.ref_steps;
-    type = 1;
-    return true;
-  }
-  return false;
 }
 
 // Exclusive prefix of per-lane counts c in [0, 7] across a wavefront from
@@ -114,7 +85,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_step(DevNet p, int offset, int qp
     double y[4] = {ya.x, ya.y, yb.x, yb.y};
     double I[4] = {ia.x, ia.y, ib.x, ib.y};
     int r[4] = {r4.x, r4.y, r4.z, r4.w};
-    uint8_t type[4] = {3, 3, 3, 3};
+    uint8_t type[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const unsigned pop = (pops >> (8 * k)) & 0xFFu;
@@ -128,11 +99,6 @@ __global__ __launch_bounds__(kMaxBlock) void k_step(DevNet p, int offset, int qp
     *reinterpret_cast<double2*>(Iq) = make_double2(I[0], I[1]);
     *reinterpret_cast<double2*>(Iq + 2) = make_double2(I[2], I[3]);
     *reinterpret_cast<int4*>(rq) = make_int4(r[0], r[1], r[2], r[3]);
-    if (p.rec_y) {
-      const size_t base = (size_t)(n - p.rec_step0) * p.n_pad + 4 * q;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) { p.rec_y[base + k] = y[k]; p.rec_type[base + k] = type[k]; }
-    }
   }
 
   // compaction: ascending ids (thread order = quad order, bit order = id order)

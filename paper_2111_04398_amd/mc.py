@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import sys
 from typing import Optional
 
 import numpy as np
@@ -20,7 +21,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmc.so")
 
 MC_OK = 0
+MC_ERR_INVALID_ARG = -1
 MC_ERR_BUFFER_TOO_SMALL = -6
+MC_ERR_MISMATCH = -8
 MC_MAX_POPS = 16
 RING_SLOTS = 128
 RULE_FIXED_INDEGREE, RULE_BERNOULLI = 0, 1
@@ -75,10 +78,11 @@ EXPORTS = [
     "mc_get_state", "mc_set_state", "mc_get_ring", "mc_inject", "mc_get_propagators", "mc_get_drive_tables",
     "mc_get_counters", "mc_set_launch", "mc_get_launch", "mc_tune", "mc_last_simulate_ms", "mc_reserve",
     "mc_save_state", "mc_load_state", "mc_set_weights", "mc_stream", "mc_profile_phases", "mc_replay_delivery",
-    "mc_atomic_rate",
+    "mc_atomic_rate", "mc_last_adjoint_ms",
 ]
 
 _lib = None
+loaded_after_torch = False
 
 
 def lib() -> C.CDLL:
@@ -88,6 +92,12 @@ def lib() -> C.CDLL:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run paper_2111_04398_amd/build.py (or __graft_entry__.build())")
+    # libmc links the HIP runtime by soname.  If torch (which ships its own
+    # runtime under another file name) is already imported, that runtime
+    # serves libmc too; torch imported *after* this point would bring a
+    # second runtime into the process, which the torch binding refuses.
+    global loaded_after_torch
+    loaded_after_torch = "torch" in sys.modules
     L = C.CDLL(LIB_PATH)
     vp, i32, i64, f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     P = np.ctypeslib.ndpointer
@@ -125,6 +135,7 @@ def lib() -> C.CDLL:
     L.mc_profile_phases.argtypes = [vp, i64, P(np.float64)]
     L.mc_replay_delivery.argtypes = [vp, i64, i64, vp, i64, C.POINTER(f64), C.POINTER(i64)]
     L.mc_atomic_rate.argtypes = [vp, i64, C.POINTER(f64)]
+    L.mc_last_adjoint_ms.argtypes = [vp, C.POINTER(f64), C.POINTER(f64)]
     _lib = L
     return L
 
@@ -317,6 +328,12 @@ class Network:
         ms = C.c_double()
         _check(lib().mc_last_simulate_ms(self.h, C.byref(ms)), "mc_last_simulate_ms")
         return ms.value
+
+    def last_adjoint_ms(self) -> tuple[float, float]:
+        """(forward ms, reverse ms) of the most recent adjoint, from HIP events."""
+        f, r = C.c_double(), C.c_double()
+        _check(lib().mc_last_adjoint_ms(self.h, C.byref(f), C.byref(r)), "mc_last_adjoint_ms")
+        return f.value, r.value
 
     def reserve(self, steps: int):
         _check(lib().mc_reserve(self.h, steps), "mc_reserve")

@@ -3,6 +3,11 @@ import sys
 
 import pytest
 
+try:   # one HIP runtime per process: torch's, loaded before libmc (the autograd tests need torch)
+    import torch  # noqa: F401
+except ImportError:
+    pass
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 for p in (ROOT, os.path.join(ROOT, "oracle"), os.path.join(ROOT, "tests")):
     if p not in sys.path:
