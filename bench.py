@@ -8,15 +8,27 @@ the paper's Methods section: the network is instantiated (untimed), `--warmup`
 steps are simulated as the presimulation (default 1000 = 0.1 s, discarded),
 then `--steps` steps are timed (default 100000 = 10 s of model time).
 RTF = T_wall / T_model.  Inputs are synthetic (the paper's connectivity table
-and initial conditions are not published in it): see the design doc.
+and initial conditions are not published in it).
+
+Workloads (`--workload`):
+  microcircuit  (default) the line above, plus the delivery replay, the
+                full-scale adjoint cost per step and the CPU oracle baseline;
+  balanced      the 5,000-neuron balanced random network, same protocol;
+  batched       64 microcircuit instances of scale 0.05-0.25 in one network,
+                2 s of model time each, against 64 sequential plain runs;
+  adjoint_small / adjoint_full
+                adjoint cost per step against the plain forward per step.
 
 Prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
+import ctypes as C
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -25,6 +37,8 @@ sys.path.insert(0, ROOT)
 
 H_MS = 0.1
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_persist_microcircuit_hbm_traffic.md")
+PERSIST_SRC = os.path.join(ROOT, "paper_2111_04398_amd", "csrc", "mc_persist.hip")
 
 
 def algorithmic_bytes(events: int, spikes: int, neuron_steps: int) -> int:
@@ -34,6 +48,38 @@ def algorithmic_bytes(events: int, spikes: int, neuron_steps: int) -> int:
     (4 B) and a raster entry (8 B); per neuron-step y, I, r read and written
     (2 x 20 B) and its ring slot read and cleared (2 x 8 B)."""
     return events * (9 + 16) + spikes * (16 + 4 + 8) + neuron_steps * (40 + 16)
+
+
+def measured_traffic(kernel: str, steps_per_launch: int):
+    """HBM bytes per step of the persistent kernel from the committed
+    counter summary (FETCH_SIZE + WRITE_SIZE scaled by a plain copy), if it
+    was taken on the kernel source as it is now; else None."""
+    if kernel != "k_persist" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    text = open(TRAFFIC_FILE).read()
+    h = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", text)
+    b = re.search(r"hbm_bytes_per_step:\s*([0-9.eE+]+)", text)
+    if not h or not b:
+        return None
+    if hashlib.sha256(open(PERSIST_SRC, "rb").read()).hexdigest() != h.group(1):
+        return None
+    per_step = float(b.group(1))
+    return {"per_step": per_step, "per_launch": per_step * steps_per_launch}
+
+
+class DeviceBuffer:
+    """Device memory from the HIP runtime that libmc uses (no torch here)."""
+
+    def __init__(self, nbytes: int):
+        self.hip = C.CDLL("libamdhip64.so.7")
+        self.ptr = C.c_void_p()
+        if self.hip.hipMalloc(C.byref(self.ptr), C.c_size_t(nbytes)) != 0:
+            raise RuntimeError(f"hipMalloc of {nbytes} bytes failed")
+
+    def free(self):
+        if self.ptr:
+            self.hip.hipFree(self.ptr)
+            self.ptr = C.c_void_p()
 
 
 def cpu_baseline(workload, presim: int, steps: int) -> dict:
@@ -55,60 +101,60 @@ def cpu_baseline(workload, presim: int, steps: int) -> dict:
                       f"({steps * H_MS:g} ms of model time), {ev} synaptic events, {t:.2f} s"}
 
 
-def main() -> int:
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100000)
-    ap.add_argument("--warmup", type=int, default=1000)
-    ap.add_argument("--workload", default="microcircuit", choices=["microcircuit", "balanced"])
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=15000)
-    ap.add_argument("--launch", default="", help="scheme,block,neurons_per_wg,steps_per_graph (default: autotuned)")
-    ap.add_argument("--tune-steps", type=int, default=2000, help="steps per autotuner candidate")
-    ap.add_argument("--replay-steps", type=int, default=1000, help="steps of raster replayed in one launch")
-    ap.add_argument("--phases", type=int, default=0, help="after timing, profile this many steps per phase")
-    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
-                    help="at the end, copy a MIB-MiB device buffer 3 times (scale for HBM byte counters)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU sharding is a design in DESIGN.md, not an executable path", file=sys.stderr)
-        return 2
-
-    from paper_2111_04398_amd import mc, workloads
-    if not os.path.exists(mc.LIB_PATH):
-        from paper_2111_04398_amd import build as _b
-        _b.build()
-    w = workloads.microcircuit() if args.workload == "microcircuit" else workloads.balanced()
-
-    t0 = time.perf_counter()
-    net = mc.Network(w)
-    build_s = time.perf_counter() - t0
-    net.simulate(args.warmup)                 # presimulation, discarded from timing
-    if args.launch:
-        s, b, npw, spg = (int(v) for v in args.launch.split(","))
+def timed_run(net, steps: int, warmup: int, launch: str, tune_steps: int):
+    """Presimulation, launch choice, then `steps` timed steps.  Returns
+    (gpu ms, events, spikes, host s, autotuned)."""
+    net.simulate(warmup)                      # presimulation, discarded from timing
+    if launch:
+        s, b, npw, spg = (int(v) for v in launch.split(","))
         net.set_launch(scheme=s, block=b, neurons_per_wg=npw, steps_per_graph=spg)
         tuned = False
     else:
-        net.tune(args.tune_steps)             # restores the state it started from
+        net.tune(tune_steps)                  # restores the state it started from
         tuned = True
-    net.reserve(args.steps)
+    net.reserve(steps)
     c0 = net.counters()                       # synchronizes
     t0 = time.perf_counter()
-    net.simulate(args.steps)
+    net.simulate(steps)
     gpu_ms = net.last_simulate_ms()           # HIP events on the simulation stream
-    t1 = time.perf_counter()
+    host_s = time.perf_counter() - t0
     c1 = net.counters()
-    events = c1["events"] - c0["events"]
-    spikes = c1["spikes"] - c0["spikes"]
+    return gpu_ms, c1["events"] - c0["events"], c1["spikes"] - c0["spikes"], host_s, tuned
+
+
+def adjoint_cost(net, window: int, ckpt_every: int, v_target: float, fp32: bool, plain_ms_per_step: float) -> dict:
+    """One adjoint window from the network's current state: GPU time of its
+    forward (with checkpoints) and reverse pass per step, against the plain
+    forward per step."""
+    buf = DeviceBuffer(net.M * (4 if fp32 else 8))
+    try:
+        t0 = time.perf_counter()
+        loss = net.adjoint(window, ckpt_every, v_target, fp32, buf.ptr.value)
+        host_s = time.perf_counter() - t0
+        fwd, rev = net.last_adjoint_ms()
+    finally:
+        buf.free()
+    return {"window_steps": window, "ckpt_every": ckpt_every, "grad": "f32" if fp32 else "f64", "loss": loss,
+            "forward_ms_per_step": fwd / window, "reverse_ms_per_step": rev / window,
+            "plain_forward_ms_per_step": plain_ms_per_step,
+            "adjoint_vs_plain": (fwd + rev) / window / plain_ms_per_step,
+            "host_s": host_s}
+
+
+def run_plain(args, mc, w) -> dict:
+    t0 = time.perf_counter()
+    net = mc.Network(w)
+    build_s = time.perf_counter() - t0
+    gpu_ms, events, spikes, host_s, tuned = timed_run(net, args.steps, args.warmup, args.launch, args.tune_steps)
     wall_s = gpu_ms * 1e-3
     t_model = args.steps * H_MS * 1e-3
     launch = net.get_launch()
-
-    per_step_s = wall_s / args.steps
     alg_bytes_per_step = algorithmic_bytes(events, spikes, net.N * args.steps) / args.steps
-    achieved_gbs = alg_bytes_per_step / per_step_s / 1e9
+    achieved_gbs = alg_bytes_per_step / (wall_s / args.steps) / 1e9
     kernel = "k_step" if launch["scheme"] == mc.SCHEME_STEP_KERNELS else "k_persist"
+    steps_per_launch = launch["steps_per_graph"] if kernel == "k_persist" and launch["steps_per_graph"] else (
+        args.steps if kernel == "k_persist" else 1)
+    tr = measured_traffic(kernel, steps_per_launch)
     out = {
         "metric": "realtime factor + synaptic events/s, full microcircuit 77k neurons/3e8 syn",
         "value": events / wall_s,
@@ -125,7 +171,7 @@ def main() -> int:
         "config": {"workload": w.name, "neurons": net.N, "synapses": net.M, "h_ms": H_MS,
                    "t_model_s": t_model, "presim_steps": args.warmup, "launch": launch, "autotuned": tuned},
         "rtf": wall_s / t_model,
-        "rtf_host_clock": (t1 - t0) / t_model,
+        "rtf_host_clock": host_s / t_model,
         "events": events,
         "spikes": spikes,
         "mean_rate_hz": spikes / net.N / t_model,
@@ -137,7 +183,9 @@ def main() -> int:
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved_gbs / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": tr["per_launch"] if tr else None,
+            "traffic_per_step": tr["per_step"] if tr else None,
+            "steps_per_launch": steps_per_launch,
             "alg_bytes_per_step": alg_bytes_per_step,
             "atomics_per_s": events / wall_s,
         },
@@ -157,13 +205,89 @@ def main() -> int:
         }
     if args.phases and launch["scheme"] == mc.SCHEME_PERSISTENT_LDS:
         out["phases_us_per_step"] = net.profile_phases(args.phases)
+    if args.adjoint_window > 0 and w.name.startswith("microcircuit"):
+        out["adjoint"] = adjoint_cost(net, args.adjoint_window, 100, -58.0, True, gpu_ms / args.steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, presim=1000, steps=args.cpu_steps)
-    print(json.dumps(out), flush=True)
     net.close()
-    if args.copy_calibration > 0:
-        copy_calibration(args.copy_calibration << 20)
-    return 0
+    return out
+
+
+def run_batched(args, mc, w) -> dict:
+    """All instances in one network (one launch per graph of steps) against
+    the same instances simulated one after another as plain networks."""
+    steps = w.sim_steps if args.steps == 100000 else args.steps
+    t0 = time.perf_counter()
+    net = mc.Network(w)
+    build_s = time.perf_counter() - t0
+    gpu_ms, events, spikes, host_s, tuned = timed_run(net, steps, args.warmup, args.launch, args.tune_steps)
+    launch = net.get_launch()
+    N, M, n_inst = net.N, net.M, net.n_instances
+    net.close()
+    seq_ms, seq_events, seq_launch = 0.0, 0, {}
+    n_seq = n_inst if args.seq_instances <= 0 else min(args.seq_instances, n_inst)
+    for b in range(n_seq):
+        one = mc.Network(w.instance(b))
+        ms, ev, _, _, _ = timed_run(one, steps, args.warmup, args.seq_launch, args.tune_steps)
+        seq_ms += ms
+        seq_events += ev
+        lc = one.get_launch()
+        key = f"{lc['scheme']},{lc['block']},{lc['neurons_per_wg']},{lc['steps_per_graph']}"
+        seq_launch[key] = seq_launch.get(key, 0) + 1
+        one.close()
+    seq_ms_all = seq_ms * n_inst / n_seq
+    wall_s = gpu_ms * 1e-3
+    return {
+        "metric": "instances/s, 64 batched microcircuit instances (scale 0.05-0.25), 2 s model time each",
+        "value": n_inst / wall_s,
+        "unit": "instances/s",
+        "n_gpus": 1, "steps": steps, "warmup": args.warmup, "ms_per_step": gpu_ms / steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+i64", "data": "synthetic",
+        "config": {"workload": w.name, "instances": n_inst, "neurons": N, "synapses": M, "h_ms": H_MS,
+                   "t_model_s_each": steps * H_MS * 1e-3, "presim_steps": args.warmup, "launch": launch,
+                   "autotuned": tuned},
+        "events": events, "spikes": spikes, "events_per_s": events / wall_s,
+        "build_s": build_s,
+        "sequential": {"instances_timed": n_seq, "gpu_s": seq_ms * 1e-3, "gpu_s_all": seq_ms_all * 1e-3,
+                       "instances_per_s": n_inst / (seq_ms_all * 1e-3), "events": seq_events,
+                       "launches": seq_launch},
+        "speedup_vs_sequential": (seq_ms_all * 1e-3) / wall_s,
+        "atomics_per_s": events / wall_s,
+    }
+
+
+def run_adjoint(args, mc, w) -> dict:
+    """Adjoint over the workload's window from a fresh network against the
+    plain forward of the same window on a twin network (same launch)."""
+    S, K = w.adj_window, w.adj_ckpt_every
+    plain = mc.Network(w)
+    if args.launch:
+        s, b, npw, spg = (int(v) for v in args.launch.split(","))
+        plain.set_launch(scheme=s, block=b, neurons_per_wg=npw, steps_per_graph=spg)
+    else:
+        plain.tune(min(args.tune_steps, S))
+    launch = plain.get_launch()
+    plain.reserve(S)
+    plain.counters()
+    plain.simulate(S)
+    plain_ms = plain.last_simulate_ms()
+    plain.close()
+    net = mc.Network(w)
+    net.set_launch(scheme=launch["scheme"], block=launch["block"], neurons_per_wg=launch["neurons_per_wg"],
+                   steps_per_graph=launch["steps_per_graph"])
+    a = adjoint_cost(net, S, K, w.adj_v_target, w.adj_fp32, plain_ms / S)
+    c = net.counters()
+    net.close()
+    return {
+        "metric": "adjoint ms per step vs plain forward ms per step",
+        "value": a["forward_ms_per_step"] + a["reverse_ms_per_step"],
+        "unit": "ms/step",
+        "n_gpus": 1, "steps": S, "warmup": 0, "ms_per_step": a["forward_ms_per_step"] + a["reverse_ms_per_step"],
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" + ("->f32 grad" if w.adj_fp32 else ""), "data": "synthetic",
+        "config": {"workload": w.name, "window_steps": S, "ckpt_every": K, "launch": launch},
+        "adjoint": a, "spikes": int(sum(c["spikes_per_pop"])), "events": c["events"],
+    }
 
 
 def copy_calibration(nbytes: int) -> None:
@@ -171,21 +295,60 @@ def copy_calibration(nbytes: int) -> None:
     kernel, called through the runtime libmc already loaded): reads nbytes
     and writes nbytes per copy.  Its HBM byte counters give the scale of the
     counters taken on the simulation kernels."""
-    import ctypes as C
-    hip = C.CDLL("libamdhip64.so.7")
-    src, dst = C.c_void_p(), C.c_void_p()
-    for p in (src, dst):
-        if hip.hipMalloc(C.byref(p), C.c_size_t(nbytes)) != 0:
-            raise RuntimeError("hipMalloc failed")
-    ok = hip.hipMemset(src, 1, C.c_size_t(nbytes)) == 0 and hip.hipDeviceSynchronize() == 0
+    src, dst = DeviceBuffer(nbytes), DeviceBuffer(nbytes)
+    hip = src.hip
+    ok = hip.hipMemset(src.ptr, 1, C.c_size_t(nbytes)) == 0 and hip.hipDeviceSynchronize() == 0
     for _ in range(3):
-        ok = ok and hip.hipMemcpy(dst, src, C.c_size_t(nbytes), 3) == 0   # hipMemcpyDeviceToDevice
+        ok = ok and hip.hipMemcpy(dst.ptr, src.ptr, C.c_size_t(nbytes), 3) == 0   # hipMemcpyDeviceToDevice
     ok = ok and hip.hipDeviceSynchronize() == 0
-    hip.hipFree(src)
-    hip.hipFree(dst)
+    src.free()
+    dst.free()
     if not ok:
         raise RuntimeError("copy calibration failed")
     print(json.dumps({"copy_calibration_bytes": nbytes, "copies": 3}), flush=True)
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100000)
+    ap.add_argument("--warmup", type=int, default=1000)
+    ap.add_argument("--workload", default="microcircuit",
+                    choices=["microcircuit", "balanced", "batched", "adjoint_small", "adjoint_full"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=15000)
+    ap.add_argument("--launch", default="", help="scheme,block,neurons_per_wg,steps_per_graph (default: autotuned)")
+    ap.add_argument("--tune-steps", type=int, default=2000, help="steps per autotuner candidate")
+    ap.add_argument("--replay-steps", type=int, default=1000, help="steps of raster replayed in one launch")
+    ap.add_argument("--phases", type=int, default=0, help="after timing, profile this many steps per phase")
+    ap.add_argument("--adjoint-window", type=int, default=2000,
+                    help="microcircuit: steps of the full-scale FP32 adjoint timed after the run (0: skip)")
+    ap.add_argument("--seq-instances", type=int, default=0,
+                    help="batched: instances timed sequentially (0: all; the total is scaled to all)")
+    ap.add_argument("--seq-launch", default="", help="batched: launch of the sequential runs (default: autotuned)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="at the end, copy a MIB-MiB device buffer 3 times (scale for HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU sharding is a design in DESIGN.md, not an executable path", file=sys.stderr)
+        return 2
+
+    from paper_2111_04398_amd import mc, workloads
+    if not os.path.exists(mc.LIB_PATH):
+        from paper_2111_04398_amd import build as _b
+        _b.build()
+    w = workloads.PRESETS[args.workload]()
+    if args.workload in ("microcircuit", "balanced"):
+        out = run_plain(args, mc, w)
+    elif args.workload == "batched":
+        out = run_batched(args, mc, w)
+    else:
+        out = run_adjoint(args, mc, w)
+    print(json.dumps(out), flush=True)
+    if args.copy_calibration > 0:
+        copy_calibration(args.copy_calibration << 20)
+    return 0
 
 
 if __name__ == "__main__":
