@@ -169,7 +169,8 @@ def run_plain(args, mc, w) -> dict:
         "dtype": "f64+i64",
         "data": "synthetic",
         "config": {"workload": w.name, "neurons": net.N, "synapses": net.M, "h_ms": H_MS,
-                   "t_model_s": t_model, "presim_steps": args.warmup, "launch": launch, "autotuned": tuned},
+                   "t_model_s": t_model, "presim_steps": args.warmup, "launch": launch, "autotuned": tuned,
+                   "persist_shape": net.persist_shape()},
         "rtf": wall_s / t_model,
         "rtf_host_clock": host_s / t_model,
         "events": events,

@@ -211,6 +211,10 @@ int mc_get_launch(mc_net* net, mc_launch* l);
 /* Times candidate launch configurations on copies of the current state for
  * `steps` steps each, keeps the fastest (state and raster are restored). */
 int mc_tune(mc_net* net, int64_t steps, mc_launch* best_out);
+/* Shape of the persistent scheme in use: workgroups, target neurons per
+ * workgroup and steps of pending input held in LDS (all 0 under the step
+ * kernels). */
+int mc_get_persist_shape(mc_net* net, int32_t* workgroups_out, int32_t* targets_per_wg_out, int32_t* lds_steps_out);
 /* Simulates `steps` steps with per-phase device timestamps (persistent
  * scheme only) and returns the mean time per step in microseconds, averaged
  * over workgroups: us_out[0] update, [1] compaction+publication, [2] wait

@@ -1013,6 +1013,15 @@ int mc_tune(mc_net* n, int64_t steps, mc_launch* best) {
   return MC_OK;
 }
 
+int mc_get_persist_shape(mc_net* n, int32_t* G, int32_t* B, int32_t* DL) {
+  if (!device_ready(n) || !G || !B || !DL) return set_error(MC_ERR_INVALID_ARG, "bad handle or NULL output");
+  const bool on = n->launch.scheme == MC_SCHEME_PERSISTENT_LDS;
+  *G = on ? n->pG : 0;
+  *B = on ? n->pB : 0;
+  *DL = on ? n->pDL : 0;
+  return MC_OK;
+}
+
 int mc_adjoint(mc_net* n, const mc_adjoint_config* a, void* grad, double* loss) {
   if (!device_ready(n)) return set_error(MC_ERR_STATE, "handle is host-only, failed or NULL");
   if (!a || !grad || !loss) return set_error(MC_ERR_INVALID_ARG, "NULL config, gradient or loss pointer");

@@ -78,7 +78,7 @@ EXPORTS = [
     "mc_get_state", "mc_set_state", "mc_get_ring", "mc_inject", "mc_get_propagators", "mc_get_drive_tables",
     "mc_get_counters", "mc_set_launch", "mc_get_launch", "mc_tune", "mc_last_simulate_ms", "mc_reserve",
     "mc_save_state", "mc_load_state", "mc_set_weights", "mc_stream", "mc_profile_phases", "mc_replay_delivery",
-    "mc_atomic_rate", "mc_last_adjoint_ms",
+    "mc_atomic_rate", "mc_last_adjoint_ms", "mc_get_persist_shape",
 ]
 
 _lib = None
@@ -136,6 +136,7 @@ def lib() -> C.CDLL:
     L.mc_replay_delivery.argtypes = [vp, i64, i64, vp, i64, C.POINTER(f64), C.POINTER(i64)]
     L.mc_atomic_rate.argtypes = [vp, i64, C.POINTER(f64)]
     L.mc_last_adjoint_ms.argtypes = [vp, C.POINTER(f64), C.POINTER(f64)]
+    L.mc_get_persist_shape.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
     _lib = L
     return L
 
@@ -328,6 +329,12 @@ class Network:
         ms = C.c_double()
         _check(lib().mc_last_simulate_ms(self.h, C.byref(ms)), "mc_last_simulate_ms")
         return ms.value
+
+    def persist_shape(self) -> dict:
+        """Persistent-scheme shape in use (zeros under the step kernels)."""
+        g, b, dl = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().mc_get_persist_shape(self.h, C.byref(g), C.byref(b), C.byref(dl)), "mc_get_persist_shape")
+        return {"workgroups": g.value, "targets_per_wg": b.value, "lds_steps": dl.value}
 
     def last_adjoint_ms(self) -> tuple[float, float]:
         """(forward ms, reverse ms) of the most recent adjoint, from HIP events."""

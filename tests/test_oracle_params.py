@@ -80,3 +80,37 @@ def test_external_weight_quantisation():
     """J = 87.8 pA in units of 2^-16 pA, rounded to nearest: 5,754,061."""
     o = oracle.Oracle(workloads.balanced().to_dict(), synapses=False)
     assert o.jext_q() == 5754061
+
+
+def _golden_parameters():
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "paper_parameters.txt")
+    out = {}
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            name, value = line.split()[:2]
+            out[name] = float(value)
+    return out
+
+
+def test_paper_parameters_golden():
+    """The microcircuit workload and the oracle's propagators use what the
+    paper prints (tests/golden/paper_parameters.txt): h, the smallest delay,
+    tau_syn, tau_m, 10 s after a 0.1 s presimulation, about 8e4 neurons in
+    8 populations and about 3e8 synapses (expected count of the pairwise
+    rule, within 5 %)."""
+    g = _golden_parameters()
+    w = workloads.microcircuit()
+    assert w.h == g["h"] and w.tau_syn == g["tau_syn"] and w.tau_m == g["tau_m"]
+    assert w.d_min_steps * w.h == pytest.approx(g["d_min"])
+    assert w.sim_steps * w.h * 1e-3 == pytest.approx(g["t_model"])
+    assert w.presim_steps * w.h * 1e-3 == pytest.approx(g["t_presim"])
+    assert w.n_pops == g["populations"]
+    N = np.asarray(w.pop_size, float)
+    assert abs(N.sum() / g["neurons"] - 1) < 0.05
+    p = np.floor(np.asarray(w.conn, float) * 2.0**32) / 2.0**32      # [post][pre]
+    expected_m = float((p * N[:, None] * N[None, :]).sum())
+    assert abs(expected_m / g["synapses"] - 1) < 0.05
+    o = oracle.Oracle(w.to_dict(), synapses=False)
+    P11, _, P22, _ = o.propagators()
+    assert P22 == math.exp(-g["h"] / g["tau_m"]) and P11 == math.exp(-g["h"] / g["tau_syn"])
