@@ -145,24 +145,27 @@ def run_plain(args, mc, w) -> dict:
     t0 = time.perf_counter()
     net = mc.Network(w)
     build_s = time.perf_counter() - t0
-    gpu_ms, events, spikes, host_s, tuned = timed_run(net, args.steps, args.warmup, args.launch, args.tune_steps)
+    steps = args.steps or w.sim_steps
+    gpu_ms, events, spikes, host_s, tuned = timed_run(net, steps, args.warmup, args.launch, args.tune_steps)
     wall_s = gpu_ms * 1e-3
-    t_model = args.steps * H_MS * 1e-3
+    t_model = steps * H_MS * 1e-3
     launch = net.get_launch()
-    alg_bytes_per_step = algorithmic_bytes(events, spikes, net.N * args.steps) / args.steps
-    achieved_gbs = alg_bytes_per_step / (wall_s / args.steps) / 1e9
+    alg_bytes_per_step = algorithmic_bytes(events, spikes, net.N * steps) / steps
+    achieved_gbs = alg_bytes_per_step / (wall_s / steps) / 1e9
     kernel = "k_step" if launch["scheme"] == mc.SCHEME_STEP_KERNELS else "k_persist"
     steps_per_launch = launch["steps_per_graph"] if kernel == "k_persist" and launch["steps_per_graph"] else (
-        args.steps if kernel == "k_persist" else 1)
-    tr = measured_traffic(kernel, steps_per_launch)
+        steps if kernel == "k_persist" else 1)
+    full = w.name == "microcircuit"
+    tr = measured_traffic(kernel, steps_per_launch) if full else None   # counters were taken on this workload
     out = {
-        "metric": "realtime factor + synaptic events/s, full microcircuit 77k neurons/3e8 syn",
+        "metric": "realtime factor + synaptic events/s, full microcircuit 77k neurons/3e8 syn" if full else
+                  f"realtime factor + synaptic events/s, {w.name} ({net.N} neurons, {net.M} synapses)",
         "value": events / wall_s,
         "unit": "synaptic events/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": steps,
         "warmup": args.warmup,
-        "ms_per_step": gpu_ms / args.steps,
+        "ms_per_step": gpu_ms / steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -193,7 +196,7 @@ def run_plain(args, mc, w) -> dict:
         "paper_context": {"rtf_2x64_core_epyc_node": 0.67, "rtf_2_nodes": 0.53},
     }
     # throughput form of the delivery: recorded spikes of replay-steps steps in one launch
-    rs = min(args.replay_steps, args.steps)
+    rs = min(args.replay_steps, steps)
     if rs > 0:
         r_ms, r_ev, _ = net.replay_delivery(args.warmup, args.warmup + rs)
         peak = net.atomic_rate(net.N * (rs + 101))
@@ -206,8 +209,8 @@ def run_plain(args, mc, w) -> dict:
         }
     if args.phases and launch["scheme"] == mc.SCHEME_PERSISTENT_LDS:
         out["phases_us_per_step"] = net.profile_phases(args.phases)
-    if args.adjoint_window > 0 and w.name.startswith("microcircuit"):
-        out["adjoint"] = adjoint_cost(net, args.adjoint_window, 100, -58.0, True, gpu_ms / args.steps)
+    if args.adjoint_window > 0 and full:
+        out["adjoint"] = adjoint_cost(net, args.adjoint_window, 100, -58.0, True, gpu_ms / steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, presim=1000, steps=args.cpu_steps)
     net.close()
@@ -217,7 +220,7 @@ def run_plain(args, mc, w) -> dict:
 def run_batched(args, mc, w) -> dict:
     """All instances in one network (one launch per graph of steps) against
     the same instances simulated one after another as plain networks."""
-    steps = w.sim_steps if args.steps == 100000 else args.steps
+    steps = args.steps or w.sim_steps
     t0 = time.perf_counter()
     net = mc.Network(w)
     build_s = time.perf_counter() - t0
@@ -312,7 +315,8 @@ def copy_calibration(nbytes: int) -> None:
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100000)
+    ap.add_argument("--steps", type=int, default=0,
+                    help="timed steps (default: the workload's span, 100000 = 10 s for the microcircuit)")
     ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--workload", default="microcircuit",
                     choices=["microcircuit", "balanced", "batched", "adjoint_small", "adjoint_full"])

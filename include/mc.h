@@ -108,13 +108,18 @@ typedef struct mc_config {
 } mc_config;
 
 /* Launch configuration of the simulation loop (see mc_set_launch). */
-enum { MC_SCHEME_STEP_KERNELS = 0,   /* one update and one delivery kernel per step, replayed from a HIP graph */
-       MC_SCHEME_PERSISTENT_LDS = 1 };/* one persistent kernel per chunk; near-future input held in LDS */
+enum { MC_SCHEME_STEP_KERNELS = 0,   /* one kernel per step (update, then source-owner delivery with device
+                                        atomics), replayed from a HIP graph */
+       MC_SCHEME_PERSISTENT_LDS = 1,  /* one persistent kernel per chunk; near-future input held in LDS */
+       MC_SCHEME_TARGET_OWNER = 2 };  /* two kernels per step: update, then target-owner delivery combined
+                                        in LDS (no device atomics); replayed from a HIP graph */
 typedef struct mc_launch {
   uint32_t struct_size;
   int32_t scheme;
   int32_t block;                 /* threads per workgroup: 64..1024, multiple of 64 */
-  int32_t neurons_per_wg;        /* neurons updated by one workgroup: multiple of 4, <= 4*block (0: automatic) */
+  int32_t neurons_per_wg;        /* neurons updated by one workgroup: multiple of 4, <= 4*block, <= 1024
+                                    (persistent: <= block; target owner: the targets of one delivery block,
+                                    its update kernel takes one quad per thread); 0: automatic */
   int32_t steps_per_graph;       /* steps captured per graph replay / per persistent launch (>= 1) */
 } mc_launch;
 
@@ -224,6 +229,11 @@ int mc_get_persist_shape(mc_net* net, int32_t* workgroups_out, int32_t* targets_
  * [7] polling (first polling thread).  The trajectory is the one
  * mc_simulate would produce. */
 int mc_profile_phases(mc_net* net, int64_t steps, double* us_out_host);
+/* The per-workgroup times behind the last mc_profile_phases, [G][8] us per
+ * step (columns 0..4 as us_out[0..4], 5: drive + pending delivery of
+ * wavefront 0, 6: polling of the first poller, 7: unused); *workgroups_out =
+ * G (0 before any profile).  BUFFER_TOO_SMALL if capacity < 8*G. */
+int mc_get_phase_table(mc_net* net, double* out_host, int64_t capacity, int32_t* workgroups_out);
 /* Throughput form of the delivery: every synapse of every recorded spike
  * with step in [step_begin, step_end) (< current step) is delivered in ONE
  * launch into a scratch ring of S = step_end - step_begin + 101 slots with

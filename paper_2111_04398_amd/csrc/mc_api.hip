@@ -103,8 +103,23 @@ struct mc_net {
   long long* d_blk = nullptr;
   unsigned long long* d_flags = nullptr;
   int* d_pub = nullptr;
+  int* d_bstart = nullptr;
+  std::vector<int> bstart_host;        // [pG+1] target blocks of the persistent workgroups
+  // target-owner scheme
+  int32_t* d_qinst = nullptr;          // [n_quads]
+  int64_t* d_inst_base = nullptr;      // [n_inst+1]
+  int* d_ilist = nullptr;              // [2][n_pad]
+  int* d_icnt = nullptr;               // [2][n_inst]
+  int* d_bt0 = nullptr;                // [n_blocks+1]
+  int* d_binst = nullptr;              // [n_blocks]
+  int* d_blb = nullptr;                // [n_blocks]
+  int* d_ifb = nullptr;                // [n_inst] first block of each instance
+  int64_t* d_boff = nullptr;           // [n_pad+1]
+  int32_t* d_blk2 = nullptr;
+  int own_blocks = 0, own_bmax = 0, own_targets = 0;
   unsigned long long* d_phase = nullptr;
   bool phase_on = false;
+  std::vector<double> phase_wg;        // per-workgroup phase times (us/step) of the last mc_profile_phases
   unsigned long long* d_d1 = nullptr;
   int d1_cap = 0, nsb = 1, wg_per_sb = 1;
   // recording
@@ -142,12 +157,21 @@ struct mc_net {
     p.step_base = d_step;
     p.raster = d_raster; p.raster_cap = raster_cap; p.raster_cnt = d_raster_cnt;
     p.wg_events = d_wg_events; p.wg_spikes = d_wg_spikes; p.overflow = d_overflow;
+    p.n_inst = h.n_inst; p.qinst = d_qinst; p.inst_base = d_inst_base; p.ilist = d_ilist; p.icnt = d_icnt;
     return p;
+  }
+
+  OwnerArgs owner() const {
+    OwnerArgs a{};
+    a.n_blocks = own_blocks; a.bmax = own_bmax;
+    a.bt0 = d_bt0; a.binst = d_binst; a.blb = d_blb; a.boff = d_boff; a.blk2 = d_blk2;
+    return a;
   }
 
   PersistArgs persist() const {
     PersistArgs a{};
     a.G = pG; a.B = pB; a.DL = pDL; a.BW = (pB + 31) / 32;
+    a.bstart = d_bstart;
     a.blk = d_blk; a.flags = d_flags; a.pub = d_pub;
     a.spin_limit = 1LL << 24;
     a.phase = phase_on ? d_phase : nullptr;
@@ -188,6 +212,10 @@ void release_all(mc_net* n) {
   if (n->graph) { (void)hipGraphExecDestroy(n->graph); n->graph = nullptr; }
   release_recording(n);
   dev_free(n->d_blk); dev_free(n->d_flags); dev_free(n->d_pub); dev_free(n->d_phase); dev_free(n->d_d1);
+  dev_free(n->d_bstart);
+  dev_free(n->d_qinst); dev_free(n->d_inst_base); dev_free(n->d_ilist); dev_free(n->d_icnt);
+  dev_free(n->d_bt0); dev_free(n->d_binst); dev_free(n->d_blb); dev_free(n->d_ifb); dev_free(n->d_boff);
+  dev_free(n->d_blk2);
   dev_free(n->d_overflow);
   dev_free(n->d_row_ptr); dev_free(n->d_tgt); dev_free(n->d_wq); dev_free(n->d_dly);
   dev_free(n->d_y); dev_free(n->d_I); dev_free(n->d_r); dev_free(n->d_ring);
@@ -274,14 +302,14 @@ int setup_recording(mc_net* n, int64_t steps) {
 
 int validate_launch(const mc_net* n, const mc_launch& l) {
   if (l.struct_size != sizeof(mc_launch)) return set_error(MC_ERR_INVALID_ARG, "mc_launch.struct_size mismatch");
-  if (l.scheme != MC_SCHEME_STEP_KERNELS && l.scheme != MC_SCHEME_PERSISTENT_LDS)
+  if (l.scheme != MC_SCHEME_STEP_KERNELS && l.scheme != MC_SCHEME_PERSISTENT_LDS && l.scheme != MC_SCHEME_TARGET_OWNER)
     return set_error(MC_ERR_INVALID_ARG, "unknown scheme");
   if (l.block < 64 || l.block > 1024 || l.block % 64) return set_error(MC_ERR_INVALID_ARG, "block must be a multiple of 64 in [64, 1024]");
   if (l.scheme == MC_SCHEME_PERSISTENT_LDS && l.block > kPersistMaxBlock)
     return set_error(MC_ERR_INVALID_ARG, "the persistent scheme runs at most 512 threads per workgroup");
   const int npw = l.neurons_per_wg;
-  const int npw_max = l.scheme == MC_SCHEME_STEP_KERNELS ? std::min(4 * l.block, 4 * kMaxQuadsPerWgHost)
-                                                         : std::min(l.block, kPersistMaxB);
+  const int npw_max = l.scheme == MC_SCHEME_PERSISTENT_LDS ? std::min(l.block, kPersistMaxB)
+                                                           : std::min(4 * l.block, 4 * kMaxQuadsPerWgHost);
   if (npw < 0 || npw % 4 || npw > npw_max)
     return set_error(MC_ERR_INVALID_ARG, "neurons_per_wg must be a multiple of 4, <= min(4*block, 1024) (step "
                                          "kernels) or <= block (persistent)");
@@ -290,17 +318,24 @@ int validate_launch(const mc_net* n, const mc_launch& l) {
   return MC_OK;
 }
 
-// Shape of the persistent scheme: G co-resident workgroups owning B targets
-// each, DL near steps of input in LDS (as many as the LDS holds, <= 101).
-int persist_shape(mc_net* n, const mc_launch& l, int* G, int* B, int* DL) {
+// Shape of the persistent scheme: G co-resident workgroups, workgroup g owning
+// targets [bs[g], bs[g+1]) (B of them, the last block possibly fewer), DL
+// near steps of input in LDS (as many as the LDS holds, <= 101).
+// neurons_per_wg = 0: one workgroup per compute unit.  (Blocks sized to
+// equalise the expected synaptic input per workgroup were measured slower on
+// the full microcircuit: the larger blocks leave fewer delay steps in LDS.)
+int persist_shape(mc_net* n, const mc_launch& l, int* G, int* B, int* DL, std::vector<int>& bs) {
+  const int64_t P = n->n_pad;
+  const int cap = std::min(kPersistMaxB, l.block);
   int b = l.neurons_per_wg;
   if (b == 0) {
-    const int g = std::max(1, std::min(n->n_cu, l.block));
-    b = (int)align_up((n->n_pad + g - 1) / g, 4);
+    const int g0 = (int)std::max<int64_t>(1, std::min<int64_t>(std::min(n->n_cu, l.block), P / 4));
+    b = (int)align_up((P + g0 - 1) / g0, 4);
   }
-  if (b > kPersistMaxB || b > l.block)
-    return set_error(MC_ERR_RANGE, "network too large for the persistent LDS scheme at this block size");
-  const int g = (int)((n->n_pad + b - 1) / b);
+  if (b > cap) return set_error(MC_ERR_RANGE, "network too large for the persistent LDS scheme at this block size");
+  const int g = (int)((P + b - 1) / b);
+  bs.assign((size_t)g + 1, 0);
+  for (int k = 0; k <= g; ++k) bs[k] = (int)std::min<int64_t>((int64_t)k * b, P);
   if (g > l.block) return set_error(MC_ERR_RANGE, "persistent scheme needs workgroups <= threads per workgroup");
   size_t stat = 0;
   HIP_TRY(persist_static_lds(&stat));
@@ -317,21 +352,76 @@ int persist_shape(mc_net* n, const mc_launch& l, int* G, int* B, int* DL) {
   return MC_OK;
 }
 
+// Target blocks of the owner kernel: every instance's padded range split
+// into blocks of at most `targets` targets (no block spans two instances),
+// and each row's sub-row bounds for the blocks of its own instance.
+int setup_owner(mc_net* n, int targets) {
+  const int ni = n->h.n_inst;
+  std::vector<int> bt0, binst, blb, ifb((size_t)ni);
+  for (int b = 0; b < ni; ++b) {
+    const int64_t p0 = n->inst_off_pad[b], L = n->inst_off_pad[b + 1] - p0;
+    const int64_t G = std::max<int64_t>(1, (L + targets - 1) / targets);
+    ifb[b] = (int)bt0.size();
+    for (int64_t j = 0; j < G; ++j) {
+      bt0.push_back((int)(p0 + L * j / G));
+      binst.push_back(b);
+      blb.push_back((int)j);
+    }
+  }
+  const int nb = (int)bt0.size();
+  bt0.push_back((int)n->n_pad);
+  int bmax = 1;
+  for (int k = 0; k < nb; ++k) bmax = std::max(bmax, bt0[k + 1] - bt0[k]);
+  if (bmax > kOwnerMaxTargets) return set_error(MC_ERR_INVALID_ARG, "owner blocks hold at most 1024 targets");
+  std::vector<int64_t> boff((size_t)n->n_pad + 1, 0);
+  for (int b = 0; b < ni; ++b) {
+    const int nblk = ((b + 1 < ni) ? ifb[b + 1] : nb) - ifb[b];
+    for (int64_t i = n->inst_off_pad[b]; i < n->inst_off_pad[b + 1]; ++i) boff[i + 1] = boff[i] + nblk + 1;
+  }
+  int rc;
+  dev_free(n->d_bt0); dev_free(n->d_binst); dev_free(n->d_blb); dev_free(n->d_ifb); dev_free(n->d_boff);
+  dev_free(n->d_blk2);
+  if ((rc = dev_alloc(&n->d_bt0, (size_t)nb + 1)) != MC_OK) return rc;
+  if ((rc = dev_alloc(&n->d_binst, (size_t)nb)) != MC_OK) return rc;
+  if ((rc = dev_alloc(&n->d_blb, (size_t)nb)) != MC_OK) return rc;
+  if ((rc = dev_alloc(&n->d_ifb, (size_t)ni)) != MC_OK) return rc;
+  if ((rc = dev_alloc(&n->d_boff, (size_t)n->n_pad + 1)) != MC_OK) return rc;
+  if ((rc = dev_alloc(&n->d_blk2, (size_t)boff[n->n_pad])) != MC_OK) return rc;
+  HIP_TRY(hipMemcpy(n->d_bt0, bt0.data(), sizeof(int) * (nb + 1), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(n->d_binst, binst.data(), sizeof(int) * nb, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(n->d_blb, blb.data(), sizeof(int) * nb, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(n->d_ifb, ifb.data(), sizeof(int) * ni, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(n->d_boff, boff.data(), sizeof(int64_t) * (n->n_pad + 1), hipMemcpyHostToDevice));
+  HIP_TRY(launch_build_blk2(n->d_row_ptr, n->d_tgt, n->n_pad, n->d_boff, n->d_qinst, n->d_ifb, n->d_bt0, n->d_blk2,
+                            n->stream));
+  HIP_TRY(hipStreamSynchronize(n->stream));
+  n->own_blocks = nb;
+  n->own_bmax = bmax;
+  n->own_targets = targets;
+  return MC_OK;
+}
+
 int apply_launch(mc_net* n, const mc_launch& l) {
   int rc = validate_launch(n, l);
   if (rc != MC_OK) return rc;
   int qpw = 0, n_wg = 0, wg_neurons = 0, G = 0, B = 0, DL = 0;
-  if (l.scheme == MC_SCHEME_STEP_KERNELS) {
-    qpw = l.neurons_per_wg / 4;
+  std::vector<int> bs;
+  if (l.scheme != MC_SCHEME_PERSISTENT_LDS) {
+    // step kernels: neurons_per_wg / 4 quads per workgroup; target owner: one
+    // quad per thread in the update kernel, neurons_per_wg sizes the delivery blocks
+    qpw = l.scheme == MC_SCHEME_TARGET_OWNER ? std::min(l.block, kMaxQuadsPerWgHost) : l.neurons_per_wg / 4;
     if (qpw == 0) qpw = std::min<int>(l.block, 64);
     n_wg = (int)((n->n_quads + qpw - 1) / qpw);
     wg_neurons = 4 * qpw;
   } else {
-    if ((rc = persist_shape(n, l, &G, &B, &DL)) != MC_OK) return rc;
+    if ((rc = persist_shape(n, l, &G, &B, &DL, bs)) != MC_OK) return rc;
     n_wg = G;
     wg_neurons = B;
   }
-  const bool shape_changed = (l.scheme != n->launch.scheme || n_wg != n->n_wg || wg_neurons != n->wg_neurons);
+  const bool shape_changed = (l.scheme != n->launch.scheme || n_wg != n->n_wg || wg_neurons != n->wg_neurons ||
+                              (l.scheme == MC_SCHEME_PERSISTENT_LDS && bs != n->bstart_host) ||
+                              (l.scheme == MC_SCHEME_TARGET_OWNER &&
+                               n->own_targets != (l.neurons_per_wg ? l.neurons_per_wg : 256)));
   if (n->graph && (shape_changed || l.steps_per_graph != n->graph_steps || l.block != n->launch.block)) {
     (void)hipGraphExecDestroy(n->graph);
     n->graph = nullptr;
@@ -341,32 +431,37 @@ int apply_launch(mc_net* n, const mc_launch& l) {
     if ((rc = fold_counters(n)) != MC_OK) return rc;
     release_recording(n);   // sized for the old shape
     if (l.scheme == MC_SCHEME_PERSISTENT_LDS) {
-      dev_free(n->d_blk); dev_free(n->d_flags); dev_free(n->d_pub);
+      dev_free(n->d_blk); dev_free(n->d_flags); dev_free(n->d_pub); dev_free(n->d_bstart);
       if ((rc = dev_alloc(&n->d_blk, (size_t)n->n_pad * (G + 1))) != MC_OK) return rc;
-      if ((rc = dev_alloc(&n->d_flags, (size_t)G * 2 * kPersistFlagStride)) != MC_OK) return rc;
+      if ((rc = dev_alloc(&n->d_flags, persist_flag_words(G))) != MC_OK) return rc;
       if ((rc = dev_alloc(&n->d_pub, (size_t)G * 2 * B)) != MC_OK) return rc;
-      HIP_TRY(launch_build_blk(n->d_row_ptr, n->d_tgt, n->n_pad, G, B, n->d_blk, n->stream));
-      HIP_TRY(hipMemsetAsync(n->d_flags, 0, sizeof(unsigned long long) * G * 2 * kPersistFlagStride, n->stream));
+      if ((rc = dev_alloc(&n->d_bstart, (size_t)G + 1)) != MC_OK) return rc;
+      HIP_TRY(hipMemcpy(n->d_bstart, bs.data(), sizeof(int) * (G + 1), hipMemcpyHostToDevice));
+      n->bstart_host = bs;
+      HIP_TRY(launch_build_blk(n->d_row_ptr, n->d_tgt, n->n_pad, G, n->d_bstart, n->d_blk, n->stream));
+      HIP_TRY(hipMemsetAsync(n->d_flags, 0, sizeof(unsigned long long) * persist_flag_words(G), n->stream));
       // delay-1 table: per (source, superblock of wg_per_sb target blocks)
       dev_free(n->d_d1);
       n->nsb = std::min(8, G);
       n->wg_per_sb = (G + n->nsb - 1) / n->nsb;
-      const long long sb_size = (long long)n->wg_per_sb * B;
       const size_t slots = (size_t)n->n_pad * n->nsb;
       int* d_cnt = nullptr;
       if ((rc = dev_alloc(&d_cnt, slots)) != MC_OK) return rc;
       std::vector<int> hcnt(slots);
-      hipError_t e = launch_d1_count(n->d_row_ptr, n->d_tgt, n->d_dly, n->n_pad, n->nsb, sb_size, d_cnt, n->stream);
+      hipError_t e = launch_d1_count(n->d_row_ptr, n->d_tgt, n->d_dly, n->n_pad, n->nsb, n->d_bstart, n->wg_per_sb, G,
+                                     d_cnt, n->stream);
       if (e == hipSuccess) e = hipStreamSynchronize(n->stream);
       if (e == hipSuccess) e = hipMemcpy(hcnt.data(), d_cnt, sizeof(int) * slots, hipMemcpyDeviceToHost);
       dev_free(d_cnt);
       if (e != hipSuccess) return set_error(MC_ERR_HIP, std::string("delay-1 table: ") + hipGetErrorString(e));
       n->d1_cap = std::max(1, *std::max_element(hcnt.begin(), hcnt.end()));
       if ((rc = dev_alloc(&n->d_d1, slots * (size_t)(n->d1_cap + 1))) != MC_OK) return rc;
-      HIP_TRY(launch_d1_fill(n->d_row_ptr, n->d_tgt, n->d_wq, n->d_dly, n->n_pad, n->nsb, sb_size, n->d1_cap, n->d_d1,
-                             n->stream));
+      HIP_TRY(launch_d1_fill(n->d_row_ptr, n->d_tgt, n->d_wq, n->d_dly, n->n_pad, n->nsb, n->d_bstart, n->wg_per_sb, G,
+                             n->d1_cap, n->d_d1, n->stream));
       HIP_TRY(hipStreamSynchronize(n->stream));
     }
+    if (l.scheme == MC_SCHEME_TARGET_OWNER && (rc = setup_owner(n, l.neurons_per_wg ? l.neurons_per_wg : 256)) != MC_OK)
+      return rc;
     n->qpw = qpw;
     n->n_wg = n_wg;
     n->wg_neurons = wg_neurons;
@@ -384,6 +479,13 @@ hipError_t enqueue_direct(mc_net* n, int count, hipStream_t s) {
   hipError_t e = hipSuccess;
   if (n->launch.scheme == MC_SCHEME_STEP_KERNELS) {
     for (int k = 0; k < count && e == hipSuccess; ++k) e = launch_step(p, k, n->qpw, n->n_wg, n->launch.block, s);
+  } else if (n->launch.scheme == MC_SCHEME_TARGET_OWNER) {
+    const OwnerArgs a = n->owner();
+    e = launch_zero_lists(n->d_icnt, 2 * n->h.n_inst, s);
+    for (int k = 0; k < count && e == hipSuccess; ++k) {
+      e = launch_step_lists(p, k, n->qpw, n->n_wg, n->launch.block, s);
+      if (e == hipSuccess) e = launch_owner(p, a, k, s);
+    }
   } else {
     e = launch_persist(p, n->persist(), count, n->launch.block, s);
   }
@@ -498,6 +600,16 @@ int upload_network(mc_net* n) {
   if ((rc = dev_alloc(&n->d_table, h.table.size())) != MC_OK) return rc;
   if ((rc = dev_alloc(&n->d_step, 1)) != MC_OK) return rc;
   if ((rc = dev_alloc(&n->d_overflow, 1)) != MC_OK) return rc;
+  std::vector<int32_t> qinst((size_t)n->n_quads);
+  for (int b = 0; b < h.n_inst; ++b)
+    for (int64_t qq = n->inst_off_pad[b] / 4; qq < n->inst_off_pad[b + 1] / 4; ++qq) qinst[qq] = b;
+  if ((rc = dev_alloc(&n->d_qinst, (size_t)n->n_quads)) != MC_OK) return rc;
+  if ((rc = dev_alloc(&n->d_inst_base, (size_t)h.n_inst + 1)) != MC_OK) return rc;
+  if ((rc = dev_alloc(&n->d_ilist, (size_t)2 * P)) != MC_OK) return rc;
+  if ((rc = dev_alloc(&n->d_icnt, (size_t)2 * h.n_inst)) != MC_OK) return rc;
+  HIP_TRY(hipMemcpy(n->d_qinst, qinst.data(), sizeof(int32_t) * n->n_quads, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(n->d_inst_base, n->inst_off_pad.data(), sizeof(int64_t) * (h.n_inst + 1), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemset(n->d_icnt, 0, sizeof(int) * 2 * h.n_inst));
   HIP_TRY(hipMemcpy(n->d_row_ptr, rp.data(), sizeof(int64_t) * (P + 1), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(n->d_tgt, tg.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(n->d_wq, h.wq.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice));
@@ -787,7 +899,7 @@ int mc_set_weights(mc_net* n, const double* w_dev) {
   if (!device_ready(n) || !w_dev) return set_error(MC_ERR_INVALID_ARG, "bad handle or NULL");
   HIP_TRY(launch_set_weights(n->d_wq, w_dev, n->h.M, n->stream));
   if (n->d_d1)   // the persistent scheme's delay-1/2 table holds copies of those weights
-    HIP_TRY(launch_d1_fill(n->d_row_ptr, n->d_tgt, n->d_wq, n->d_dly, n->n_pad, n->nsb, (long long)n->wg_per_sb * n->pB,
+    HIP_TRY(launch_d1_fill(n->d_row_ptr, n->d_tgt, n->d_wq, n->d_dly, n->n_pad, n->nsb, n->d_bstart, n->wg_per_sb, n->pG,
                            n->d1_cap, n->d_d1, n->stream));
   HIP_TRY(hipStreamSynchronize(n->stream));
   HIP_TRY(hipMemcpy(n->h.wq.data(), n->d_wq, sizeof(int32_t) * n->h.M, hipMemcpyDeviceToHost));
@@ -883,10 +995,21 @@ int mc_profile_phases(mc_net* n, int64_t steps, double* us) {
   for (int g = 0; g < n->pG; ++g)
     for (int k = 0; k < 7; ++k) acc[k] += (double)h[(size_t)g * 8 + k];
   const double norm = tick_us / ((double)n->pG * (double)steps);
+  n->phase_wg.assign((size_t)n->pG * 8, 0.0);
+  for (size_t k = 0; k < h.size(); ++k) n->phase_wg[k] = (k % 8 == 7) ? 0.0 : (double)h[k] * tick_us / (double)steps;
   us[5] = 0;
   for (int k = 0; k < 5; ++k) { us[k] = acc[k] * norm; us[5] += us[k]; }
   us[6] = acc[5] * norm;   // drive + pending delivery of wavefront 0 while waiting
   us[7] = acc[6] * norm;   // polling of the first poller thread
+  return MC_OK;
+}
+
+int mc_get_phase_table(mc_net* n, double* out, int64_t capacity, int32_t* workgroups_out) {
+  if (!usable(n) || !workgroups_out) return set_error(MC_ERR_INVALID_ARG, "bad handle or NULL");
+  const int64_t G = (int64_t)n->phase_wg.size() / 8;
+  *workgroups_out = (int32_t)G;
+  if (!out || capacity < 8 * G) return G ? set_error(MC_ERR_BUFFER_TOO_SMALL, "phase table buffer too small") : MC_OK;
+  std::memcpy(out, n->phase_wg.data(), sizeof(double) * 8 * G);
   return MC_OK;
 }
 
@@ -986,6 +1109,11 @@ int mc_tune(mc_net* n, int64_t steps, mc_launch* best) {
       {sizeof(mc_launch), MC_SCHEME_PERSISTENT_LDS, 512, 0, (int)std::min<int64_t>(steps, 10000)},
       {sizeof(mc_launch), MC_SCHEME_PERSISTENT_LDS, 256, 0, (int)std::min<int64_t>(steps, 10000)},
       {sizeof(mc_launch), MC_SCHEME_PERSISTENT_LDS, 512, 256, (int)std::min<int64_t>(steps, 10000)},
+      {sizeof(mc_launch), MC_SCHEME_PERSISTENT_LDS, 512, 512, (int)std::min<int64_t>(steps, 10000)},
+      {sizeof(mc_launch), MC_SCHEME_PERSISTENT_LDS, 256, 128, (int)std::min<int64_t>(steps, 10000)},
+      {sizeof(mc_launch), MC_SCHEME_TARGET_OWNER, 256, 256, spg},
+      {sizeof(mc_launch), MC_SCHEME_TARGET_OWNER, 256, 128, spg},
+      {sizeof(mc_launch), MC_SCHEME_TARGET_OWNER, 256, 64, spg},
       {sizeof(mc_launch), MC_SCHEME_STEP_KERNELS, 256, 256, spg},
       {sizeof(mc_launch), MC_SCHEME_STEP_KERNELS, 256, 1024, spg},
       {sizeof(mc_launch), MC_SCHEME_STEP_KERNELS, 512, 512, spg},

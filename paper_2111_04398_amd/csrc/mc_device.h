@@ -44,6 +44,12 @@ struct DevNet {
   unsigned long long* wg_events;   // [n_wg]
   unsigned long long* wg_spikes;   // [n_wg * n_pops]
   unsigned* overflow;       // set if a raster segment would overflow
+  // target-owner scheme: per-instance spike lists of the current step
+  int32_t n_inst;
+  const int32_t* qinst;     // [n_quads] instance of each quad
+  const int64_t* inst_base; // [n_inst+1] first padded id of each instance
+  int* ilist;               // [2][n_pad] spike ids by step parity, instance b at inst_base[b]
+  int* icnt;                // [2][n_inst] list lengths by step parity
 };
 
 }  // namespace mc
@@ -53,10 +59,11 @@ namespace mc {
 // Arguments of the persistent LDS kernel (target-owner delivery).
 struct PersistArgs {
   int G;                       // workgroups (all co-resident, G <= block)
-  int B;                       // target neurons per workgroup (multiple of 4, <= 1024)
+  int B;                       // most target neurons of one workgroup (multiple of 4, <= kPersistMaxB)
+  const int* bstart;           // [G+1] workgroup g owns padded targets [bstart[g], bstart[g+1]) (multiples of 4)
   int DL;                      // near slots held in LDS (2..101)
   int BW;                      // 32-bit words per far-bitmap row: ceil(B/32)
-  const long long* blk;        // [n_pad][G+1] absolute synapse offsets of each target block
+  const long long* blk;        // [n_pad][G+1] first synapse of each row with target >= bstart[g]
   unsigned long long* flags;   // [G][2][8] spike records: (tag << 32) | count, (tag << 32) | id x7
   int* pub;                    // [G][2][B] published spike ids
   long long spin_limit;        // polls before giving up
@@ -66,23 +73,25 @@ struct PersistArgs {
   const unsigned long long* d1;   // [n_pad][nsb][d1_cap+1]
   int d1_cap;                  // entries per (source, superblock) slot
   int nsb;                     // superblocks
-  int wg_per_sb;               // workgroups per superblock (superblock = wg_per_sb*B targets)
+  int wg_per_sb;               // workgroups per superblock (superblock s = the targets of workgroups [s*wg_per_sb, ...))
 };
 constexpr int kPersistFlagStride = 8;
+inline size_t persist_flag_words(int G) { return (size_t)G * 2 * kPersistFlagStride; }
 constexpr int kPersistMaxB = 512;       // owned targets per workgroup (one per thread)
 constexpr int kPersistMaxBlock = 512;   // threads per workgroup: 256 VGPRs per lane, no scratch spills
 size_t persist_lds_bytes(int G, int B, int DL);
 // Delay-1 table: counts per (source, superblock), then the fill.
 hipError_t launch_d1_count(const int64_t* row_ptr, const int32_t* tgt, const uint8_t* dly, long long n_pad, int nsb,
-                           long long sb_size, int* counts, hipStream_t s);
+                           const int* bstart, int wps, int G, int* counts, hipStream_t s);
 hipError_t launch_d1_fill(const int64_t* row_ptr, const int32_t* tgt, const int32_t* wq, const uint8_t* dly,
-                          long long n_pad, int nsb, long long sb_size, int cap, unsigned long long* d1, hipStream_t s);
+                          long long n_pad, int nsb, const int* bstart, int wps, int G, int cap, unsigned long long* d1,
+                          hipStream_t s);
 hipError_t persist_static_lds(size_t* bytes);
 hipError_t persist_occupancy(int block, size_t lds, int* blocks_per_cu);
 hipError_t persist_set_lds_limit(size_t lds);
 hipError_t launch_persist(const DevNet& p, const PersistArgs& a, int steps, int block, hipStream_t s);
-hipError_t launch_build_blk(const int64_t* row_ptr, const int32_t* tgt, long long n_pad, int G, int B, long long* blk,
-                            hipStream_t s);
+hipError_t launch_build_blk(const int64_t* row_ptr, const int32_t* tgt, long long n_pad, int G, const int* bstart,
+                            long long* blk, hipStream_t s);
 
 constexpr int kReplayChunkHost = 256;     // must equal the replay kernel's chunk
 hipError_t launch_replay(const int2* spikes, const long long* first_item, int n_spikes, long long n_items,
@@ -118,6 +127,29 @@ hipError_t launch_adj_verify(const int2* spikes, int n, const uint8_t* rec_t, lo
 hipError_t launch_adj_gather(const int4* items, long long n_items, const int* times, const int64_t* row_ptr,
                              const int32_t* tgt, const uint8_t* dly, const double* li_ring, long long stride, int R,
                              long long last_m, void* grad, bool fp32, int grid, hipStream_t s);
+
+// Target-owner delivery (one kernel per step after the update kernel):
+// block k owns padded targets [bt0[k], bt0[k+1]) of instance binst[k]; it is
+// the lb = blb[k]-th block of that instance.  Row i's sub-row for the
+// instance's block lb is [row_ptr[i] + blk2[boff[i] + lb], row_ptr[i] +
+// blk2[boff[i] + lb + 1]).
+struct OwnerArgs {
+  int n_blocks;
+  int bmax;                 // most targets of one block
+  const int* bt0;           // [n_blocks+1]
+  const int* binst;         // [n_blocks]
+  const int* blb;           // [n_blocks]
+  const int64_t* boff;      // [n_pad+1]
+  const int32_t* blk2;      // [boff[n_pad]] offsets inside the row
+};
+constexpr int kOwnerBlock = 256;          // threads of the owner kernel
+constexpr int kOwnerMaxTargets = 1024;    // targets of one owner block
+hipError_t launch_step_lists(const DevNet& p, int offset, int qpw, int n_wg, int block, hipStream_t s);
+hipError_t launch_owner(const DevNet& p, const OwnerArgs& a, int offset, hipStream_t s);
+hipError_t launch_zero_lists(int* icnt, int n, hipStream_t s);
+hipError_t launch_build_blk2(const int64_t* row_ptr, const int32_t* tgt, long long n_pad, const int64_t* boff,
+                             const int32_t* qinst, const int* inst_first_block, const int* bt0, int32_t* blk2,
+                             hipStream_t s);
 
 constexpr int kMaxQuadsPerWgHost = 256;   // must equal the kernel's per-workgroup quad limit
 hipError_t launch_step(const DevNet& p, int offset, int qpw, int n_wg, int block, hipStream_t s);

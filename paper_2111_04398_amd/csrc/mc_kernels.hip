@@ -53,6 +53,7 @@ __device__ __forceinline__ int wave_prefix_small(int c, int* total) {
 // an ascending list in LDS, appends them to its private raster segment and
 // walks their synapse rows with all of its threads.
 // ---------------------------------------------------------------------------
+template <bool kOwnerLists>
 __global__ __launch_bounds__(kMaxBlock) void k_step(DevNet p, int offset, int qpw) {
   __shared__ uint64_t s_table[kMaxPops * kTableLen];
   __shared__ int s_wcnt[kMaxWaves];
@@ -143,6 +144,19 @@ __global__ __launch_bounds__(kMaxBlock) void k_step(DevNet p, int offset, int qp
     }
   }
 
+  if (kOwnerLists) {
+    // target-owner scheme: the spikes go to their instance's list of this
+    // step; the owner kernel delivers them
+    const int par = (int)(n & 1);
+    for (int s = tid; s < total; s += blockDim.x) {
+      const int i = s_spk[s];
+      const int b = p.qinst[i >> 2];
+      const int pos = atomicAdd(&p.icnt[par * p.n_inst + b], 1);
+      p.ilist[(size_t)par * p.n_pad + p.inst_base[b] + pos] = i;
+    }
+    return;
+  }
+
   // owner delivery: all threads walk each spiking row
   const long long nn = n;
   for (int s = 0; s < total; ++s) {
@@ -186,7 +200,12 @@ __global__ void k_set_weights(int32_t* wq, const double* w, long long M) {
 namespace mc {
 
 hipError_t launch_step(const DevNet& p, int offset, int qpw, int n_wg, int block, hipStream_t s) {
-  hipLaunchKernelGGL(k_step, dim3(n_wg), dim3(block), 0, s, p, offset, qpw);
+  hipLaunchKernelGGL(k_step<false>, dim3(n_wg), dim3(block), 0, s, p, offset, qpw);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_lists(const DevNet& p, int offset, int qpw, int n_wg, int block, hipStream_t s) {
+  hipLaunchKernelGGL(k_step<true>, dim3(n_wg), dim3(block), 0, s, p, offset, qpw);
   return hipGetLastError();
 }
 

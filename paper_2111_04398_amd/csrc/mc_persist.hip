@@ -47,6 +47,8 @@ constexpr int kListCap = 1024;       // spikes of one step kept in LDS (more: de
 constexpr int kRecWords = 8;         // record words (64 bytes)
 constexpr int kInline = kRecWords - 1;
 constexpr int kUnroll = 4;           // entries in flight per lane
+constexpr int kPollPerLane = kPersistMaxBlock / 64;   // producers polled by one lane (G <= block <= 512)
+constexpr int kNearUnroll = 12;      // near-table rows in flight per wavefront (one round for <= 12 spikes per wave)
 constexpr unsigned kNearD2 = 0x80000000u;   // near-table flag: delay 2 (else 1)
 
 __device__ __forceinline__ int poisson_inv(const uint64_t* T, uint32_t u) {
@@ -176,10 +178,10 @@ __device__ void wave_near(const PersistArgs& a, const Block& b, const int* list,
                           int Bg, int slot1, int slot2) {
   const int lane = threadIdx.x & 63;
   const int rowlen = a.d1_cap + 1;
-  for (int k = k0; k < k1; k += stride * kUnroll) {
-    unsigned long long v[kUnroll][2];
+  for (int k = k0; k < k1; k += stride * kNearUnroll) {
+    unsigned long long v[kNearUnroll][2];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
+    for (int u = 0; u < kNearUnroll; ++u) {
       const int kk = k + u * stride;
       v[u][0] = v[u][1] = 0;
       if (kk < k1) {
@@ -189,7 +191,7 @@ __device__ void wave_near(const PersistArgs& a, const Block& b, const int* list,
       }
     }
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
+    for (int u = 0; u < kNearUnroll; ++u) {
       const int kk = k + u * stride;
       if (kk >= k1) continue;
       const unsigned long long* row = a.d1 + ((size_t)list[kk] * a.nsb + sb) * rowlen;
@@ -223,6 +225,7 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
   __shared__ uint64_t s_table[kMaxPops * kTableLen];
   __shared__ int s_tmp[2][16];
   __shared__ int s_local[kPersistMaxB];
+  __shared__ int s_cnt[kPersistMaxBlock];   // spike count of every producer in the current step
   __shared__ int s_abort;
   __shared__ unsigned long long s_events;
   __shared__ unsigned long long s_popcnt[kMaxPops];
@@ -236,18 +239,16 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
 
   const int g = blockIdx.x, tid = threadIdx.x, nthr = blockDim.x;
   const int wave = tid >> 6, nw = nthr >> 6;
-  const long long j0 = (long long)g * a.B;                          // first owned target (padded id)
-  const int Bg = (int)max(0LL, min((long long)a.B, p.n_pad - j0));  // owned targets (multiple of 4)
+  const long long j0 = a.bstart[g];                                 // first owned target (padded id)
+  const int Bg = a.bstart[g + 1] - a.bstart[g];                     // owned targets (multiple of 4, <= B)
   const long long n0 = *p.step_base;
   const int DL = a.DL;
-  // Polling: one thread per producer workgroup.  If the workgroup has
-  // wavefronts to spare, the pollers are the last ceil(G/64) whole wavefronts
-  // and the others work on the pipelined delivery meanwhile.
-  const int nwp = (a.G + 63) / 64;
-  const bool overlap = nw > nwp;
-  const int nwd = overlap ? nw - nwp : nw;                           // wavefronts working while polling
-  const int pbase = overlap ? 64 * nwd : 0;
-  const int poller = (tid >= pbase && tid - pbase < a.G) ? tid - pbase : -1;
+  // Polling: the last wavefront polls every producer workgroup (lane l takes
+  // producers l, l+64, ...); the other wavefronts work on the pipelined
+  // delivery meanwhile.  A one-wavefront workgroup polls, then works.
+  const bool overlap = nw > 1;
+  const int nwd = overlap ? nw - 1 : nw;                             // wavefronts working while polling
+  const bool pollw = overlap ? (wave == nw - 1) : true;
   const int sb = g / a.wg_per_sb;
   const Block blk{acc, fbits, a.B, a.BW, DL, j0};
   auto bounds_of = [&](int par_) {
@@ -295,6 +296,11 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
   int S1 = 0;                           // spikes of step n-1: ids kept, block bounds due
   int S2 = 0;                           // spikes of step n-2: bounds kept, entries due
   int sn = (int)(n0 % DL);              // LDS slot of the current step
+  // every load above has landed: the loop body then waits only for its own
+  // memory operations (without this the compiler's wait insertion assumes the
+  // initial loads may still be in flight at every iteration and waits for all
+  // outstanding operations, stores included, at their first use)
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
 
   for (int it = 0; it < steps; ++it) {
@@ -366,34 +372,57 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
     //      wavefronts); polling (poller wavefronts) -----------------------------
     const long long tp_wait = (a.phase != nullptr) ? wall_clock64() : 0;
     if (upd && it + 1 < steps) kdrive = (int)((drive_counts(n + 1, qlocal, seed, qpops, s_table) >> (8 * qk)) & 0xFFu);
-    int cnt_h = 0;
-    const bool work_now = overlap ? (tid < pbase) : false;
-    if (poller >= 0) {
-      const unsigned long long* rec = a.flags + ((size_t)poller * 2 + par) * kPersistFlagStride;
+    const bool work_now = overlap && !pollw;
+    if (pollw) {
+      const int lane = tid & 63;
       long long spins = 0;
-      int ids[kInline];
-      while (true) {
-        const unsigned long long w0 = ld_dev(&rec[0]);
-        bool ok = (w0 & 0xFFFFFFFF00000000ull) == tag;
-        cnt_h = (int)(w0 & 0xFFFFFFFFu);
-        if (ok) {
+      unsigned todo = 0;
+#pragma unroll
+      for (int r = 0; r < kPollPerLane; ++r)
+        if (lane + 64 * r < a.G) todo |= 1u << r;
+      while (todo) {
+        unsigned long long w0[kPollPerLane];
+#pragma unroll
+        for (int r = 0; r < kPollPerLane; ++r)
+          w0[r] = ((todo >> r) & 1u) ? ld_dev(&a.flags[((size_t)(lane + 64 * r) * 2 + par) * kPersistFlagStride]) : 0ull;
+#pragma unroll
+        for (int r = 0; r < kPollPerLane; ++r) {
+          if (!((todo >> r) & 1u) || (w0[r] & 0xFFFFFFFF00000000ull) != tag) continue;
+          const int h = lane + 64 * r;
+          const int c = (int)(w0[r] & 0xFFFFFFFFu);
+          const unsigned long long* rec = a.flags + ((size_t)h * 2 + par) * kPersistFlagStride;
+          // all id words in one round trip (independent loads), then the tags
+          unsigned long long wk[kInline];
+          if (c > 0) {
+#pragma unroll
+            for (int k = 0; k < kInline; ++k) wk[k] = ld_dev(&rec[1 + k]);
+          }
+          bool ok = true;
+          int ids[kInline];
 #pragma unroll
           for (int k = 0; k < kInline; ++k) {
-            if (k < cnt_h) {
-              const unsigned long long wk = ld_dev(&rec[1 + k]);
-              ok = ok && ((wk & 0xFFFFFFFF00000000ull) == tag);
-              ids[k] = (int)(wk & 0xFFFFFFFFu);
-            }
+            ids[k] = (int)(wk[k] & 0xFFFFFFFFu);
+            if (k < c) ok &= ((wk[k] & 0xFFFFFFFF00000000ull) == tag);
           }
-        }
-        if (ok) break;
-        __builtin_amdgcn_s_sleep(1);
-        if (++spins > a.spin_limit) { atomicOr(p.overflow, 2u); s_abort = 1; cnt_h = 0; break; }
-      }
+          if (!ok) continue;
 #pragma unroll
-      for (int k = 0; k < kInline; ++k)
-        if (k < cnt_h) s_inl[poller * kInline + k] = ids[k];
-      if (a.phase != nullptr && poller == 0) ph[6] += wall_clock64() - tp_wait;
+          for (int k = 0; k < kInline; ++k)
+            if (k < c) s_inl[h * kInline + k] = ids[k];
+          s_cnt[h] = c;
+          todo &= ~(1u << r);
+        }
+        if (!todo) break;
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > a.spin_limit) {
+          atomicOr(p.overflow, 2u);
+          s_abort = 1;
+#pragma unroll
+          for (int r = 0; r < kPollPerLane; ++r)
+            if ((todo >> r) & 1u) s_cnt[lane + 64 * r] = 0;
+          break;
+        }
+      }
+      if (a.phase != nullptr && tid == nthr - 64) ph[6] += wall_clock64() - tp_wait;
     }
     if (work_now || !overlap) {
       if (!overlap) __syncthreads();      // no spare wavefronts: after the poll, all wavefronts
@@ -435,10 +464,12 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
       if (ev) atomicAdd(&s_events, ev);
       if (timing) ph[5] += wall_clock64() - tp_wait;
     }
+    __syncthreads();                       // s_cnt and the inline ids complete
     int S;
+    const int cnt_h = (tid < a.G) ? s_cnt[tid] : 0;
     const int pre_h = block_exscan(cnt_h, s_tmp[1], &S);   // also a barrier
     if (s_abort) break;
-    if (poller >= 0) s_pre[poller] = pre_h;
+    if (tid < a.G) s_pre[tid] = pre_h;
     if (tid == 0) s_pre[a.G] = S;
     __syncthreads();
     if (timing) { const long long t = wall_clock64(); ph[2] += t - tp0; tp0 = t; }
@@ -510,7 +541,7 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
     for (int k = 0; k < 6; ++k) a.phase[(size_t)g * 8 + k] += (unsigned long long)ph[k];
     a.phase[(size_t)g * 8 + 7] += (unsigned long long)steps;
   }
-  if (a.phase && poller == 0) a.phase[(size_t)g * 8 + 6] += (unsigned long long)ph[6];
+  if (a.phase && tid == nthr - 64) a.phase[(size_t)g * 8 + 6] += (unsigned long long)ph[6];
   if (tid == 0) {
     p.raster_cnt[g] = rcnt;
     p.wg_events[g] += s_events;
@@ -529,14 +560,15 @@ __global__ void k_zero_flags(unsigned long long* flags, int n) {
   for (int k = threadIdx.x; k < n; k += blockDim.x) flags[k] = 0;
 }
 
-// blk[i][g] = first synapse of row i whose target is >= g*B (rows sorted by target).
-__global__ void k_build_blk(const int64_t* row_ptr, const int32_t* tgt, long long n_pad, int G, int B, long long* blk) {
+// blk[i][g] = first synapse of row i whose target is >= bstart[g] (rows sorted by target).
+__global__ void k_build_blk(const int64_t* row_ptr, const int32_t* tgt, long long n_pad, int G, const int* bstart,
+                            long long* blk) {
   const long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (idx >= n_pad * (G + 1)) return;
   const long long i = idx / (G + 1);
   const int g = (int)(idx - i * (G + 1));
   long long lo = row_ptr[i], hi = row_ptr[i + 1];
-  const long long key = (long long)g * B;
+  const long long key = bstart[g];
   while (lo < hi) { const long long mid = (lo + hi) >> 1; if (tgt[mid] < key) lo = mid + 1; else hi = mid; }
   blk[idx] = lo;
 }
@@ -552,27 +584,28 @@ __device__ __forceinline__ void row_range(const int64_t* row_ptr, const int32_t*
   *e = lo;
 }
 
+// Superblock s covers the targets of workgroups [s*wps, min((s+1)*wps, G)).
 __global__ void k_d1_count(const int64_t* row_ptr, const int32_t* tgt, const uint8_t* dly, long long n_pad, int nsb,
-                           long long sb_size, int* counts) {
+                           const int* bstart, int wps, int G, int* counts) {
   const long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (idx >= n_pad * nsb) return;
   const long long i = idx / nsb;
   const int s = (int)(idx - i * nsb);
   long long b, e;
-  row_range(row_ptr, tgt, i, s * sb_size, (s + 1) * sb_size, &b, &e);
+  row_range(row_ptr, tgt, i, bstart[min(s * wps, G)], bstart[min((s + 1) * wps, G)], &b, &e);
   int c = 0;
   for (long long k = b; k < e; ++k) c += (dly[k] <= 2);
   counts[idx] = c;
 }
 
 __global__ void k_d1_fill(const int64_t* row_ptr, const int32_t* tgt, const int32_t* wq, const uint8_t* dly,
-                          long long n_pad, int nsb, long long sb_size, int cap, unsigned long long* d1) {
+                          long long n_pad, int nsb, const int* bstart, int wps, int G, int cap, unsigned long long* d1) {
   const long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (idx >= n_pad * nsb) return;
   const long long i = idx / nsb;
   const int s = (int)(idx - i * nsb);
   long long b, e;
-  row_range(row_ptr, tgt, i, s * sb_size, (s + 1) * sb_size, &b, &e);
+  row_range(row_ptr, tgt, i, bstart[min(s * wps, G)], bstart[min((s + 1) * wps, G)], &b, &e);
   unsigned long long* row = d1 + (size_t)idx * (cap + 1);
   int c = 0;
   for (long long k = b; k < e && c < cap; ++k)
@@ -607,26 +640,28 @@ hipError_t launch_persist(const DevNet& p, const PersistArgs& a, int steps, int 
   return hipGetLastError();
 }
 
-hipError_t launch_build_blk(const int64_t* row_ptr, const int32_t* tgt, long long n_pad, int G, int B, long long* blk,
-                            hipStream_t s) {
+hipError_t launch_build_blk(const int64_t* row_ptr, const int32_t* tgt, long long n_pad, int G, const int* bstart,
+                            long long* blk, hipStream_t s) {
   const long long total = n_pad * (G + 1);
-  hipLaunchKernelGGL(k_build_blk, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, row_ptr, tgt, n_pad, G, B, blk);
+  hipLaunchKernelGGL(k_build_blk, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, row_ptr, tgt, n_pad, G, bstart,
+                     blk);
   return hipGetLastError();
 }
 
 hipError_t launch_d1_count(const int64_t* row_ptr, const int32_t* tgt, const uint8_t* dly, long long n_pad, int nsb,
-                           long long sb_size, int* counts, hipStream_t s) {
+                           const int* bstart, int wps, int G, int* counts, hipStream_t s) {
   const long long total = n_pad * nsb;
   hipLaunchKernelGGL(k_d1_count, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, row_ptr, tgt, dly, n_pad, nsb,
-                     sb_size, counts);
+                     bstart, wps, G, counts);
   return hipGetLastError();
 }
 
 hipError_t launch_d1_fill(const int64_t* row_ptr, const int32_t* tgt, const int32_t* wq, const uint8_t* dly,
-                          long long n_pad, int nsb, long long sb_size, int cap, unsigned long long* d1, hipStream_t s) {
+                          long long n_pad, int nsb, const int* bstart, int wps, int G, int cap, unsigned long long* d1,
+                          hipStream_t s) {
   const long long total = n_pad * nsb;
   hipLaunchKernelGGL(k_d1_fill, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, row_ptr, tgt, wq, dly, n_pad,
-                     nsb, sb_size, cap, d1);
+                     nsb, bstart, wps, G, cap, d1);
   return hipGetLastError();
 }
 

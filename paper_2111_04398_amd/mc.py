@@ -29,7 +29,7 @@ RING_SLOTS = 128
 RULE_FIXED_INDEGREE, RULE_BERNOULLI = 0, 1
 GRAD_F64, GRAD_F32 = 0, 1
 FLAG_HOST_ONLY = 1
-SCHEME_STEP_KERNELS, SCHEME_PERSISTENT_LDS = 0, 1
+SCHEME_STEP_KERNELS, SCHEME_PERSISTENT_LDS, SCHEME_TARGET_OWNER = 0, 1, 2
 
 ERROR_NAMES = {0: "MC_OK", -1: "MC_ERR_INVALID_ARG", -2: "MC_ERR_RANGE", -3: "MC_ERR_OOM", -4: "MC_ERR_HIP",
                -5: "MC_ERR_STATE", -6: "MC_ERR_BUFFER_TOO_SMALL", -7: "MC_ERR_NO_DEVICE", -8: "MC_ERR_MISMATCH"}
@@ -78,7 +78,7 @@ EXPORTS = [
     "mc_get_state", "mc_set_state", "mc_get_ring", "mc_inject", "mc_get_propagators", "mc_get_drive_tables",
     "mc_get_counters", "mc_set_launch", "mc_get_launch", "mc_tune", "mc_last_simulate_ms", "mc_reserve",
     "mc_save_state", "mc_load_state", "mc_set_weights", "mc_stream", "mc_profile_phases", "mc_replay_delivery",
-    "mc_atomic_rate", "mc_last_adjoint_ms", "mc_get_persist_shape",
+    "mc_atomic_rate", "mc_last_adjoint_ms", "mc_get_persist_shape", "mc_get_phase_table",
 ]
 
 _lib = None
@@ -137,6 +137,7 @@ def lib() -> C.CDLL:
     L.mc_atomic_rate.argtypes = [vp, i64, C.POINTER(f64)]
     L.mc_last_adjoint_ms.argtypes = [vp, C.POINTER(f64), C.POINTER(f64)]
     L.mc_get_persist_shape.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
+    L.mc_get_phase_table.argtypes = [vp, vp, i64, C.POINTER(i32)]
     _lib = L
     return L
 
@@ -307,6 +308,16 @@ class Network:
         _check(lib().mc_profile_phases(self.h, steps, us), "mc_profile_phases")
         return dict(zip(["update", "publish", "wait", "gather", "deliver_d1", "total", "pending_delivery",
                          "poll"], us.tolist()))
+
+    def phase_table(self) -> np.ndarray:
+        """[G, 8] per-workgroup phase times (us/step) of the last profile_phases."""
+        g = C.c_int32()
+        rc = lib().mc_get_phase_table(self.h, None, 0, C.byref(g))
+        if rc not in (MC_OK, MC_ERR_BUFFER_TOO_SMALL):
+            _check(rc, "mc_get_phase_table")
+        out = np.zeros((g.value, 8), np.float64)
+        _check(lib().mc_get_phase_table(self.h, out.ctypes.data, out.size, C.byref(g)), "mc_get_phase_table")
+        return out
 
     def replay_delivery(self, begin: int, end: int, want_ring: bool = False):
         """Delivers the recorded spikes of steps [begin, end) in one launch;

@@ -47,12 +47,14 @@ def small():
     return w, S, loss, g, g32, (rs, ri), o.state(), o.synapses()
 
 
-@pytest.mark.parametrize("scheme", [0, 1])
+@pytest.mark.parametrize("scheme", [0, 1, 2])
 def test_adjoint_fp64_matches_oracle(small, scheme):
     w, S, loss, g, _, (rs, ri), (oy, oI, orr), (rp, tg, wq, d) = small
     net = mc.Network(w)
     if scheme == 1:
         net.set_launch(scheme=1, block=512, neurons_per_wg=0, steps_per_graph=0)
+    elif scheme == 2:
+        net.set_launch(scheme=2, block=256, neurons_per_wg=256, steps_per_graph=0)
     gl, gg = gpu_adjoint(net, S, w.adj_ckpt_every)
     assert abs(gl - loss) <= 1e-12 * abs(loss), (gl, loss)
     nz = np.count_nonzero(g)

@@ -78,11 +78,13 @@ def test_balanced_network_full_protocol():
 
 @pytest.mark.parametrize("scheme,block,npw,spg", [
     (0, 64, 64, 1), (0, 256, 256, 1000), (0, 256, 1024, 7), (0, 1024, 512, 333), (0, 128, 16, 50), (0, 256, 256, 0),
-    (1, 512, 0, 1000), (1, 256, 0, 100), (1, 512, 64, 7), (1, 512, 512, 250), (1, 512, 200, 0)])
+    (1, 512, 0, 1000), (1, 256, 0, 100), (1, 512, 64, 7), (1, 512, 512, 250), (1, 512, 200, 0),
+    (2, 256, 256, 1000), (2, 64, 16, 7), (2, 1024, 1024, 0), (2, 128, 100, 33)])
 def test_launch_configuration_invariance(scheme, block, npw, spg):
-    """Every launch shape of both schemes gives identical bits (integer sums,
-    fixed FP order).  neurons_per_wg = 512 leaves room for only ~30 delay
-    steps in LDS, so most events take the far (global) path."""
+    """Every launch shape of every scheme gives identical bits (integer sums,
+    fixed FP order).  Persistent neurons_per_wg = 512 leaves room for only ~30
+    delay steps in LDS, so most events take the far (global) path; the
+    target-owner shapes range from 16 to 1024 targets per delivery block."""
     w = workloads.balanced()
     net, o = mc.Network(w), oracle.Oracle(w.to_dict())
     net.set_launch(scheme=scheme, block=block, neurons_per_wg=npw, steps_per_graph=spg)
@@ -105,11 +107,12 @@ def test_scheme_switch_midway():
     """Switching between the schemes in the middle of a run changes nothing."""
     w = workloads.balanced()
     net, o = mc.Network(w), oracle.Oracle(w.to_dict())
-    for k, sch in enumerate([1, 0, 1, 1, 0]):
-        net.set_launch(scheme=sch, block=512 if sch else 256, neurons_per_wg=0 if sch else 256,
+    order = [1, 0, 2, 1, 1, 2, 0, 2]
+    for k, sch in enumerate(order):
+        net.set_launch(scheme=sch, block=512 if sch == 1 else 256, neurons_per_wg=0 if sch == 1 else 256,
                        steps_per_graph=97 + k)
         net.simulate(311)
-    o.run(5 * 311)
+    o.run(len(order) * 311)
     assert_same(net, o, what="switch")
 
 
@@ -134,12 +137,19 @@ def test_resume_and_checkpoint():
     assert np.array_equal(s_first, s2) and np.array_equal(i_first, i2)
 
 
-def test_batched_instances_match_standalone():
-    """Instances of a batch are bit-identical to their standalone runs."""
+@pytest.mark.parametrize("scheme", [0, 1, 2])
+def test_batched_instances_match_standalone(scheme):
+    """Instances of a batch are bit-identical to their standalone runs, in
+    every scheme (target-owner blocks of 64 targets: several per instance,
+    none spanning two instances)."""
     base = workloads.microcircuit()
     scales = [0.01, 0.013, 0.0071, 0.02]
     w = base.replace(inst_scale=scales, inst_seed=[1001, 1002, 1003, 1004])
     net = mc.Network(w)
+    if scheme == 1:
+        net.set_launch(scheme=1, block=512, neurons_per_wg=0, steps_per_graph=500)
+    elif scheme == 2:
+        net.set_launch(scheme=2, block=256, neurons_per_wg=64, steps_per_graph=300)
     net.simulate(1500)
     s, i = net.spikes()
     y, I, r = net.state()
@@ -171,7 +181,7 @@ def micro_oracle_runs():
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("scheme", [0, 1])
+@pytest.mark.parametrize("scheme", [0, 1, 2])
 def test_full_microcircuit_parity(micro_oracle_runs, scheme):
     """The full-scale microcircuit (77,169 neurons, ~3e8 synapses): raster,
     state bits and the first logical ring slots equal to the oracle's after
@@ -181,6 +191,8 @@ def test_full_microcircuit_parity(micro_oracle_runs, scheme):
     net = mc.Network(w)
     if scheme == 1:
         net.set_launch(scheme=1, block=512, neurons_per_wg=0, steps_per_graph=1000)
+    elif scheme == 2:
+        net.set_launch(scheme=2, block=256, neurons_per_wg=256, steps_per_graph=1000)
     assert (net.N, net.M) == (N, M)
     for steps, (ras, st, ring, cnt) in ((1000, a), (300, b)):
         net.simulate(steps)
