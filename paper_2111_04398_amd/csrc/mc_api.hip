@@ -120,8 +120,8 @@ struct mc_net {
   unsigned long long* d_phase = nullptr;
   bool phase_on = false;
   std::vector<double> phase_wg;        // per-workgroup phase times (us/step) of the last mc_profile_phases
-  unsigned long long* d_d1 = nullptr;
-  int d1_cap = 0, nsb = 1, wg_per_sb = 1;
+  unsigned* d_nb = nullptr;            // near table offsets [n_pad][pG+1]
+  unsigned long long* d_ne = nullptr;  // near table entries
   // recording
   int n_wg = 0;
   int qpw = 0;
@@ -175,7 +175,7 @@ struct mc_net {
     a.blk = d_blk; a.flags = d_flags; a.pub = d_pub;
     a.spin_limit = 1LL << 24;
     a.phase = phase_on ? d_phase : nullptr;
-    a.d1 = d_d1; a.d1_cap = d1_cap; a.nsb = nsb; a.wg_per_sb = wg_per_sb;
+    a.nb = d_nb; a.ne = d_ne;
     return a;
   }
 
@@ -211,7 +211,8 @@ int release_recording(mc_net* n) {
 void release_all(mc_net* n) {
   if (n->graph) { (void)hipGraphExecDestroy(n->graph); n->graph = nullptr; }
   release_recording(n);
-  dev_free(n->d_blk); dev_free(n->d_flags); dev_free(n->d_pub); dev_free(n->d_phase); dev_free(n->d_d1);
+  dev_free(n->d_blk); dev_free(n->d_flags); dev_free(n->d_pub); dev_free(n->d_phase); dev_free(n->d_nb);
+  dev_free(n->d_ne);
   dev_free(n->d_bstart);
   dev_free(n->d_qinst); dev_free(n->d_inst_base); dev_free(n->d_ilist); dev_free(n->d_icnt);
   dev_free(n->d_bt0); dev_free(n->d_binst); dev_free(n->d_blb); dev_free(n->d_ifb); dev_free(n->d_boff);
@@ -440,24 +441,22 @@ int apply_launch(mc_net* n, const mc_launch& l) {
       n->bstart_host = bs;
       HIP_TRY(launch_build_blk(n->d_row_ptr, n->d_tgt, n->n_pad, G, n->d_bstart, n->d_blk, n->stream));
       HIP_TRY(hipMemsetAsync(n->d_flags, 0, sizeof(unsigned long long) * persist_flag_words(G), n->stream));
-      // delay-1 table: per (source, superblock of wg_per_sb target blocks)
-      dev_free(n->d_d1);
-      n->nsb = std::min(8, G);
-      n->wg_per_sb = (G + n->nsb - 1) / n->nsb;
-      const size_t slots = (size_t)n->n_pad * n->nsb;
-      int* d_cnt = nullptr;
-      if ((rc = dev_alloc(&d_cnt, slots)) != MC_OK) return rc;
-      std::vector<int> hcnt(slots);
-      hipError_t e = launch_d1_count(n->d_row_ptr, n->d_tgt, n->d_dly, n->n_pad, n->nsb, n->d_bstart, n->wg_per_sb, G,
-                                     d_cnt, n->stream);
-      if (e == hipSuccess) e = hipStreamSynchronize(n->stream);
-      if (e == hipSuccess) e = hipMemcpy(hcnt.data(), d_cnt, sizeof(int) * slots, hipMemcpyDeviceToHost);
-      dev_free(d_cnt);
-      if (e != hipSuccess) return set_error(MC_ERR_HIP, std::string("delay-1 table: ") + hipGetErrorString(e));
-      n->d1_cap = std::max(1, *std::max_element(hcnt.begin(), hcnt.end()));
-      if ((rc = dev_alloc(&n->d_d1, slots * (size_t)(n->d1_cap + 1))) != MC_OK) return rc;
-      HIP_TRY(launch_d1_fill(n->d_row_ptr, n->d_tgt, n->d_wq, n->d_dly, n->n_pad, n->nsb, n->d_bstart, n->wg_per_sb, G,
-                             n->d1_cap, n->d_d1, n->stream));
+      // near table: the delay-1/2 synapses per (source, workgroup), CSR
+      dev_free(n->d_nb); dev_free(n->d_ne);
+      const size_t cells = (size_t)n->n_pad * (G + 1);
+      if ((rc = dev_alloc(&n->d_nb, cells)) != MC_OK) return rc;
+      HIP_TRY(launch_near_count(n->d_tgt, n->d_dly, n->d_blk, n->n_pad, G, n->d_nb, n->stream));
+      std::vector<unsigned> hc;
+      try { hc.resize(cells); } catch (...) { return set_error(MC_ERR_OOM, "host allocation of the near-table offsets failed"); }
+      HIP_TRY(hipStreamSynchronize(n->stream));
+      HIP_TRY(hipMemcpy(hc.data(), n->d_nb, sizeof(unsigned) * cells, hipMemcpyDeviceToHost));
+      uint64_t total = 0;
+      for (size_t k = 0; k < cells; ++k) { const unsigned c = hc[k]; hc[k] = (unsigned)total; total += c; }
+      if (total >= ((uint64_t)1 << 32)) return set_error(MC_ERR_RANGE, "more than 2^32 delay-1/2 synapses");
+      HIP_TRY(hipMemcpy(n->d_nb, hc.data(), sizeof(unsigned) * cells, hipMemcpyHostToDevice));
+      if ((rc = dev_alloc(&n->d_ne, (size_t)std::max<uint64_t>(total, 1))) != MC_OK) return rc;
+      HIP_TRY(launch_near_fill(n->d_tgt, n->d_wq, n->d_dly, n->d_blk, n->d_bstart, n->n_pad, G, n->d_nb, n->d_ne,
+                               n->stream));
       HIP_TRY(hipStreamSynchronize(n->stream));
     }
     if (l.scheme == MC_SCHEME_TARGET_OWNER && (rc = setup_owner(n, l.neurons_per_wg ? l.neurons_per_wg : 256)) != MC_OK)
@@ -898,9 +897,9 @@ int mc_stream(mc_net* n, void** s) {
 int mc_set_weights(mc_net* n, const double* w_dev) {
   if (!device_ready(n) || !w_dev) return set_error(MC_ERR_INVALID_ARG, "bad handle or NULL");
   HIP_TRY(launch_set_weights(n->d_wq, w_dev, n->h.M, n->stream));
-  if (n->d_d1)   // the persistent scheme's delay-1/2 table holds copies of those weights
-    HIP_TRY(launch_d1_fill(n->d_row_ptr, n->d_tgt, n->d_wq, n->d_dly, n->n_pad, n->nsb, n->d_bstart, n->wg_per_sb, n->pG,
-                           n->d1_cap, n->d_d1, n->stream));
+  if (n->d_ne)   // the persistent scheme's near table holds copies of the delay-1/2 weights
+    HIP_TRY(launch_near_fill(n->d_tgt, n->d_wq, n->d_dly, n->d_blk, n->d_bstart, n->n_pad, n->pG, n->d_nb, n->d_ne,
+                             n->stream));
   HIP_TRY(hipStreamSynchronize(n->stream));
   HIP_TRY(hipMemcpy(n->h.wq.data(), n->d_wq, sizeof(int32_t) * n->h.M, hipMemcpyDeviceToHost));
   return MC_OK;

@@ -68,24 +68,22 @@ struct PersistArgs {
   int* pub;                    // [G][2][B] published spike ids
   long long spin_limit;        // polls before giving up
   unsigned long long* phase;   // optional [G*8]: summed wall_clock64 ticks per phase (nullptr: off)
-  // delay-1 table: for source i and target superblock sb, word 0 = count,
-  // words 1..count = (target << 32) | (uint32)weight of its delay-1 synapses
-  const unsigned long long* d1;   // [n_pad][nsb][d1_cap+1]
-  int d1_cap;                  // entries per (source, superblock) slot
-  int nsb;                     // superblocks
-  int wg_per_sb;               // workgroups per superblock (superblock s = the targets of workgroups [s*wg_per_sb, ...))
+  // near table: the delay-1/2 synapses of row i into workgroup g's block are
+  // ne[nb[i][g] .. nb[i][g+1]), each (delay-2 flag | target - bstart[g]) << 32 | weight
+  const unsigned* nb;          // [n_pad][G+1]
+  const unsigned long long* ne;
 };
 constexpr int kPersistFlagStride = 8;
 inline size_t persist_flag_words(int G) { return (size_t)G * 2 * kPersistFlagStride; }
 constexpr int kPersistMaxB = 512;       // owned targets per workgroup (one per thread)
 constexpr int kPersistMaxBlock = 512;   // threads per workgroup: 256 VGPRs per lane, no scratch spills
 size_t persist_lds_bytes(int G, int B, int DL);
-// Delay-1 table: counts per (source, superblock), then the fill.
-hipError_t launch_d1_count(const int64_t* row_ptr, const int32_t* tgt, const uint8_t* dly, long long n_pad, int nsb,
-                           const int* bstart, int wps, int G, int* counts, hipStream_t s);
-hipError_t launch_d1_fill(const int64_t* row_ptr, const int32_t* tgt, const int32_t* wq, const uint8_t* dly,
-                          long long n_pad, int nsb, const int* bstart, int wps, int G, int cap, unsigned long long* d1,
-                          hipStream_t s);
+// Near table: counts per (source, workgroup), then (after an exclusive scan) the fill.
+hipError_t launch_near_count(const int32_t* tgt, const uint8_t* dly, const long long* blk, long long n_pad, int G,
+                             unsigned* cnt, hipStream_t s);
+hipError_t launch_near_fill(const int32_t* tgt, const int32_t* wq, const uint8_t* dly, const long long* blk,
+                            const int* bstart, long long n_pad, int G, const unsigned* nb, unsigned long long* ne,
+                            hipStream_t s);
 hipError_t persist_static_lds(size_t* bytes);
 hipError_t persist_occupancy(int block, size_t lds, int* blocks_per_cu);
 hipError_t persist_set_lds_limit(size_t lds);

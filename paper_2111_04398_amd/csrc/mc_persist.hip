@@ -171,46 +171,52 @@ __device__ __forceinline__ void wave_entries(const DevNet& p, const Block& b, in
   }
 }
 
-// One wavefront adds the delay-1 and delay-2 events of spikes list[k]
-// (k = k0, k0+stride, ...) from the near table: slots slot1 (step n+1) and
-// slot2 (step n+2).  Lanes walk a table slot's entries.
-__device__ void wave_near(const PersistArgs& a, const Block& b, const int* list, int k0, int k1, int stride, int sb,
-                          int Bg, int slot1, int slot2) {
+// One wavefront adds the delay-1 and delay-2 events of spikes list[k0..k1)
+// that land in this workgroup's block: the near table holds them per
+// (source, workgroup) as a CSR (offsets nb[i][g], nb[i][g+1]; entries
+// (delay-2 flag | local target) << 32 | weight).  Lanes load the offsets of 64
+// spikes, scan the counts and walk the concatenated entries.
+__device__ __forceinline__ void wave_near(const PersistArgs& a, const Block& b, const int* list, int k0, int k1, int g,
+                                          int slot1, int slot2) {
   const int lane = threadIdx.x & 63;
-  const int rowlen = a.d1_cap + 1;
-  for (int k = k0; k < k1; k += stride * kNearUnroll) {
-    unsigned long long v[kNearUnroll][2];
-#pragma unroll
-    for (int u = 0; u < kNearUnroll; ++u) {
-      const int kk = k + u * stride;
-      v[u][0] = v[u][1] = 0;
-      if (kk < k1) {
-        const unsigned long long* row = a.d1 + ((size_t)list[kk] * a.nsb + sb) * rowlen;
-        if (lane < rowlen) v[u][0] = row[lane];
-        if (lane + 64 < rowlen) v[u][1] = row[lane + 64];
-      }
+  for (int base = k0; base < k1; base += 64) {
+    unsigned lo = 0;
+    int len = 0;
+    if (base + lane < k1) {
+      const unsigned* o = a.nb + (size_t)list[base + lane] * (a.G + 1) + g;
+      lo = o[0];
+      len = (int)(o[1] - lo);
     }
+    int x = len;
 #pragma unroll
-    for (int u = 0; u < kNearUnroll; ++u) {
-      const int kk = k + u * stride;
-      if (kk >= k1) continue;
-      const unsigned long long* row = a.d1 + ((size_t)list[kk] * a.nsb + sb) * rowlen;
-      const int cnt = (int)__shfl((long long)v[u][0], 0, 64);   // wave-uniform
-      for (int e0 = 0; e0 < cnt; e0 += 64) {
-        // entry e sits in word e+1; every lane takes part in the shuffles
-        const int e = e0 + lane;
-        const int wi = e + 1;
-        const long long s0 = __shfl((long long)v[u][0], wi & 63, 64);
-        const long long s1 = __shfl((long long)v[u][1], wi & 63, 64);
-        if (e >= cnt) continue;
-        const unsigned long long wv = wi < 64 ? (unsigned long long)s0 : wi < 128 ? (unsigned long long)s1 : row[wi];
-        const unsigned hi = (unsigned)(wv >> 32);
-        const int jl = (int)((long long)(hi & ~kNearD2) - b.j0);
-        if (jl >= 0 && jl < Bg) {
-          const int slot = (hi & kNearD2) ? slot2 : slot1;
-          atomicAdd(reinterpret_cast<unsigned long long*>(&b.acc[(size_t)slot * b.B + jl]),
-                    (unsigned long long)(long long)(int)(wv & 0xFFFFFFFFu));
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    const int total = __shfl(x, 63, 64);
+    const int excl = x - len;
+    for (int f0 = 0; f0 < total; f0 += 64 * kUnroll) {
+      unsigned long long v[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int f = f0 + u * 64 + lane;
+        int lo_l = 0, hi_l = 64;              // lane j holding entry f: excl_j <= f < excl_{j+1}
+#pragma unroll
+        for (int st = 0; st < 6; ++st) {
+          const int mid = (lo_l + hi_l) >> 1;
+          if (__shfl(excl, mid, 64) <= f) lo_l = mid; else hi_l = mid;
         }
+        const unsigned lo_j = (unsigned)__shfl((int)lo, lo_l, 64);
+        const int ex_j = __shfl(excl, lo_l, 64);
+        v[u] = (f < total) ? a.ne[lo_j + (unsigned)(f - ex_j)] : 0ull;
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        if (f0 + u * 64 + lane >= total) continue;
+        const unsigned hi = (unsigned)(v[u] >> 32);
+        const int slot = (hi & kNearD2) ? slot2 : slot1;
+        atomicAdd(reinterpret_cast<unsigned long long*>(&b.acc[(size_t)slot * b.B + (hi & 0xFFFFu)]),
+                  (unsigned long long)(long long)(int)(v[u] & 0xFFFFFFFFu));
       }
     }
   }
@@ -249,7 +255,6 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
   const bool overlap = nw > 1;
   const int nwd = overlap ? nw - 1 : nw;                             // wavefronts working while polling
   const bool pollw = overlap ? (wave == nw - 1) : true;
-  const int sb = g / a.wg_per_sb;
   const Block blk{acc, fbits, a.B, a.BW, DL, j0};
   auto bounds_of = [&](int par_) {
     return [=](int k, long long* lo, int* len) { *lo = s_lo[par_ * kListCap + k]; *len = s_len[par_ * kListCap + k]; };
@@ -487,7 +492,7 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
       __syncthreads();
       if (timing) { const long long t = wall_clock64(); ph[3] += t - tp0; tp0 = t; }
       if (S <= kListCap) {
-        wave_near(a, blk, ids_n, wave, cnt, nw, sb, Bg, sn1, sn2);
+        wave_near(a, blk, ids_n, (int)((long long)cnt * wave / nw), (int)((long long)cnt * (wave + 1) / nw), g, sn1, sn2);
       } else {
         // too many spikes to keep: deliver all events of this chunk now
         const int k0 = (int)((long long)cnt * wave / nw), k1 = (int)((long long)cnt * (wave + 1) / nw);
@@ -585,33 +590,31 @@ __device__ __forceinline__ void row_range(const int64_t* row_ptr, const int32_t*
 }
 
 // Superblock s covers the targets of workgroups [s*wps, min((s+1)*wps, G)).
-__global__ void k_d1_count(const int64_t* row_ptr, const int32_t* tgt, const uint8_t* dly, long long n_pad, int nsb,
-                           const int* bstart, int wps, int G, int* counts) {
+// Near (delay 1-2) synapses of row i that land in workgroup g's block:
+// counts into cnt[i][g] (g < G; cnt[i][G] = 0 for the exclusive scan).
+__global__ void k_near_count(const int32_t* tgt, const uint8_t* dly, const long long* blk, long long n_pad, int G,
+                             unsigned* cnt) {
   const long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (idx >= n_pad * nsb) return;
-  const long long i = idx / nsb;
-  const int s = (int)(idx - i * nsb);
-  long long b, e;
-  row_range(row_ptr, tgt, i, bstart[min(s * wps, G)], bstart[min((s + 1) * wps, G)], &b, &e);
-  int c = 0;
-  for (long long k = b; k < e; ++k) c += (dly[k] <= 2);
-  counts[idx] = c;
+  if (idx >= n_pad * (G + 1)) return;
+  const int g = (int)(idx % (G + 1));
+  unsigned c = 0;
+  if (g < G)
+    for (long long k = blk[idx]; k < blk[idx + 1]; ++k) c += (dly[k] <= 2);
+  cnt[idx] = c;
 }
 
-__global__ void k_d1_fill(const int64_t* row_ptr, const int32_t* tgt, const int32_t* wq, const uint8_t* dly,
-                          long long n_pad, int nsb, const int* bstart, int wps, int G, int cap, unsigned long long* d1) {
+// Entries at nb[i][g]...: (delay-2 flag | target - bstart[g]) << 32 | weight, in row order.
+__global__ void k_near_fill(const int32_t* tgt, const int32_t* wq, const uint8_t* dly, const long long* blk,
+                            const int* bstart, long long n_pad, int G, const unsigned* nb, unsigned long long* ne) {
   const long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (idx >= n_pad * nsb) return;
-  const long long i = idx / nsb;
-  const int s = (int)(idx - i * nsb);
-  long long b, e;
-  row_range(row_ptr, tgt, i, bstart[min(s * wps, G)], bstart[min((s + 1) * wps, G)], &b, &e);
-  unsigned long long* row = d1 + (size_t)idx * (cap + 1);
-  int c = 0;
-  for (long long k = b; k < e && c < cap; ++k)
+  if (idx >= n_pad * (G + 1)) return;
+  const int g = (int)(idx % (G + 1));
+  if (g == G) return;
+  unsigned o = nb[idx];
+  for (long long k = blk[idx]; k < blk[idx + 1]; ++k)
     if (dly[k] <= 2)
-      row[1 + c++] = ((unsigned long long)((unsigned)tgt[k] | (dly[k] == 2 ? kNearD2 : 0u)) << 32) | (unsigned)wq[k];
-  row[0] = (unsigned long long)c;
+      ne[o++] = ((unsigned long long)((unsigned)(tgt[k] - bstart[g]) | (dly[k] == 2 ? kNearD2 : 0u)) << 32) |
+                (unsigned)wq[k];
 }
 
 size_t persist_lds_bytes(int G, int B, int DL) {
@@ -648,20 +651,19 @@ hipError_t launch_build_blk(const int64_t* row_ptr, const int32_t* tgt, long lon
   return hipGetLastError();
 }
 
-hipError_t launch_d1_count(const int64_t* row_ptr, const int32_t* tgt, const uint8_t* dly, long long n_pad, int nsb,
-                           const int* bstart, int wps, int G, int* counts, hipStream_t s) {
-  const long long total = n_pad * nsb;
-  hipLaunchKernelGGL(k_d1_count, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, row_ptr, tgt, dly, n_pad, nsb,
-                     bstart, wps, G, counts);
+hipError_t launch_near_count(const int32_t* tgt, const uint8_t* dly, const long long* blk, long long n_pad, int G,
+                             unsigned* cnt, hipStream_t s) {
+  const long long total = n_pad * (G + 1);
+  hipLaunchKernelGGL(k_near_count, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, tgt, dly, blk, n_pad, G, cnt);
   return hipGetLastError();
 }
 
-hipError_t launch_d1_fill(const int64_t* row_ptr, const int32_t* tgt, const int32_t* wq, const uint8_t* dly,
-                          long long n_pad, int nsb, const int* bstart, int wps, int G, int cap, unsigned long long* d1,
-                          hipStream_t s) {
-  const long long total = n_pad * nsb;
-  hipLaunchKernelGGL(k_d1_fill, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, row_ptr, tgt, wq, dly, n_pad,
-                     nsb, bstart, wps, G, cap, d1);
+hipError_t launch_near_fill(const int32_t* tgt, const int32_t* wq, const uint8_t* dly, const long long* blk,
+                            const int* bstart, long long n_pad, int G, const unsigned* nb, unsigned long long* ne,
+                            hipStream_t s) {
+  const long long total = n_pad * (G + 1);
+  hipLaunchKernelGGL(k_near_fill, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, tgt, wq, dly, blk, bstart,
+                     n_pad, G, nb, ne);
   return hipGetLastError();
 }
 
