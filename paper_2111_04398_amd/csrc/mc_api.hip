@@ -1104,12 +1104,15 @@ int mc_tune(mc_net* n, int64_t steps, mc_launch* best) {
   if (rc != MC_OK) return rc;
   const mc_launch original = n->launch;
   const int spg = (int)std::min<int64_t>(steps, 1000);
+  // persistent launches of 10,000 steps: the per-launch prologue and
+  // epilogue (LDS window in and out) amortise over 1 s of model time
+  const int kPersistSteps = 10000;
   const mc_launch cands[] = {
-      {sizeof(mc_launch), MC_SCHEME_PERSISTENT_LDS, 512, 0, (int)std::min<int64_t>(steps, 10000)},
-      {sizeof(mc_launch), MC_SCHEME_PERSISTENT_LDS, 256, 0, (int)std::min<int64_t>(steps, 10000)},
-      {sizeof(mc_launch), MC_SCHEME_PERSISTENT_LDS, 512, 256, (int)std::min<int64_t>(steps, 10000)},
-      {sizeof(mc_launch), MC_SCHEME_PERSISTENT_LDS, 512, 512, (int)std::min<int64_t>(steps, 10000)},
-      {sizeof(mc_launch), MC_SCHEME_PERSISTENT_LDS, 256, 128, (int)std::min<int64_t>(steps, 10000)},
+      {sizeof(mc_launch), MC_SCHEME_PERSISTENT_LDS, 512, 0, kPersistSteps},
+      {sizeof(mc_launch), MC_SCHEME_PERSISTENT_LDS, 256, 0, kPersistSteps},
+      {sizeof(mc_launch), MC_SCHEME_PERSISTENT_LDS, 512, 256, kPersistSteps},
+      {sizeof(mc_launch), MC_SCHEME_PERSISTENT_LDS, 512, 512, kPersistSteps},
+      {sizeof(mc_launch), MC_SCHEME_PERSISTENT_LDS, 256, 128, kPersistSteps},
       {sizeof(mc_launch), MC_SCHEME_TARGET_OWNER, 256, 256, spg},
       {sizeof(mc_launch), MC_SCHEME_TARGET_OWNER, 256, 128, spg},
       {sizeof(mc_launch), MC_SCHEME_TARGET_OWNER, 256, 64, spg},

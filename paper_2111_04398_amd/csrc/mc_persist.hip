@@ -478,24 +478,24 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
     if (tid == 0) s_pre[a.G] = S;
     __syncthreads();
     if (timing) { const long long t = wall_clock64(); ph[2] += t - tp0; tp0 = t; }
-    // ---- the spikes of step n: ids into LDS, then their near events ---------
+    // ---- the spikes of step n: each wavefront lists its share of the ids in
+    //      LDS (for the pipeline) and delivers their near events -------------
     int* ids_n = s_ids + par * kListCap;
     for (int base = 0; base < S; base += kListCap) {
       const int cnt = min(kListCap, S - base);
-      for (int k = tid; k < cnt; k += nthr) {
+      const int k0 = (int)((long long)cnt * wave / nw), k1 = (int)((long long)cnt * (wave + 1) / nw);
+      for (int k = k0 + (tid & 63); k < k1; k += 64) {
         const int gk = base + k;
         int lo = 0, hi = a.G;                 // producer h: s_pre[h] <= gk < s_pre[h+1]
         while (hi - lo > 1) { const int mid = (lo + hi) >> 1; if (s_pre[mid] <= gk) lo = mid; else hi = mid; }
         const int kk = gk - s_pre[lo];
         ids_n[k] = (kk < kInline) ? s_inl[lo * kInline + kk] : ld_dev(&a.pub[((size_t)lo * 2 + par) * a.B + kk]);
       }
-      __syncthreads();
       if (timing) { const long long t = wall_clock64(); ph[3] += t - tp0; tp0 = t; }
       if (S <= kListCap) {
-        wave_near(a, blk, ids_n, (int)((long long)cnt * wave / nw), (int)((long long)cnt * (wave + 1) / nw), g, sn1, sn2);
+        wave_near(a, blk, ids_n, k0, k1, g, sn1, sn2);   // reads the ids this wavefront wrote
       } else {
         // too many spikes to keep: deliver all events of this chunk now
-        const int k0 = (int)((long long)cnt * wave / nw), k1 = (int)((long long)cnt * (wave + 1) / nw);
         unsigned long long ev = 0;
         auto direct = [&](int k, long long* lo, int* len) {
           const long long* bi = a.blk + (size_t)ids_n[k] * (a.G + 1) + g;
