@@ -136,7 +136,12 @@ typedef struct mc_adjoint_config {
   int64_t ckpt_every;            /* K >= 1: forward state kept every K steps, recomputed in between */
   double v_target_mV;            /* loss target V* */
   int32_t grad_dtype;            /* MC_GRAD_F64 or MC_GRAD_F32 */
+  int32_t input_mode;            /* how a segment's synaptic input is recovered for the recompute:
+                                    MC_ADJ_INPUT_AUTO, _RECORD (the forward stores every neuron's integer
+                                    input: 8 B per neuron-step), _REPLAY (the ring is kept with every
+                                    checkpoint and the recorded spikes are delivered again) */
 } mc_adjoint_config;
+enum { MC_ADJ_INPUT_AUTO = 0, MC_ADJ_INPUT_RECORD = 1, MC_ADJ_INPUT_REPLAY = 2 };
 
 /* --- the four calls of the simulation --------------------------------- */
 
@@ -171,10 +176,12 @@ int mc_get_spikes(mc_net* net, int64_t step_begin, int64_t step_end,
  * instances.  The state at n0, including inputs still pending from spikes
  * before n0, is the fixed initial condition.  The network advances by S
  * steps exactly as mc_simulate(S) would (same spikes, same raster).  The
- * forward state is kept every ckpt_every steps (y, I, r and the ring, about
- * 8 B x 128 x N per checkpoint) and recomputed per segment from the recorded
- * spikes; a recompute that does not reproduce the recorded spikes returns
- * MISMATCH.  grad_dev: caller-owned device array of mc_get_sizes().n_synapses
+ * forward state (y, I, r) is kept every ckpt_every steps and recomputed per
+ * segment; the segment's synaptic input comes either from a record of every
+ * neuron's integer input made by the forward (8 B per neuron-step: the
+ * default up to 16 GiB) or from the ring kept with each checkpoint (about
+ * 8 B x 128 x N) plus a second delivery of the recorded spikes.  A recompute
+ * that does not reproduce the recorded spikes returns MISMATCH.  grad_dev: caller-owned device array of mc_get_sizes().n_synapses
  * elements (double for MC_GRAD_F64; float for MC_GRAD_F32, accumulated as
  * g = f32(g + f32(term)) from FP64 adjoint states), in the canonical synapse
  * order of mc_get_synapses; overwritten.  *loss_out (host): L.

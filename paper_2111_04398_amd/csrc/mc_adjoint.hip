@@ -31,7 +31,7 @@
 //                      over the segment, writing LI into a ring of R slots;
 //   4. k_adj_verify    every recorded spike of the segment must be a spike
 //                      of the recompute (and the counts must agree);
-//   5. k_adj_gather    one wavefront per (source, chunk of its row): for
+//   5. k_adj_gather    one wavefront per (source, chunk of 256 of its row): for
 //                      every synapse, adds LI_tgt(t + d + 1) over the
 //                      source's spikes t in [a-2, a+len-2), latest first,
 //                      into grad[s] (FP64, or FP32 as g = f32(g + f32(LI))).
@@ -124,18 +124,23 @@ __global__ __launch_bounds__(kAdjBlock) void k_adj_verify(const int2* spikes, in
 
 constexpr int kGatherChunk = 256;   // synapses per work item (4 per lane)
 
-// Work item: (source row, chunk of the row, first spike time in `times`, count).
+// Work item it: chunk it - first[j] of source j, the j with first[j] <= it
+// < first[j+1]; srcs[j] = (padded source id, first spike time in `times`,
+// number of its spike times, -).
 template <typename G>
-__global__ __launch_bounds__(kAdjBlock) void k_adj_gather(const int4* items, long long n_items, const int* times,
-                                                          const int64_t* row_ptr, const int32_t* tgt,
-                                                          const uint8_t* dly, const double* li_ring, long long stride,
-                                                          int R, long long last_m, G* grad) {
+__global__ __launch_bounds__(kAdjBlock) void k_adj_gather(const int4* srcs, const long long* first, int nsrc,
+                                                          long long n_items, const int* times, const int64_t* row_ptr,
+                                                          const int32_t* tgt, const uint8_t* dly,
+                                                          const double* li_ring, long long stride, int R,
+                                                          long long last_m, G* grad) {
   const int lane = threadIdx.x & 63;
   const long long wave = (blockIdx.x * (long long)blockDim.x + threadIdx.x) >> 6;
   const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
   for (long long it = wave; it < n_items; it += nwaves) {
-    const int4 w = items[it];
-    const long long rs = row_ptr[w.x] + (long long)w.y * kGatherChunk;
+    int lo = 0, hi = nsrc;
+    while (hi - lo > 1) { const int mid = (lo + hi) >> 1; if (first[mid] <= it) lo = mid; else hi = mid; }
+    const int4 w = srcs[lo];
+    const long long rs = row_ptr[w.x] + (it - first[lo]) * kGatherChunk;
     const long long re = min(rs + kGatherChunk, (long long)row_ptr[w.x + 1]);
 #pragma unroll
     for (int u = 0; u < kGatherChunk / 64; ++u) {
@@ -145,8 +150,8 @@ __global__ __launch_bounds__(kAdjBlock) void k_adj_gather(const int4* items, lon
       const int d = dly[e];
       G acc = grad[e];
       bool hit = false;
-      for (int q = 0; q < w.w; ++q) {
-        const long long m = (long long)times[w.z + q] + d + 1;
+      for (int q = 0; q < w.z; ++q) {
+        const long long m = (long long)times[w.y + q] + d + 1;
         if (m > last_m) continue;
         const double v = li_ring[(size_t)(m & (R - 1)) * stride + j];
         acc = (G)(acc + (G)v);
@@ -182,16 +187,16 @@ hipError_t launch_adj_verify(const int2* spikes, int n, const uint8_t* rec_t, lo
   return hipGetLastError();
 }
 
-hipError_t launch_adj_gather(const int4* items, long long n_items, const int* times, const int64_t* row_ptr,
-                             const int32_t* tgt, const uint8_t* dly, const double* li_ring, long long stride, int R,
-                             long long last_m, void* grad, bool fp32, int grid, hipStream_t s) {
+hipError_t launch_adj_gather(const int4* srcs, const long long* first, int nsrc, long long n_items, const int* times,
+                             const int64_t* row_ptr, const int32_t* tgt, const uint8_t* dly, const double* li_ring,
+                             long long stride, int R, long long last_m, void* grad, bool fp32, int grid, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   if (fp32)
-    hipLaunchKernelGGL(k_adj_gather<float>, dim3(grid), dim3(kAdjBlock), 0, s, items, n_items, times, row_ptr, tgt,
-                       dly, li_ring, stride, R, last_m, (float*)grad);
+    hipLaunchKernelGGL(k_adj_gather<float>, dim3(grid), dim3(kAdjBlock), 0, s, srcs, first, nsrc, n_items, times,
+                       row_ptr, tgt, dly, li_ring, stride, R, last_m, (float*)grad);
   else
-    hipLaunchKernelGGL(k_adj_gather<double>, dim3(grid), dim3(kAdjBlock), 0, s, items, n_items, times, row_ptr, tgt,
-                       dly, li_ring, stride, R, last_m, (double*)grad);
+    hipLaunchKernelGGL(k_adj_gather<double>, dim3(grid), dim3(kAdjBlock), 0, s, srcs, first, nsrc, n_items, times,
+                       row_ptr, tgt, dly, li_ring, stride, R, last_m, (double*)grad);
   return hipGetLastError();
 }
 

@@ -117,6 +117,9 @@ struct mc_net {
   int64_t* d_boff = nullptr;           // [n_pad+1]
   int32_t* d_blk2 = nullptr;
   int own_blocks = 0, own_bmax = 0, own_targets = 0;
+  // input record of an adjoint's forward (owned by that mc_adjoint call)
+  long long* d_xrec = nullptr;
+  long long xrec_step0 = 0, xrec_steps = 0;
   unsigned long long* d_phase = nullptr;
   bool phase_on = false;
   std::vector<double> phase_wg;        // per-workgroup phase times (us/step) of the last mc_profile_phases
@@ -158,6 +161,7 @@ struct mc_net {
     p.raster = d_raster; p.raster_cap = raster_cap; p.raster_cnt = d_raster_cnt;
     p.wg_events = d_wg_events; p.wg_spikes = d_wg_spikes; p.overflow = d_overflow;
     p.n_inst = h.n_inst; p.qinst = d_qinst; p.inst_base = d_inst_base; p.ilist = d_ilist; p.icnt = d_icnt;
+    p.xrec = d_xrec; p.xrec_step0 = xrec_step0; p.xrec_steps = xrec_steps;
     return p;
   }
 
@@ -1152,6 +1156,9 @@ int mc_get_persist_shape(mc_net* n, int32_t* G, int32_t* B, int32_t* DL) {
   return MC_OK;
 }
 
+// Largest input record an adjoint makes by default (8 B per neuron-step).
+constexpr double kRecordBudget = 16.0 * 1024 * 1024 * 1024;
+
 int mc_adjoint(mc_net* n, const mc_adjoint_config* a, void* grad, double* loss) {
   if (!device_ready(n)) return set_error(MC_ERR_STATE, "handle is host-only, failed or NULL");
   if (!a || !grad || !loss) return set_error(MC_ERR_INVALID_ARG, "NULL config, gradient or loss pointer");
@@ -1160,6 +1167,8 @@ int mc_adjoint(mc_net* n, const mc_adjoint_config* a, void* grad, double* loss) 
   if (S < 1 || S > 1000000) return set_error(MC_ERR_INVALID_ARG, "window_steps out of [1, 1e6]");
   if (K < 1 || K > 4096) return set_error(MC_ERR_INVALID_ARG, "ckpt_every out of [1, 4096]");
   if (a->grad_dtype != MC_GRAD_F64 && a->grad_dtype != MC_GRAD_F32) return set_error(MC_ERR_INVALID_ARG, "unknown grad_dtype");
+  if (a->input_mode != MC_ADJ_INPUT_AUTO && a->input_mode != MC_ADJ_INPUT_RECORD && a->input_mode != MC_ADJ_INPUT_REPLAY)
+    return set_error(MC_ERR_INVALID_ARG, "unknown input_mode");
   if (n->step + S > 2147483647LL) return set_error(MC_ERR_RANGE, "step count beyond int32 raster steps");
   const bool fp32 = a->grad_dtype == MC_GRAD_F32;
   const int64_t n0 = n->step;
@@ -1174,23 +1183,41 @@ int mc_adjoint(mc_net* n, const mc_adjoint_config* a, void* grad, double* loss) 
   double *ck_y = nullptr, *ck_I = nullptr;
   int32_t* ck_r = nullptr;
   long long* ck_ring = nullptr;
+  long long* xrec = nullptr;
   const size_t ring_elems = (size_t)kRingSlots * st;
+  const bool record = a->input_mode == MC_ADJ_INPUT_RECORD ||
+                      (a->input_mode == MC_ADJ_INPUT_AUTO && (double)S * (double)st * 8.0 <= kRecordBudget);
   if ((rc = B.alloc(&ck_y, (size_t)nseg * st)) != MC_OK) return rc;
   if ((rc = B.alloc(&ck_I, (size_t)nseg * st)) != MC_OK) return rc;
   if ((rc = B.alloc(&ck_r, (size_t)nseg * st)) != MC_OK) return rc;
-  if ((rc = B.alloc(&ck_ring, (size_t)nseg * ring_elems)) != MC_OK) return rc;
-
-  // forward: checkpoint, then K steps, per segment
-  HIP_TRY(hipEventRecord(n->ev0, n->stream));
-  for (int64_t k = 0; k < nseg; ++k) {
-    const int64_t len = std::min(K, S - k * K);
-    HIP_TRY(hipMemcpyAsync(ck_y + k * st, n->d_y, sizeof(double) * n->n_pad, hipMemcpyDeviceToDevice, n->stream));
-    HIP_TRY(hipMemcpyAsync(ck_I + k * st, n->d_I, sizeof(double) * n->n_pad, hipMemcpyDeviceToDevice, n->stream));
-    HIP_TRY(hipMemcpyAsync(ck_r + k * st, n->d_r, sizeof(int32_t) * n->n_pad, hipMemcpyDeviceToDevice, n->stream));
-    HIP_TRY(hipMemcpyAsync(ck_ring + k * ring_elems, n->d_ring, sizeof(long long) * ring_elems, hipMemcpyDeviceToDevice,
-                           n->stream));
-    if ((rc = enqueue_steps(n, len)) != MC_OK) { n->failed = true; return rc; }
+  if (record) {
+    if ((rc = B.alloc(&xrec, (size_t)S * st)) != MC_OK) return rc;
+  } else {
+    if ((rc = B.alloc(&ck_ring, (size_t)nseg * ring_elems)) != MC_OK) return rc;
   }
+
+  // forward: checkpoint, then K steps, per segment (direct launches: a
+  // captured graph would carry the record-off arguments)
+  HIP_TRY(hipEventRecord(n->ev0, n->stream));
+  const int spg = n->launch.steps_per_graph;
+  if (record) {
+    n->launch.steps_per_graph = 0;
+    n->d_xrec = xrec; n->xrec_step0 = n0; n->xrec_steps = S;
+  }
+  for (int64_t k = 0; k < nseg && rc == MC_OK; ++k) {
+    const int64_t len = std::min(K, S - k * K);
+    hipError_t e = hipMemcpyAsync(ck_y + k * st, n->d_y, sizeof(double) * n->n_pad, hipMemcpyDeviceToDevice, n->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(ck_I + k * st, n->d_I, sizeof(double) * n->n_pad, hipMemcpyDeviceToDevice, n->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(ck_r + k * st, n->d_r, sizeof(int32_t) * n->n_pad, hipMemcpyDeviceToDevice, n->stream);
+    if (e == hipSuccess && !record)
+      e = hipMemcpyAsync(ck_ring + k * ring_elems, n->d_ring, sizeof(long long) * ring_elems, hipMemcpyDeviceToDevice,
+                         n->stream);
+    if (e != hipSuccess) rc = set_error(MC_ERR_HIP, std::string("checkpoint copy: ") + hipGetErrorString(e));
+    else if ((rc = enqueue_steps(n, len)) != MC_OK) n->failed = true;
+  }
+  n->d_xrec = nullptr; n->xrec_step0 = 0; n->xrec_steps = 0;
+  n->launch.steps_per_graph = spg;
+  if (rc != MC_OK) return rc;
   HIP_TRY(hipEventRecord(n->ev_mid, n->stream));
   if ((rc = drain(n)) != MC_OK) return rc;
 
@@ -1208,36 +1235,41 @@ int mc_adjoint(mc_net* n, const mc_adjoint_config* a, void* grad, double* loss) 
   // verify (t in [a, a+len)) and to gather (t in [a-2, a+len-2), t <= n0+S-3)
   std::vector<int2> dl_sp, vf_sp;
   std::vector<long long> dl_first;
-  std::vector<int4> items;
+  std::vector<int4> srcs;               // gather: per source (padded id, first time, time count, -)
+  std::vector<long long> gfirst;        // gather: first chunk of each source, a terminator per segment
   std::vector<int> times;
-  std::vector<size_t> dl_off(nseg + 1), vf_off(nseg + 1), it_off(nseg + 1);
+  std::vector<size_t> dl_off(nseg + 1), vf_off(nseg + 1), it_off(nseg + 1), fc_off(nseg + 1);
   std::vector<unsigned long long> want_count(nseg);
   for (int64_t k = 0; k < nseg; ++k) {
     const int64_t s0 = n0 + k * K, len = std::min(K, S - k * K);
     size_t f, c;
     dl_off[k] = dl_sp.size();
-    spikes_in(s0, s0 + len - 1, &f, &c);
-    long long acc = 0;
-    for (size_t q = f; q < f + c; ++q) {
-      const int64_t dense = n->r_id[q];
-      const int64_t rl = n->h.row_ptr[dense + 1] - n->h.row_ptr[dense];
-      dl_sp.push_back(make_int2(n->r_step[q], (int)n->pad_of(dense)));
-      dl_first.push_back(acc);
-      acc += (rl + kReplayChunkHost - 1) / kReplayChunkHost;
+    if (!record) {
+      spikes_in(s0, s0 + len - 1, &f, &c);
+      long long acc = 0;
+      for (size_t q = f; q < f + c; ++q) {
+        const int64_t dense = n->r_id[q];
+        const int64_t rl = n->h.row_ptr[dense + 1] - n->h.row_ptr[dense];
+        dl_sp.push_back(make_int2(n->r_step[q], (int)n->pad_of(dense)));
+        dl_first.push_back(acc);
+        acc += (rl + kReplayChunkHost - 1) / kReplayChunkHost;
+      }
+      dl_first.push_back(acc);   // one terminator per segment
     }
-    dl_first.push_back(acc);   // one terminator per segment
     vf_off[k] = vf_sp.size();
     spikes_in(s0, s0 + len, &f, &c);
     want_count[k] = c;
     for (size_t q = f; q < f + c; ++q) vf_sp.push_back(make_int2(n->r_step[q], (int)n->pad_of(n->r_id[q])));
-    // gather: group by source, times decreasing
-    it_off[k] = items.size();
+    // gather: group by source, times decreasing; per source its chunk range
+    it_off[k] = srcs.size();
+    fc_off[k] = gfirst.size();
     spikes_in(s0 - 2, std::min(s0 + len - 2, n0 + S - 2), &f, &c);
     std::vector<std::pair<int64_t, int32_t>> by_src(c);
     for (size_t q = 0; q < c; ++q) by_src[q] = {n->r_id[f + q], n->r_step[f + q]};
     std::sort(by_src.begin(), by_src.end(), [](const std::pair<int64_t, int32_t>& x, const std::pair<int64_t, int32_t>& y) {
       return x.first != y.first ? x.first < y.first : x.second > y.second;
     });
+    long long chunks_so_far = 0;
     for (size_t q = 0; q < c;) {
       size_t e = q;
       while (e < c && by_src[e].first == by_src[q].first) ++e;
@@ -1245,17 +1277,20 @@ int mc_adjoint(mc_net* n, const mc_adjoint_config* a, void* grad, double* loss) 
       const int64_t rl = n->h.row_ptr[dense + 1] - n->h.row_ptr[dense];
       const int t0 = (int)times.size();
       for (size_t z = q; z < e; ++z) times.push_back(by_src[z].second);
-      const int64_t chunks = (rl + kGatherChunkHost - 1) / kGatherChunkHost;
-      for (int64_t ch = 0; ch < chunks; ++ch) items.push_back(make_int4((int)n->pad_of(dense), (int)ch, t0, (int)(e - q)));
+      srcs.push_back(make_int4((int)n->pad_of(dense), t0, (int)(e - q), 0));
+      gfirst.push_back(chunks_so_far);
+      chunks_so_far += (rl + kGatherChunkHost - 1) / kGatherChunkHost;
       q = e;
     }
+    gfirst.push_back(chunks_so_far);   // one terminator per segment: its item count
   }
-  dl_off[nseg] = dl_sp.size(); vf_off[nseg] = vf_sp.size(); it_off[nseg] = items.size();
+  dl_off[nseg] = dl_sp.size(); vf_off[nseg] = vf_sp.size(); it_off[nseg] = srcs.size(); fc_off[nseg] = gfirst.size();
 
   // device work lists and reverse-pass buffers
   int2 *d_dl = nullptr, *d_vf = nullptr;
   long long* d_first = nullptr;
-  int4* d_items = nullptr;
+  int4* d_srcs = nullptr;
+  long long* d_gfirst = nullptr;
   int* d_times = nullptr;
   long long* xseg = nullptr;
   double *rec_y = nullptr, *li_ring = nullptr, *carry = nullptr, *loss_part = nullptr;
@@ -1265,9 +1300,10 @@ int mc_adjoint(mc_net* n, const mc_adjoint_config* a, void* grad, double* loss) 
   if ((rc = B.alloc(&d_dl, dl_sp.size())) != MC_OK) return rc;
   if ((rc = B.alloc(&d_vf, vf_sp.size())) != MC_OK) return rc;
   if ((rc = B.alloc(&d_first, dl_first.size())) != MC_OK) return rc;
-  if ((rc = B.alloc(&d_items, items.size())) != MC_OK) return rc;
+  if ((rc = B.alloc(&d_srcs, srcs.size())) != MC_OK) return rc;
+  if ((rc = B.alloc(&d_gfirst, gfirst.size())) != MC_OK) return rc;
   if ((rc = B.alloc(&d_times, times.size())) != MC_OK) return rc;
-  if ((rc = B.alloc(&xseg, (size_t)(Kc + 101) * st)) != MC_OK) return rc;
+  if (!record && (rc = B.alloc(&xseg, (size_t)(Kc + 101) * st)) != MC_OK) return rc;
   if ((rc = B.alloc(&rec_y, (size_t)Kc * st)) != MC_OK) return rc;
   if ((rc = B.alloc(&rec_t, (size_t)Kc * st)) != MC_OK) return rc;
   if ((rc = B.alloc(&li_ring, (size_t)R * st)) != MC_OK) return rc;
@@ -1277,8 +1313,10 @@ int mc_adjoint(mc_net* n, const mc_adjoint_config* a, void* grad, double* loss) 
   loss_part = carry + 2 * st;
   if (!dl_sp.empty()) HIP_TRY(hipMemcpy(d_dl, dl_sp.data(), sizeof(int2) * dl_sp.size(), hipMemcpyHostToDevice));
   if (!vf_sp.empty()) HIP_TRY(hipMemcpy(d_vf, vf_sp.data(), sizeof(int2) * vf_sp.size(), hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(d_first, dl_first.data(), sizeof(long long) * dl_first.size(), hipMemcpyHostToDevice));
-  if (!items.empty()) HIP_TRY(hipMemcpy(d_items, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice));
+  if (!dl_first.empty())
+    HIP_TRY(hipMemcpy(d_first, dl_first.data(), sizeof(long long) * dl_first.size(), hipMemcpyHostToDevice));
+  if (!srcs.empty()) HIP_TRY(hipMemcpy(d_srcs, srcs.data(), sizeof(int4) * srcs.size(), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(d_gfirst, gfirst.data(), sizeof(long long) * gfirst.size(), hipMemcpyHostToDevice));
   if (!times.empty()) HIP_TRY(hipMemcpy(d_times, times.data(), sizeof(int) * times.size(), hipMemcpyHostToDevice));
   HIP_TRY(hipMemsetAsync(carry, 0, sizeof(double) * 3 * st, n->stream));
   HIP_TRY(hipMemsetAsync(seg_count, 0, sizeof(unsigned long long) * nseg, n->stream));
@@ -1294,20 +1332,24 @@ int mc_adjoint(mc_net* n, const mc_adjoint_config* a, void* grad, double* loss) 
   for (int64_t k = 0; k < nseg; ++k) { first_off[k] = dl_first_off; dl_first_off += (dl_off[k + 1] - dl_off[k]) + 1; }
   for (int64_t k = nseg - 1; k >= 0; --k) {
     const int64_t s0 = n0 + k * K, len = std::min(K, S - k * K);
-    HIP_TRY(launch_adj_seed(xseg, ck_ring + k * ring_elems, st, s0, (int)(len + 101), n->stream));
-    const size_t nd = dl_off[k + 1] - dl_off[k];
-    if (nd)
-      HIP_TRY(launch_replay(d_dl + dl_off[k], d_first + first_off[k], (int)nd, dl_first[first_off[k] + nd], n->d_row_ptr,
-                            n->d_tgt, n->d_wq, n->d_dly, xseg, st, s0, grid, n->stream));
+    if (!record) {
+      HIP_TRY(launch_adj_seed(xseg, ck_ring + k * ring_elems, st, s0, (int)(len + 101), n->stream));
+      const size_t nd = dl_off[k + 1] - dl_off[k];
+      if (nd)
+        HIP_TRY(launch_replay(d_dl + dl_off[k], d_first + first_off[k], (int)nd, dl_first[first_off[k] + nd],
+                              n->d_row_ptr, n->d_tgt, n->d_wq, n->d_dly, xseg, st, s0, grid, n->stream));
+    }
     AdjSeg sg{};
     sg.a = s0; sg.len = (int)len; sg.R = R; sg.c = c; sg.ystar = ystar;
     sg.ck_y = ck_y + k * st; sg.ck_I = ck_I + k * st; sg.ck_r = ck_r + k * st;
-    sg.xseg = xseg; sg.rec_y = rec_y; sg.rec_t = rec_t; sg.li_ring = li_ring;
+    sg.xseg = record ? xrec + (size_t)(s0 - n0) * st : xseg;
+    sg.rec_y = rec_y; sg.rec_t = rec_t; sg.li_ring = li_ring;
     sg.carry_ly = carry; sg.carry_li = carry + st; sg.loss_part = loss_part; sg.spike_count = seg_count + k;
     HIP_TRY(launch_adj_segment(p, sg, n->stream));
     HIP_TRY(launch_adj_verify(d_vf + vf_off[k], (int)(vf_off[k + 1] - vf_off[k]), rec_t, st, s0, mismatch, n->stream));
-    HIP_TRY(launch_adj_gather(d_items + it_off[k], (long long)(it_off[k + 1] - it_off[k]), d_times, n->d_row_ptr,
-                              n->d_tgt, n->d_dly, li_ring, st, R, n0 + S - 1, grad, fp32, grid, n->stream));
+    const int nsrc = (int)(it_off[k + 1] - it_off[k]);
+    HIP_TRY(launch_adj_gather(d_srcs + it_off[k], d_gfirst + fc_off[k], nsrc, gfirst[fc_off[k] + nsrc], d_times,
+                              n->d_row_ptr, n->d_tgt, n->d_dly, li_ring, st, R, n0 + S - 1, grad, fp32, grid, n->stream));
   }
   HIP_TRY(hipEventRecord(n->ev1, n->stream));
   HIP_TRY(hipStreamSynchronize(n->stream));

@@ -44,6 +44,12 @@ struct DevNet {
   unsigned long long* wg_events;   // [n_wg]
   unsigned long long* wg_spikes;   // [n_wg * n_pops]
   unsigned* overflow;       // set if a raster segment would overflow
+  // adjoint forward: when xrec is set, the integer synaptic input (ring and
+  // far part, without the drive) of every neuron at step n in [xrec_step0,
+  // xrec_step0 + xrec_steps) goes to xrec[(n - xrec_step0) * ring_stride + i]
+  long long* xrec;
+  long long xrec_step0;
+  long long xrec_steps;
   // target-owner scheme: per-instance spike lists of the current step
   int32_t n_inst;
   const int32_t* qinst;     // [n_quads] instance of each quad
@@ -122,9 +128,9 @@ hipError_t launch_adj_seed(long long* xseg, const long long* ring_ckpt, long lon
 hipError_t launch_adj_segment(const DevNet& p, const AdjSeg& a, hipStream_t s);
 hipError_t launch_adj_verify(const int2* spikes, int n, const uint8_t* rec_t, long long stride, long long a,
                              unsigned* mismatch, hipStream_t s);
-hipError_t launch_adj_gather(const int4* items, long long n_items, const int* times, const int64_t* row_ptr,
-                             const int32_t* tgt, const uint8_t* dly, const double* li_ring, long long stride, int R,
-                             long long last_m, void* grad, bool fp32, int grid, hipStream_t s);
+hipError_t launch_adj_gather(const int4* srcs, const long long* first, int nsrc, long long n_items, const int* times,
+                             const int64_t* row_ptr, const int32_t* tgt, const uint8_t* dly, const double* li_ring,
+                             long long stride, int R, long long last_m, void* grad, bool fp32, int grid, hipStream_t s);
 
 // Target-owner delivery (one kernel per step after the update kernel):
 // block k owns padded targets [bt0[k], bt0[k+1]) of instance binst[k]; it is

@@ -77,6 +77,11 @@ __global__ __launch_bounds__(kMaxBlock) void k_step(DevNet p, int offset, int qp
     *reinterpret_cast<longlong2*>(slot) = make_longlong2(0, 0);
     *reinterpret_cast<longlong2*>(slot + 2) = make_longlong2(0, 0);
     const long long sl[4] = {s01.x, s01.y, s23.x, s23.y};
+    if (p.xrec && n - p.xrec_step0 >= 0 && n - p.xrec_step0 < p.xrec_steps) {
+      long long* xr = p.xrec + (size_t)(n - p.xrec_step0) * p.ring_stride + 4 * q;
+      *reinterpret_cast<longlong2*>(xr) = s01;
+      *reinterpret_cast<longlong2*>(xr + 2) = s23;
+    }
     double* yq = p.y + 4 * q;
     double* Iq = p.I + 4 * q;
     int* rq = p.r + 4 * q;

@@ -28,6 +28,7 @@ MC_MAX_POPS = 16
 RING_SLOTS = 128
 RULE_FIXED_INDEGREE, RULE_BERNOULLI = 0, 1
 GRAD_F64, GRAD_F32 = 0, 1
+ADJ_INPUT_AUTO, ADJ_INPUT_RECORD, ADJ_INPUT_REPLAY = 0, 1, 2
 FLAG_HOST_ONLY = 1
 SCHEME_STEP_KERNELS, SCHEME_PERSISTENT_LDS, SCHEME_TARGET_OWNER = 0, 1, 2
 
@@ -68,7 +69,7 @@ class mc_counters(C.Structure):
 
 class mc_adjoint_config(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("window_steps", C.c_int64), ("ckpt_every", C.c_int64),
-                ("v_target_mV", C.c_double), ("grad_dtype", C.c_int32)]
+                ("v_target_mV", C.c_double), ("grad_dtype", C.c_int32), ("input_mode", C.c_int32)]
 
 
 #: every symbol include/mc.h declares
@@ -222,11 +223,14 @@ class Network:
                "mc_get_spikes")
         return s, i
 
-    def adjoint(self, window: int, ckpt_every: int, v_target: float, fp32: bool, grad_ptr: int) -> float:
+    def adjoint(self, window: int, ckpt_every: int, v_target: float, fp32: bool, grad_ptr: int,
+                input_mode: int = 0) -> float:
+        """mc_adjoint; input_mode: ADJ_INPUT_AUTO, ADJ_INPUT_RECORD or ADJ_INPUT_REPLAY."""
         a = mc_adjoint_config()
         a.struct_size = C.sizeof(mc_adjoint_config)
         a.window_steps, a.ckpt_every, a.v_target_mV = window, ckpt_every, v_target
         a.grad_dtype = GRAD_F32 if fp32 else GRAD_F64
+        a.input_mode = input_mode
         loss = C.c_double()
         _check(lib().mc_adjoint(self.h, C.byref(a), C.c_void_p(grad_ptr), C.byref(loss)), "mc_adjoint")
         return loss.value

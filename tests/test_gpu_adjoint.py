@@ -29,9 +29,9 @@ def arrival_mask(rp, d, rs, ri, n0, S):
     return first[src] + d.astype(np.int64) + 1 <= n0 + S - 1
 
 
-def gpu_adjoint(net, S, K, fp32=False):
+def gpu_adjoint(net, S, K, fp32=False, input_mode=mc.ADJ_INPUT_AUTO):
     g = torch.empty(net.M, dtype=torch.float32 if fp32 else torch.float64, device="cuda")
-    loss = net.adjoint(S, K, V_TARGET, fp32, g.data_ptr())
+    loss = net.adjoint(S, K, V_TARGET, fp32, g.data_ptr(), input_mode)
     return loss, g.cpu().numpy()
 
 
@@ -93,16 +93,19 @@ def test_adjoint_matches_quad_finite_differences(small):
     assert rel.max() <= 1e-9, rel.max()
 
 
+@pytest.mark.parametrize("mode", [mc.ADJ_INPUT_RECORD, mc.ADJ_INPUT_REPLAY])
 @pytest.mark.parametrize("K", [1, 7, 64, 300, 1000])
-def test_adjoint_checkpoint_interval_invariance(small, K):
+def test_adjoint_checkpoint_interval_invariance(small, K, mode):
     """The gradient does not depend on where the checkpoints fall (ragged
-    last segment, K = 1, K beyond the window)."""
+    last segment, K = 1, K beyond the window) nor on how the recompute gets
+    its input (recorded by the forward, or replayed from the checkpointed
+    ring and the recorded spikes)."""
     w = small[0]
     S = 300
     ref = oracle.Oracle(w.to_dict())
     rl, rg = ref.adjoint(S, Y_STAR)
     net = mc.Network(w)
-    gl, gg = gpu_adjoint(net, S, K)
+    gl, gg = gpu_adjoint(net, S, K, input_mode=mode)
     assert np.array_equal(gg.view(np.uint64), rg.view(np.uint64))
     assert abs(gl - rl) <= 1e-12 * abs(rl)
 
@@ -187,9 +190,9 @@ def test_set_weights_reaches_every_delivery_path():
 def test_adjoint_rejects_bad_arguments(small):
     net = mc.Network(small[0])
     g = torch.empty(net.M, dtype=torch.float64, device="cuda")
-    for S, K in ((0, 10), (10, 0), (10, 5000)):
+    for S, K, mode in ((0, 10, 0), (10, 0, 0), (10, 5000, 0), (10, 5, 3)):
         with pytest.raises(mc.MCError) as e:
-            net.adjoint(S, K, V_TARGET, False, g.data_ptr())
+            net.adjoint(S, K, V_TARGET, False, g.data_ptr(), mode)
         assert e.value.code == mc.MC_ERR_INVALID_ARG
     with pytest.raises(mc.MCError):
         net.adjoint(10, 5, V_TARGET, False, 0)
@@ -206,6 +209,9 @@ def test_adjoint_full_scale_fp32():
     S, K = w.adj_window, w.adj_ckpt_every
     net = mc.Network(w)
     gl, gg = gpu_adjoint(net, S, K, fp32=True)
+    _, gg_replay = gpu_adjoint(mc.Network(w), S, K, fp32=True, input_mode=mc.ADJ_INPUT_REPLAY)
+    assert np.array_equal(gg.view(np.uint32), gg_replay.view(np.uint32))
+    del gg_replay
     o = oracle.Oracle(w.to_dict())
     ol, og32 = o.adjoint(S, Y_STAR, fp32=True)
     assert abs(gl - ol) <= 1e-12 * abs(ol)

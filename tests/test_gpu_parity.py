@@ -231,3 +231,21 @@ def test_delivery_replay_matches_independent_sum():
     assert ev == events > 0
     assert np.array_equal(ring, expect)
     assert ms > 0
+
+
+def test_autotuner_and_phase_profile_keep_the_trajectory():
+    """mc_tune times candidate launches on copies of the state and restores
+    it; mc_profile_phases simulates exactly as mc_simulate does.  Both leave
+    the trajectory bit-identical to the oracle's."""
+    w = workloads.balanced()
+    net, o = mc.Network(w), oracle.Oracle(w.to_dict())
+    net.simulate(300)
+    best = net.tune(150)
+    assert net.counters()["step"] == 300
+    net.simulate(400)
+    net.set_launch(scheme=1, block=512, neurons_per_wg=0, steps_per_graph=100)
+    ph = net.profile_phases(300)
+    assert ph["total"] > 0 and net.phase_table().shape == (net.persist_shape()["workgroups"], 8)
+    net.simulate(200)
+    o.run(1200)
+    assert_same(net, o, what=f"tuned {best}")

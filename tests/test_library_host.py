@@ -99,3 +99,12 @@ def test_null_arguments():
     assert L.mc_build_network(None, C.byref(h)) == -1
     assert L.mc_simulate(None, 1) == -5
     assert L.mc_strerror(-8) == b"recomputation did not reproduce the recorded spikes"
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py runs on one GPU only and says so for --gpus N > 1."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
