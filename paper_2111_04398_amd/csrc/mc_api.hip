@@ -341,12 +341,16 @@ int persist_shape(mc_net* n, const mc_launch& l, int* G, int* B, int* DL, std::v
   const int g = (int)((P + b - 1) / b);
   bs.assign((size_t)g + 1, 0);
   for (int k = 0; k <= g; ++k) bs[k] = (int)std::min<int64_t>((int64_t)k * b, P);
-  if (g > l.block) return set_error(MC_ERR_RANGE, "persistent scheme needs workgroups <= threads per workgroup");
+  if (g > 2 * l.block || g > kPersistMaxBlock)
+    return set_error(MC_ERR_RANGE, "persistent scheme needs workgroups <= 2 x threads per workgroup and <= 512");
   size_t stat = 0;
   HIP_TRY(persist_static_lds(&stat));
   const size_t base = persist_lds_bytes(g, b, 0);
-  if (stat + base + 2 * (size_t)b * 8 > (size_t)n->lds_max) return set_error(MC_ERR_RANGE, "LDS too small for the persistent scheme");
-  const int dl = (int)std::min<size_t>(101, (n->lds_max - stat - base) / ((size_t)b * 8));
+  // workgroups that must share a compute unit divide its LDS
+  const int per_cu = (g + n->n_cu - 1) / n->n_cu;
+  const size_t budget = (size_t)n->lds_max / per_cu;
+  if (stat + base + 2 * (size_t)b * 8 > budget) return set_error(MC_ERR_RANGE, "LDS too small for the persistent scheme");
+  const int dl = (int)std::min<size_t>(101, (budget - stat - base) / ((size_t)b * 8));
   const size_t lds = persist_lds_bytes(g, b, dl);
   HIP_TRY(persist_set_lds_limit(lds));
   int occ = 0;

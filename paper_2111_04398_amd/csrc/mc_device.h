@@ -64,7 +64,7 @@ namespace mc {
 
 // Arguments of the persistent LDS kernel (target-owner delivery).
 struct PersistArgs {
-  int G;                       // workgroups (all co-resident, G <= block)
+  int G;                       // workgroups (all co-resident, G <= 2 * block, G <= 512)
   int B;                       // most target neurons of one workgroup (multiple of 4, <= kPersistMaxB)
   const int* bstart;           // [G+1] workgroup g owns padded targets [bstart[g], bstart[g+1]) (multiples of 4)
   int DL;                      // near slots held in LDS (2..101)

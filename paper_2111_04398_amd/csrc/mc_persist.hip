@@ -473,10 +473,13 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
     }
     __syncthreads();                       // s_cnt and the inline ids complete
     int S;
-    const int cnt_h = (tid < a.G) ? s_cnt[tid] : 0;
-    const int pre_h = block_exscan(cnt_h, s_tmp[1], &S);   // also a barrier
+    // thread t sums producers 2t and 2t+1 (G <= 2 * threads)
+    const int c0 = (2 * tid < a.G) ? s_cnt[2 * tid] : 0;
+    const int c1 = (2 * tid + 1 < a.G) ? s_cnt[2 * tid + 1] : 0;
+    const int pre_h = block_exscan(c0 + c1, s_tmp[1], &S);   // also a barrier
     if (s_abort) break;
-    if (tid < a.G) s_pre[tid] = pre_h;
+    if (2 * tid < a.G) s_pre[2 * tid] = pre_h;
+    if (2 * tid + 1 < a.G) s_pre[2 * tid + 1] = pre_h + c0;
     if (tid == 0) s_pre[a.G] = S;
     __syncthreads();
     if (timing) { const long long t = wall_clock64(); ph[2] += t - tp0; tp0 = t; }
