@@ -247,18 +247,44 @@ int drain(mc_net* n) {
   if (ovf) { n->failed = true; return set_error(MC_ERR_STATE, "raster segment overflow (internal capacity error)"); }
   std::vector<long long> cnt((size_t)n->n_wg);
   HIP_TRY(hipMemcpy(cnt.data(), n->d_raster_cnt, sizeof(long long) * n->n_wg, hipMemcpyDeviceToHost));
-  std::vector<int2> buf;
-  for (int g = 0; g < n->n_wg; ++g) {
-    if (cnt[g] == 0) continue;
-    const size_t old = buf.size();
-    buf.resize(old + (size_t)cnt[g]);
-    HIP_TRY(hipMemcpy(buf.data() + old, n->d_raster + (size_t)g * n->raster_cap, sizeof(int2) * cnt[g], hipMemcpyDeviceToHost));
+  long long mx = 0, total = 0;
+  for (long long c : cnt) { mx = std::max(mx, c); total += c; }
+  // the segments' used prefixes: one strided copy when that moves at most
+  // about twice the spikes, else one copy per segment
+  std::vector<int2> buf((size_t)total);
+  std::vector<size_t> seg_off((size_t)n->n_wg + 1, 0);
+  for (int g = 0; g < n->n_wg; ++g) seg_off[g + 1] = seg_off[g] + (size_t)cnt[g];
+  if (total > 0 && (double)mx * n->n_wg <= 2.0 * (double)total + 65536.0) {
+    std::vector<int2> rows((size_t)mx * n->n_wg);
+    HIP_TRY(hipMemcpy2D(rows.data(), sizeof(int2) * mx, n->d_raster, sizeof(int2) * n->raster_cap, sizeof(int2) * mx,
+                        n->n_wg, hipMemcpyDeviceToHost));
+    for (int g = 0; g < n->n_wg; ++g)
+      std::copy(rows.begin() + (size_t)g * mx, rows.begin() + (size_t)g * mx + cnt[g], buf.begin() + seg_off[g]);
+  } else {
+    for (int g = 0; g < n->n_wg; ++g)
+      if (cnt[g])
+        HIP_TRY(hipMemcpy(buf.data() + seg_off[g], n->d_raster + (size_t)g * n->raster_cap, sizeof(int2) * cnt[g],
+                          hipMemcpyDeviceToHost));
   }
-  for (auto& e : buf) e.y = (int)n->dense_of(e.y);
-  std::sort(buf.begin(), buf.end(), [](const int2& a, const int2& b) { return a.x != b.x ? a.x < b.x : a.y < b.y; });
-  n->r_step.reserve(n->r_step.size() + buf.size());
-  n->r_id.reserve(n->r_id.size() + buf.size());
-  for (auto& e : buf) { n->r_step.push_back(e.x); n->r_id.push_back(e.y); }
+  // Workgroup g's segment holds its own neurons, whose ids all exceed those
+  // of workgroups < g, by step and ascending id within a step; a stable
+  // counting sort by step over the segments in order is therefore the sort
+  // by (step, id).
+  if (total > 0) {
+    int smin = buf[0].x, smax = buf[0].x;
+    for (const int2& e : buf) { smin = std::min(smin, e.x); smax = std::max(smax, e.x); }
+    std::vector<size_t> pos((size_t)(smax - smin) + 2, 0);
+    for (const int2& e : buf) ++pos[(size_t)(e.x - smin) + 1];
+    for (size_t k = 1; k < pos.size(); ++k) pos[k] += pos[k - 1];
+    const size_t base = n->r_step.size();
+    n->r_step.resize(base + (size_t)total);
+    n->r_id.resize(base + (size_t)total);
+    for (const int2& e : buf) {
+      const size_t k = base + pos[(size_t)(e.x - smin)]++;
+      n->r_step[k] = e.x;
+      n->r_id[k] = (int32_t)n->dense_of(e.y);
+    }
+  }
   HIP_TRY(hipMemsetAsync(n->d_raster_cnt, 0, sizeof(long long) * n->n_wg, n->stream));
   HIP_TRY(hipStreamSynchronize(n->stream));
   n->steps_since_drain = 0;
