@@ -11,8 +11,10 @@ RTF = T_wall / T_model.  Inputs are synthetic (the paper's connectivity table
 and initial conditions are not published in it).
 
 Workloads (`--workload`):
-  microcircuit  (default) the line above, plus the delivery replay, the
-                full-scale adjoint cost per step and the CPU oracle baseline;
+  microcircuit  (default) the line above, plus the energy per synaptic event
+                (GPU package energy over ~12 s of further simulation), the
+                delivery replay, the full-scale adjoint cost per step and the
+                CPU oracle baseline;
   balanced      the 5,000-neuron balanced random network, same protocol;
   batched       64 microcircuit instances of scale 0.05-0.25 in one network,
                 2 s of model time each, against 64 sequential plain runs;
@@ -82,6 +84,132 @@ class DeviceBuffer:
             self.ptr = C.c_void_p()
 
 
+class EnergyMeter:
+    """Energy of the GPU package the library runs on (compute dies, I/O dies
+    and HBM), from the amdsmi energy accumulator.  The accumulator advances
+    about once per second with a timestamp of its own, so a sampling thread
+    records its updates and a window's power is taken over the whole update
+    intervals inside it.  The paper's energy per synaptic event is the energy
+    of the simulation phase over its synaptic events; it is reported here both
+    whole and above the idle power measured just before (the paper quotes its
+    node's power above a baseline).  Unavailable counters leave `error` set."""
+
+    def __init__(self):
+        self.h = None
+        self.error = None
+        self.samples = []            # (host s when first seen, joules, counter ns)
+        self._stop = None
+        try:
+            import amdsmi
+            self.smi = amdsmi
+            hip = C.CDLL("libamdhip64.so.7")
+            buf = C.create_string_buffer(64)
+            dev = C.c_int()
+            if hip.hipGetDevice(C.byref(dev)) != 0 or hip.hipDeviceGetPCIBusId(buf, 64, dev.value) != 0:
+                raise RuntimeError("no HIP device")
+            bdf = buf.value.decode().lower()
+            amdsmi.amdsmi_init()
+            handles = amdsmi.amdsmi_get_processor_handles()
+            for h in handles:
+                if amdsmi.amdsmi_get_gpu_device_bdf(h).lower() == bdf:
+                    self.h = h
+            if self.h is None:
+                raise RuntimeError(f"device {bdf} not among the {len(handles)} amdsmi processors")
+            self._read()
+        except Exception as e:   # no counters on this machine: the benchmark runs without them
+            self.h = None
+            self.error = f"{type(e).__name__}: {e}"
+
+    def _read(self):
+        e = self.smi.amdsmi_get_energy_count(self.h)
+        return e["energy_accumulator"] * e["counter_resolution"] * 1e-6, e["timestamp"]
+
+    def start(self, period_s: float = 0.005):
+        import threading
+        self._stop = threading.Event()
+
+        def run():
+            while not self._stop.is_set():
+                j, ts = self._read()
+                self.add(time.perf_counter(), j, ts)
+                time.sleep(period_s)
+
+        self._thread = threading.Thread(target=run, daemon=True)
+        self._thread.start()
+
+    def add(self, t: float, joules: float, ts: int):
+        """Keeps a reading if it is the first or advances the last kept one
+        (a rare read returns an unrelated timestamp); repeats are dropped."""
+        if self.samples:
+            _, j0, ts0 = self.samples[-1]
+            if not (ts0 < ts < ts0 + 5_000_000_000 and joules >= j0):
+                return
+        self.samples.append((t, joules, ts))
+
+    def stop(self):
+        if self._stop is not None:
+            self._stop.set()
+            self._thread.join()
+            self._stop = None
+
+    def power(self, t0: float, t1: float, slack: float = 0.01):
+        """Mean watts over the accumulator intervals that lie inside host
+        times [t0, t1], and the seconds they cover (None if none does)."""
+        u = self.samples
+        joules = ns = 0
+        for a, b in zip(u, u[1:]):
+            if a[0] - slack >= t0 and b[0] <= t1:
+                joules += b[1] - a[1]
+                ns += b[2] - a[2]
+        return (joules / (ns * 1e-9), ns * 1e-9) if ns > 0 else (None, 0.0)
+
+
+def energy_run(net, meter, wall_s_target: float, ms_per_step: float, idle_s: float = 3.2) -> dict:
+    """Idle window, then enough steps for about `wall_s_target` seconds; the
+    package power of each and the energy per synaptic event of the run."""
+    if meter is None or meter.h is None:
+        return {"available": False, "error": meter.error if meter else "disabled"}
+    steps = max(1000, int(wall_s_target / (ms_per_step * 1e-3)))
+    # room for the whole run's raster, so that no drain pauses it (the bound
+    # is a worst case: one spike per refractory period per neuron)
+    from paper_2111_04398_amd.mc import MCError
+    while True:
+        try:
+            net.reserve(steps)
+            break
+        except MCError:
+            if steps <= 20000:
+                raise
+            steps //= 2
+    meter.start()
+    try:
+        net.counters()                                  # synchronizes
+        i0 = time.perf_counter()
+        time.sleep(idle_s)
+        i1 = time.perf_counter()
+        c0 = net.counters()
+        t0 = time.perf_counter()
+        net.simulate(steps)
+        gpu_ms = net.last_simulate_ms()                 # waits for the steps
+        t1 = time.perf_counter()
+        c1 = net.counters()
+    finally:
+        meter.stop()
+    p_idle, s_idle = meter.power(i0, i1)
+    p_run, s_run = meter.power(t0, t1)
+    events = c1["events"] - c0["events"]
+    rate = events / (gpu_ms * 1e-3)
+    out = {"available": p_run is not None, "source": "amdsmi package energy accumulator (1 Hz updates)",
+           "steps": steps, "model_s": steps * H_MS * 1e-3, "wall_s": gpu_ms * 1e-3, "events_per_s": rate,
+           "power_w": p_run, "seconds_measured": s_run, "idle_power_w": p_idle, "idle_seconds_measured": s_idle,
+           "paper_uj_per_synaptic_event": {"128_threads_1_node": 0.33, "256_threads_2_nodes": 0.48}}
+    if p_run is not None:
+        out["uj_per_synaptic_event"] = p_run / rate * 1e6
+        if p_idle is not None:
+            out["uj_per_synaptic_event_above_idle"] = (p_run - p_idle) / rate * 1e6
+    return out
+
+
 def cpu_baseline(workload, presim: int, steps: int) -> dict:
     """The CPU oracle as it stands, on this host's cores, over a bounded
     sample of the same workload: `presim` untimed steps, then `steps` timed."""
@@ -116,7 +244,7 @@ def timed_run(net, steps: int, warmup: int, launch: str, tune_steps: int):
     c0 = net.counters()                       # synchronizes
     t0 = time.perf_counter()
     net.simulate(steps)
-    gpu_ms = net.last_simulate_ms()           # HIP events on the simulation stream
+    gpu_ms = net.last_simulate_ms()           # HIP events on the simulation stream (waits for them)
     host_s = time.perf_counter() - t0
     c1 = net.counters()
     return gpu_ms, c1["events"] - c0["events"], c1["spikes"] - c0["spikes"], host_s, tuned
@@ -195,6 +323,8 @@ def run_plain(args, mc, w) -> dict:
         },
         "paper_context": {"rtf_2x64_core_epyc_node": 0.67, "rtf_2_nodes": 0.53},
     }
+    if args.energy_wall > 0:
+        out["energy"] = energy_run(net, EnergyMeter(), args.energy_wall, gpu_ms / steps)
     # throughput form of the delivery: recorded spikes of replay-steps steps in one launch
     rs = min(args.replay_steps, steps)
     if rs > 0:
@@ -227,6 +357,7 @@ def run_batched(args, mc, w) -> dict:
     gpu_ms, events, spikes, host_s, tuned = timed_run(net, steps, args.warmup, args.launch, args.tune_steps)
     launch = net.get_launch()
     N, M, n_inst = net.N, net.M, net.n_instances
+    energy = energy_run(net, EnergyMeter(), args.energy_wall, gpu_ms / steps) if args.energy_wall > 0 else None
     net.close()
     seq_ms, seq_events, seq_launch = 0.0, 0, {}
     n_seq = n_inst if args.seq_instances <= 0 else min(args.seq_instances, n_inst)
@@ -257,6 +388,7 @@ def run_batched(args, mc, w) -> dict:
                        "launches": seq_launch},
         "speedup_vs_sequential": (seq_ms_all * 1e-3) / wall_s,
         "atomics_per_s": events / wall_s,
+        "energy": energy,
     }
 
 
@@ -321,6 +453,9 @@ def main() -> int:
     ap.add_argument("--workload", default="microcircuit",
                     choices=["microcircuit", "balanced", "batched", "adjoint_small", "adjoint_full"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--energy-wall", type=float, default=12.0, metavar="S",
+                    help="after timing: idle power, then about S seconds of simulation under the package "
+                         "energy counter for the energy per synaptic event (0: skip)")
     ap.add_argument("--cpu-steps", type=int, default=15000)
     ap.add_argument("--launch", default="", help="scheme,block,neurons_per_wg,steps_per_graph (default: autotuned)")
     ap.add_argument("--tune-steps", type=int, default=2000, help="steps per autotuner candidate")

@@ -108,3 +108,24 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
                        timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_energy_meter_windows():
+    """The package energy accumulator advances about once per second: power
+    over a window is taken over the whole update intervals inside it, and a
+    stray reading (timestamp out of order) or a repeat is ignored."""
+    import bench
+    m = bench.EnergyMeter.__new__(bench.EnergyMeter)
+    m.samples = []
+    s = 1_000_000_000
+    # (host s, joules, counter ns): 300 W idle for 3 s, then 550 W
+    for t, j, ts in [(0.0, 0.0, 10 * s), (0.5, 0.0, 10 * s), (1.0, 300.0, 11 * s), (1.4, 1e9, 3 * s),
+                     (2.0, 600.0, 12 * s), (3.0, 900.0, 13 * s), (4.0, 1450.0, 14 * s), (5.0, 2000.0, 15 * s),
+                     (6.0, 2550.0, 16 * s)]:
+        m.add(t, j, ts)
+    assert [x[0] for x in m.samples] == [0.0, 1.0, 2.0, 3.0, 4.0, 5.0, 6.0]
+    p, secs = m.power(-0.1, 3.0)
+    assert p == 300.0 and secs == 3.0
+    p, secs = m.power(3.2, 6.0)            # the interval (3, 4] starts before the window
+    assert p == 550.0 and secs == 2.0
+    assert m.power(3.2, 3.9) == (None, 0.0)
