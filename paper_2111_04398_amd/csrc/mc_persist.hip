@@ -23,15 +23,18 @@
 // block bounds blk[i][g] of step n's spikes are loaded, in step n+2 their
 // entries (delay >= 3, landing at step n+3 or later) are added.
 //
-// Spike exchange: workgroup g publishes a 64-byte record per step (two
-// records per workgroup, alternating by step parity, so a record is never
-// rewritten while a slower consumer may still be reading it): word 0 =
-// (tag << 32) | count, words 1..7 = (tag << 32) | id of its first seven
-// spikes, tag = step + 1.  Every word carries the tag, so a consumer accepts
-// a record when all the words it needs show the current tag, whatever order
-// the stores became visible in.  Spikes beyond the seventh are written to a
-// side array before word 0 (with a wait for their completion), so they are
-// visible once word 0 is.  All of these are device-scope atomic accesses
+// Spike exchange: workgroup g publishes a record per step (two records per
+// workgroup, alternating by step parity, so a record is never rewritten while
+// a slower consumer may still be reading it).  Word 0 = tag16 << 48 | count
+// << 36 | the block-local indices (9 bits each) of the first four spikes,
+// with tag16 = (step + 1) mod 65535 + 1 (never 0, distinct for consecutive
+// steps); words 1..3 = (step + 1) << 32 | id of spikes 5..7.  About four in
+// five workgroups publish no spike in a step and nearly all others at most
+// four, so one load of word 0 usually completes a record.  Every word carries
+// a tag, so a consumer accepts a record when all the words it needs show the
+// current step, whatever order the stores became visible in.  Spikes beyond
+// the seventh are written to a side array before word 0 (with a wait for
+// their completion), so they are visible once word 0 is.  All of these are device-scope atomic accesses
 // (coherent at the memory side), so the step needs no L2 writeback or
 // invalidate.  Every wait is bounded; on timeout the kernel sets an error bit
 // and every workgroup leaves the loop.
@@ -44,8 +47,8 @@ namespace mc {
 namespace {
 
 constexpr int kListCap = 1024;       // spikes of one step kept in LDS (more: delivered at once)
-constexpr int kRecWords = 8;         // record words (64 bytes)
-constexpr int kInline = kRecWords - 1;
+constexpr int kInline = 7;           // spike ids carried by a record (more: side array)
+constexpr int kW0Ids = 4;            // of which in word 0 (9-bit block-local indices)
 constexpr int kUnroll = 4;           // entries in flight per lane
 constexpr int kPollPerLane = kPersistMaxBlock / 64;   // producers polled by one lane (G <= block <= 512)
 constexpr int kNearUnroll = 12;      // near-table rows in flight per wavefront (one round for <= 12 spikes per wave)
@@ -296,6 +299,13 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
     y = p.y[j0 + tid]; I = p.I[j0 + tid]; r = p.r[j0 + tid];
     if (steps > 0) kdrive = (int)((drive_counts(n0, qlocal, seed, qpops, s_table) >> (8 * qk)) & 0xFFu);
   }
+  // first owned target of each producer this lane polls (word 0 carries block-local indices)
+  int pbs[kPollPerLane];
+#pragma unroll
+  for (int r = 0; r < kPollPerLane; ++r) {
+    const int h = (tid & 63) + 64 * r;
+    pbs[r] = (h < a.G) ? a.bstart[h] : 0;
+  }
   long long rcnt = p.raster_cnt[g];
   long long ph[7] = {0, 0, 0, 0, 0, 0, 0};
   int S1 = 0;                           // spikes of step n-1: ids kept, block bounds due
@@ -359,6 +369,7 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
     if (spiked) s_local[pre] = (int)(j0 + tid);
     __syncthreads();
     const unsigned long long tag = (unsigned long long)(n + 1) << 32;
+    const unsigned long long tag16 = (unsigned long long)((n + 1) % 65535 + 1) << 48;
     unsigned long long* myrec = a.flags + ((size_t)g * 2 + par) * kPersistFlagStride;   // double-buffered by parity
     for (int k = tid; k < nloc; k += nthr) {
       const int id = s_local[k];
@@ -369,8 +380,12 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
       __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
     }
-    if (tid < min(nloc, kInline)) st_dev(&myrec[1 + tid], tag | (unsigned)s_local[tid]);
-    if (tid == 0) st_dev(&myrec[0], tag | (unsigned)nloc);
+    if (tid >= kW0Ids && tid < min(nloc, kInline)) st_dev(&myrec[1 + tid - kW0Ids], tag | (unsigned)s_local[tid]);
+    if (tid == 0) {
+      unsigned long long w = tag16 | (unsigned long long)nloc << 36;
+      for (int k = 0; k < min(nloc, kW0Ids); ++k) w |= (unsigned long long)(s_local[k] - j0) << (9 * k);
+      st_dev(&myrec[0], w);
+    }
     if (rcnt + nloc <= p.raster_cap) rcnt += nloc;
     else if (tid == 0) atomicOr(p.overflow, 1u);
     if (timing) { const long long t = wall_clock64(); ph[1] += t - tp0; tp0 = t; }
@@ -394,27 +409,29 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
           w0[r] = ((todo >> r) & 1u) ? ld_dev(&a.flags[((size_t)(lane + 64 * r) * 2 + par) * kPersistFlagStride]) : 0ull;
 #pragma unroll
         for (int r = 0; r < kPollPerLane; ++r) {
-          if (!((todo >> r) & 1u) || (w0[r] & 0xFFFFFFFF00000000ull) != tag) continue;
+          if (!((todo >> r) & 1u) || (w0[r] & 0xFFFF000000000000ull) != tag16) continue;
           const int h = lane + 64 * r;
-          const int c = (int)(w0[r] & 0xFFFFFFFFu);
-          const unsigned long long* rec = a.flags + ((size_t)h * 2 + par) * kPersistFlagStride;
-          // all id words in one round trip (independent loads), then the tags
-          unsigned long long wk[kInline];
-          if (c > 0) {
-#pragma unroll
-            for (int k = 0; k < kInline; ++k) wk[k] = ld_dev(&rec[1 + k]);
-          }
+          const int c = (int)((w0[r] >> 36) & 0x3FFu);
+          // ids 5..7 (one round trip for the three words, then their tags)
+          unsigned long long wk[kInline - kW0Ids];
           bool ok = true;
-          int ids[kInline];
+          if (c > kW0Ids) {
+            const unsigned long long* rec = a.flags + ((size_t)h * 2 + par) * kPersistFlagStride;
 #pragma unroll
-          for (int k = 0; k < kInline; ++k) {
-            ids[k] = (int)(wk[k] & 0xFFFFFFFFu);
-            if (k < c) ok &= ((wk[k] & 0xFFFFFFFF00000000ull) == tag);
+            for (int k = 0; k < kInline - kW0Ids; ++k) wk[k] = ld_dev(&rec[1 + k]);
+#pragma unroll
+            for (int k = 0; k < kInline - kW0Ids; ++k)
+              if (kW0Ids + k < c) ok &= ((wk[k] & 0xFFFFFFFF00000000ull) == tag);
           }
           if (!ok) continue;
 #pragma unroll
-          for (int k = 0; k < kInline; ++k)
-            if (k < c) s_inl[h * kInline + k] = ids[k];
+          for (int k = 0; k < kW0Ids; ++k)
+            if (k < c) s_inl[h * kInline + k] = pbs[r] + (int)((w0[r] >> (9 * k)) & 0x1FFu);
+          if (c > kW0Ids) {
+#pragma unroll
+            for (int k = 0; k < kInline - kW0Ids; ++k)
+              if (kW0Ids + k < c) s_inl[h * kInline + kW0Ids + k] = (int)(wk[k] & 0xFFFFFFFFu);
+          }
           s_cnt[h] = c;
           todo &= ~(1u << r);
         }
