@@ -146,6 +146,13 @@ struct mc_net {
   hipGraphExec_t graph = nullptr;
   int graph_steps = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_mid = nullptr;
+  hipStream_t aux = nullptr;           // read-back of the raster beside the simulation stream
+  int2* d_pack = nullptr;              // raster prefixes packed for one read-back
+  int64_t pack_cap = 0;
+  long long* d_pack_off = nullptr;     // [n_wg+1]
+  int64_t pack_off_cap = 0;
+  void* h_stage = nullptr;             // pinned staging of the adjoint's work lists
+  size_t stage_bytes = 0;
   double last_ms = 0.0;
   double adj_forward_ms = 0.0, adj_reverse_ms = 0.0;
 
@@ -228,6 +235,10 @@ void release_all(mc_net* n) {
   if (n->ev0) { (void)hipEventDestroy(n->ev0); n->ev0 = nullptr; }
   if (n->ev1) { (void)hipEventDestroy(n->ev1); n->ev1 = nullptr; }
   if (n->ev_mid) { (void)hipEventDestroy(n->ev_mid); n->ev_mid = nullptr; }
+  dev_free(n->d_pack); dev_free(n->d_pack_off);
+  n->pack_cap = 0; n->pack_off_cap = 0;
+  if (n->h_stage) { (void)hipHostFree(n->h_stage); n->h_stage = nullptr; n->stage_bytes = 0; }
+  if (n->aux) { (void)hipStreamDestroy(n->aux); n->aux = nullptr; }
   if (n->own_stream && n->stream) { (void)hipStreamDestroy(n->stream); n->stream = nullptr; }
 }
 
@@ -238,34 +249,45 @@ int64_t spike_bound(int64_t neurons, int64_t steps, int ref) {
 }
 
 // Copies the private raster segments to the host list (sorted by step, id)
-// and empties them.  Synchronizes the stream.
-int drain(mc_net* n) {
+// and empties them.  Waits for `upto` (an event on the simulation stream) if
+// given, else for the whole simulation stream; the read-back itself runs on
+// the second stream, so work queued after `upto` keeps running.
+int drain(mc_net* n, hipEvent_t upto = nullptr) {
   if (!n->d_raster) return MC_OK;
-  HIP_TRY(hipStreamSynchronize(n->stream));
+  if (upto) HIP_TRY(hipEventSynchronize(upto));
+  else HIP_TRY(hipStreamSynchronize(n->stream));
+  hipStream_t s = n->aux;
   unsigned ovf = 0;
-  HIP_TRY(hipMemcpy(&ovf, n->d_overflow, sizeof(unsigned), hipMemcpyDeviceToHost));
-  if (ovf) { n->failed = true; return set_error(MC_ERR_STATE, "raster segment overflow (internal capacity error)"); }
   std::vector<long long> cnt((size_t)n->n_wg);
-  HIP_TRY(hipMemcpy(cnt.data(), n->d_raster_cnt, sizeof(long long) * n->n_wg, hipMemcpyDeviceToHost));
-  long long mx = 0, total = 0;
-  for (long long c : cnt) { mx = std::max(mx, c); total += c; }
-  // the segments' used prefixes: one strided copy when that moves at most
-  // about twice the spikes, else one copy per segment
+  HIP_TRY(hipMemcpyAsync(&ovf, n->d_overflow, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(cnt.data(), n->d_raster_cnt, sizeof(long long) * n->n_wg, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (ovf) { n->failed = true; return set_error(MC_ERR_STATE, "raster segment overflow (internal capacity error)"); }
+  std::vector<long long> seg_off((size_t)n->n_wg + 1, 0);
+  for (int g = 0; g < n->n_wg; ++g) seg_off[g + 1] = seg_off[g] + cnt[g];
+  const long long total = seg_off[n->n_wg];
   std::vector<int2> buf((size_t)total);
-  std::vector<size_t> seg_off((size_t)n->n_wg + 1, 0);
-  for (int g = 0; g < n->n_wg; ++g) seg_off[g + 1] = seg_off[g] + (size_t)cnt[g];
-  if (total > 0 && (double)mx * n->n_wg <= 2.0 * (double)total + 65536.0) {
-    std::vector<int2> rows((size_t)mx * n->n_wg);
-    HIP_TRY(hipMemcpy2D(rows.data(), sizeof(int2) * mx, n->d_raster, sizeof(int2) * n->raster_cap, sizeof(int2) * mx,
-                        n->n_wg, hipMemcpyDeviceToHost));
-    for (int g = 0; g < n->n_wg; ++g)
-      std::copy(rows.begin() + (size_t)g * mx, rows.begin() + (size_t)g * mx + cnt[g], buf.begin() + seg_off[g]);
-  } else {
-    for (int g = 0; g < n->n_wg; ++g)
-      if (cnt[g])
-        HIP_TRY(hipMemcpy(buf.data() + seg_off[g], n->d_raster + (size_t)g * n->raster_cap, sizeof(int2) * cnt[g],
-                          hipMemcpyDeviceToHost));
+  if (total > 0) {
+    // the used prefixes packed on the device, then one copy
+    int rc;
+    if (n->pack_off_cap < n->n_wg + 1) {
+      dev_free(n->d_pack_off);
+      n->pack_off_cap = 0;
+      if ((rc = dev_alloc(&n->d_pack_off, (size_t)n->n_wg + 1)) != MC_OK) return rc;
+      n->pack_off_cap = n->n_wg + 1;
+    }
+    if (n->pack_cap < total) {
+      dev_free(n->d_pack);
+      n->pack_cap = 0;
+      if ((rc = dev_alloc(&n->d_pack, (size_t)total)) != MC_OK) return rc;
+      n->pack_cap = total;
+    }
+    HIP_TRY(hipMemcpyAsync(n->d_pack_off, seg_off.data(), sizeof(long long) * (n->n_wg + 1), hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_raster_pack(n->d_raster, n->raster_cap, n->d_pack_off, n->n_wg, n->d_pack, s));
+    HIP_TRY(hipMemcpyAsync(buf.data(), n->d_pack, sizeof(int2) * total, hipMemcpyDeviceToHost, s));
   }
+  HIP_TRY(hipMemsetAsync(n->d_raster_cnt, 0, sizeof(long long) * n->n_wg, s));
+  HIP_TRY(hipStreamSynchronize(s));
   // Workgroup g's segment holds its own neurons, whose ids all exceed those
   // of workgroups < g, by step and ascending id within a step; a stable
   // counting sort by step over the segments in order is therefore the sort
@@ -285,8 +307,6 @@ int drain(mc_net* n) {
       n->r_id[k] = (int32_t)n->dense_of(e.y);
     }
   }
-  HIP_TRY(hipMemsetAsync(n->d_raster_cnt, 0, sizeof(long long) * n->n_wg, n->stream));
-  HIP_TRY(hipStreamSynchronize(n->stream));
   n->steps_since_drain = 0;
   return MC_OK;
 }
@@ -717,6 +737,10 @@ int mc_build_network(const mc_config* cfg, mc_net** out) {
     else {
       if (hipStreamCreateWithFlags(&n->stream, hipStreamNonBlocking) != hipSuccess) return set_error(MC_ERR_HIP, "stream creation failed");
       n->own_stream = true;
+    }
+    if (hipStreamCreateWithFlags(&n->aux, hipStreamNonBlocking) != hipSuccess) {
+      release_all(n.get());
+      return set_error(MC_ERR_HIP, "stream creation failed");
     }
     rc = upload_network(n.get());
     if (rc == MC_OK && hipEventCreate(&n->ev0) != hipSuccess) rc = set_error(MC_ERR_HIP, "event creation failed");
@@ -1225,6 +1249,25 @@ int mc_adjoint(mc_net* n, const mc_adjoint_config* a, void* grad, double* loss) 
   } else {
     if ((rc = B.alloc(&ck_ring, (size_t)nseg * ring_elems)) != MC_OK) return rc;
   }
+  // reverse-pass buffers, allocated and cleared before the forward so that
+  // the reverse pass can start as soon as the forward ends
+  long long* xseg = nullptr;
+  double *rec_y = nullptr, *li_ring = nullptr, *carry = nullptr, *loss_part = nullptr;
+  uint8_t* rec_t = nullptr;
+  unsigned long long* seg_count = nullptr;
+  unsigned* mismatch = nullptr;
+  if (!record && (rc = B.alloc(&xseg, (size_t)(Kc + 101) * st)) != MC_OK) return rc;
+  if ((rc = B.alloc(&rec_y, (size_t)Kc * st)) != MC_OK) return rc;
+  if ((rc = B.alloc(&rec_t, (size_t)Kc * st)) != MC_OK) return rc;
+  if ((rc = B.alloc(&li_ring, (size_t)R * st)) != MC_OK) return rc;
+  if ((rc = B.alloc(&carry, (size_t)3 * st)) != MC_OK) return rc;
+  if ((rc = B.alloc(&seg_count, (size_t)nseg)) != MC_OK) return rc;
+  if ((rc = B.alloc(&mismatch, 1)) != MC_OK) return rc;
+  loss_part = carry + 2 * st;
+  HIP_TRY(hipMemsetAsync(carry, 0, sizeof(double) * 3 * st, n->stream));
+  HIP_TRY(hipMemsetAsync(seg_count, 0, sizeof(unsigned long long) * nseg, n->stream));
+  HIP_TRY(hipMemsetAsync(mismatch, 0, sizeof(unsigned), n->stream));
+  HIP_TRY(hipMemsetAsync(grad, 0, (fp32 ? sizeof(float) : sizeof(double)) * (size_t)M, n->stream));
 
   // forward: checkpoint, then K steps, per segment (direct launches: a
   // captured graph would carry the record-off arguments)
@@ -1249,7 +1292,25 @@ int mc_adjoint(mc_net* n, const mc_adjoint_config* a, void* grad, double* loss) 
   n->launch.steps_per_graph = spg;
   if (rc != MC_OK) return rc;
   HIP_TRY(hipEventRecord(n->ev_mid, n->stream));
-  if ((rc = drain(n)) != MC_OK) return rc;
+
+  const DevNet p = n->dev();
+  const double c = 2.0 / ((double)n->h.N * (double)S);
+  const double ystar = a->v_target_mV - n->h.e_l;
+  const int grid = n->n_cu * 8;
+  auto seg_args = [&](int64_t k) {
+    const int64_t s0 = n0 + k * K, len = std::min(K, S - k * K);
+    AdjSeg sg{};
+    sg.a = s0; sg.len = (int)len; sg.R = R; sg.c = c; sg.ystar = ystar;
+    sg.ck_y = ck_y + k * st; sg.ck_I = ck_I + k * st; sg.ck_r = ck_r + k * st;
+    sg.xseg = record ? xrec + (size_t)(s0 - n0) * st : xseg;
+    sg.rec_y = rec_y; sg.rec_t = rec_t; sg.li_ring = li_ring;
+    sg.carry_ly = carry; sg.carry_li = carry + st; sg.loss_part = loss_part; sg.spike_count = seg_count + k;
+    return sg;
+  };
+  // the last segment's recomputation needs only checkpoints and the input
+  // record: it runs while the raster is read back
+  if (record) HIP_TRY(launch_adj_segment(p, seg_args(nseg - 1), n->stream));
+  if ((rc = drain(n, n->ev_mid)) != MC_OK) return rc;
 
   // recorded spikes of the window (dense ids sorted by step, id)
   const auto lo = std::lower_bound(n->r_step.begin(), n->r_step.end(), (int32_t)n0) - n->r_step.begin();
@@ -1261,125 +1322,107 @@ int mc_adjoint(mc_net* n, const mc_adjoint_config* a, void* grad, double* loss) 
     const auto y = std::lower_bound(n->r_step.begin() + lo, n->r_step.begin() + hi, (int32_t)e) - n->r_step.begin();
     *first = (size_t)x; *count = (size_t)(y - x);
   };
-  // host work lists: per segment the spikes to deliver (t in [a, a+len-1)), to
-  // verify (t in [a, a+len)) and to gather (t in [a-2, a+len-2), t <= n0+S-3)
-  std::vector<int2> dl_sp, vf_sp;
-  std::vector<long long> dl_first;
-  std::vector<int4> srcs;               // gather: per source (padded id, first time, time count, -)
-  std::vector<long long> gfirst;        // gather: first chunk of each source, a terminator per segment
-  std::vector<int> times;
-  std::vector<size_t> dl_off(nseg + 1), vf_off(nseg + 1), it_off(nseg + 1), fc_off(nseg + 1);
-  std::vector<unsigned long long> want_count(nseg);
+  // Per segment, three work lists: the spikes to deliver into the replayed
+  // input (t in [a, a+len-1); replay mode only), to verify (t in [a, a+len))
+  // and to gather (t in [a-2, a+len-2), t <= n0+S-3).  Their sizes are known
+  // from the raster; each is built on the host just before its segment, into
+  // pinned staging, and copied with the segment's kernels on the stream, so
+  // the host builds segment k-1's lists while the device runs segment k.
+  struct SegLists {
+    size_t dl_f, dl_c, vf_f, vf_c, ga_f, ga_c;   // raster ranges
+    size_t o_dl, o_first, o_vf, o_srcs, o_gfirst, o_times;   // byte offsets in the staging / device arena
+  };
+  std::vector<SegLists> L((size_t)nseg);
+  size_t bytes = 0;
+  auto take = [&](size_t n_bytes) { const size_t o = bytes; bytes += (n_bytes + 15) & ~(size_t)15; return o; };
   for (int64_t k = 0; k < nseg; ++k) {
     const int64_t s0 = n0 + k * K, len = std::min(K, S - k * K);
-    size_t f, c;
-    dl_off[k] = dl_sp.size();
-    if (!record) {
-      spikes_in(s0, s0 + len - 1, &f, &c);
-      long long acc = 0;
-      for (size_t q = f; q < f + c; ++q) {
-        const int64_t dense = n->r_id[q];
-        const int64_t rl = n->h.row_ptr[dense + 1] - n->h.row_ptr[dense];
-        dl_sp.push_back(make_int2(n->r_step[q], (int)n->pad_of(dense)));
-        dl_first.push_back(acc);
-        acc += (rl + kReplayChunkHost - 1) / kReplayChunkHost;
-      }
-      dl_first.push_back(acc);   // one terminator per segment
-    }
-    vf_off[k] = vf_sp.size();
-    spikes_in(s0, s0 + len, &f, &c);
-    want_count[k] = c;
-    for (size_t q = f; q < f + c; ++q) vf_sp.push_back(make_int2(n->r_step[q], (int)n->pad_of(n->r_id[q])));
-    // gather: group by source, times decreasing; per source its chunk range
-    it_off[k] = srcs.size();
-    fc_off[k] = gfirst.size();
-    spikes_in(s0 - 2, std::min(s0 + len - 2, n0 + S - 2), &f, &c);
-    std::vector<std::pair<int64_t, int32_t>> by_src(c);
-    for (size_t q = 0; q < c; ++q) by_src[q] = {n->r_id[f + q], n->r_step[f + q]};
-    std::sort(by_src.begin(), by_src.end(), [](const std::pair<int64_t, int32_t>& x, const std::pair<int64_t, int32_t>& y) {
-      return x.first != y.first ? x.first < y.first : x.second > y.second;
-    });
-    long long chunks_so_far = 0;
-    for (size_t q = 0; q < c;) {
-      size_t e = q;
-      while (e < c && by_src[e].first == by_src[q].first) ++e;
-      const int64_t dense = by_src[q].first;
-      const int64_t rl = n->h.row_ptr[dense + 1] - n->h.row_ptr[dense];
-      const int t0 = (int)times.size();
-      for (size_t z = q; z < e; ++z) times.push_back(by_src[z].second);
-      srcs.push_back(make_int4((int)n->pad_of(dense), t0, (int)(e - q), 0));
-      gfirst.push_back(chunks_so_far);
-      chunks_so_far += (rl + kGatherChunkHost - 1) / kGatherChunkHost;
-      q = e;
-    }
-    gfirst.push_back(chunks_so_far);   // one terminator per segment: its item count
+    SegLists& q = L[(size_t)k];
+    q.dl_f = q.dl_c = 0;
+    if (!record) spikes_in(s0, s0 + len - 1, &q.dl_f, &q.dl_c);
+    spikes_in(s0, s0 + len, &q.vf_f, &q.vf_c);
+    spikes_in(s0 - 2, std::min(s0 + len - 2, n0 + S - 2), &q.ga_f, &q.ga_c);
+    q.o_dl = take(sizeof(int2) * q.dl_c);
+    q.o_first = take(sizeof(long long) * (q.dl_c + 1));
+    q.o_vf = take(sizeof(int2) * q.vf_c);
+    q.o_srcs = take(sizeof(int4) * q.ga_c);
+    q.o_gfirst = take(sizeof(long long) * (q.ga_c + 1));
+    q.o_times = take(sizeof(int) * q.ga_c);
   }
-  dl_off[nseg] = dl_sp.size(); vf_off[nseg] = vf_sp.size(); it_off[nseg] = srcs.size(); fc_off[nseg] = gfirst.size();
-
-  // device work lists and reverse-pass buffers
-  int2 *d_dl = nullptr, *d_vf = nullptr;
-  long long* d_first = nullptr;
-  int4* d_srcs = nullptr;
-  long long* d_gfirst = nullptr;
-  int* d_times = nullptr;
-  long long* xseg = nullptr;
-  double *rec_y = nullptr, *li_ring = nullptr, *carry = nullptr, *loss_part = nullptr;
-  uint8_t* rec_t = nullptr;
-  unsigned long long* seg_count = nullptr;
-  unsigned* mismatch = nullptr;
-  if ((rc = B.alloc(&d_dl, dl_sp.size())) != MC_OK) return rc;
-  if ((rc = B.alloc(&d_vf, vf_sp.size())) != MC_OK) return rc;
-  if ((rc = B.alloc(&d_first, dl_first.size())) != MC_OK) return rc;
-  if ((rc = B.alloc(&d_srcs, srcs.size())) != MC_OK) return rc;
-  if ((rc = B.alloc(&d_gfirst, gfirst.size())) != MC_OK) return rc;
-  if ((rc = B.alloc(&d_times, times.size())) != MC_OK) return rc;
-  if (!record && (rc = B.alloc(&xseg, (size_t)(Kc + 101) * st)) != MC_OK) return rc;
-  if ((rc = B.alloc(&rec_y, (size_t)Kc * st)) != MC_OK) return rc;
-  if ((rc = B.alloc(&rec_t, (size_t)Kc * st)) != MC_OK) return rc;
-  if ((rc = B.alloc(&li_ring, (size_t)R * st)) != MC_OK) return rc;
-  if ((rc = B.alloc(&carry, (size_t)3 * st)) != MC_OK) return rc;
-  if ((rc = B.alloc(&seg_count, (size_t)nseg)) != MC_OK) return rc;
-  if ((rc = B.alloc(&mismatch, 1)) != MC_OK) return rc;
-  loss_part = carry + 2 * st;
-  if (!dl_sp.empty()) HIP_TRY(hipMemcpy(d_dl, dl_sp.data(), sizeof(int2) * dl_sp.size(), hipMemcpyHostToDevice));
-  if (!vf_sp.empty()) HIP_TRY(hipMemcpy(d_vf, vf_sp.data(), sizeof(int2) * vf_sp.size(), hipMemcpyHostToDevice));
-  if (!dl_first.empty())
-    HIP_TRY(hipMemcpy(d_first, dl_first.data(), sizeof(long long) * dl_first.size(), hipMemcpyHostToDevice));
-  if (!srcs.empty()) HIP_TRY(hipMemcpy(d_srcs, srcs.data(), sizeof(int4) * srcs.size(), hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(d_gfirst, gfirst.data(), sizeof(long long) * gfirst.size(), hipMemcpyHostToDevice));
-  if (!times.empty()) HIP_TRY(hipMemcpy(d_times, times.data(), sizeof(int) * times.size(), hipMemcpyHostToDevice));
-  HIP_TRY(hipMemsetAsync(carry, 0, sizeof(double) * 3 * st, n->stream));
-  HIP_TRY(hipMemsetAsync(seg_count, 0, sizeof(unsigned long long) * nseg, n->stream));
-  HIP_TRY(hipMemsetAsync(mismatch, 0, sizeof(unsigned), n->stream));
-  HIP_TRY(hipMemsetAsync(grad, 0, (fp32 ? sizeof(float) : sizeof(double)) * (size_t)M, n->stream));
-
-  const DevNet p = n->dev();
-  const double c = 2.0 / ((double)n->h.N * (double)S);
-  const double ystar = a->v_target_mV - n->h.e_l;
-  const int grid = n->n_cu * 8;
-  size_t dl_first_off = 0;
-  std::vector<size_t> first_off(nseg);
-  for (int64_t k = 0; k < nseg; ++k) { first_off[k] = dl_first_off; dl_first_off += (dl_off[k + 1] - dl_off[k]) + 1; }
+  unsigned char* d_lists = nullptr;
+  if ((rc = B.alloc(&d_lists, bytes)) != MC_OK) return rc;
+  if (n->stage_bytes < bytes) {
+    if (n->h_stage) { (void)hipHostFree(n->h_stage); n->h_stage = nullptr; n->stage_bytes = 0; }
+    HIP_TRY(hipHostMalloc(&n->h_stage, bytes, hipHostMallocDefault));
+    n->stage_bytes = bytes;
+  }
+  unsigned char* h = static_cast<unsigned char*>(n->h_stage);
+  std::vector<unsigned long long> want_count((size_t)nseg);
+  std::vector<unsigned long long> keys;
   for (int64_t k = nseg - 1; k >= 0; --k) {
     const int64_t s0 = n0 + k * K, len = std::min(K, S - k * K);
+    const SegLists& q = L[(size_t)k];
+    // replay mode: the spikes whose delivery rebuilds the segment's input
+    long long dl_chunks = 0;
+    if (!record) {
+      int2* dl = reinterpret_cast<int2*>(h + q.o_dl);
+      long long* first = reinterpret_cast<long long*>(h + q.o_first);
+      for (size_t z = 0; z < q.dl_c; ++z) {
+        const int64_t dense = n->r_id[q.dl_f + z];
+        const int64_t rl = n->h.row_ptr[dense + 1] - n->h.row_ptr[dense];
+        dl[z] = make_int2(n->r_step[q.dl_f + z], (int)n->pad_of(dense));
+        first[z] = dl_chunks;
+        dl_chunks += (rl + kReplayChunkHost - 1) / kReplayChunkHost;
+      }
+      first[q.dl_c] = dl_chunks;
+    }
+    int2* vf = reinterpret_cast<int2*>(h + q.o_vf);
+    for (size_t z = 0; z < q.vf_c; ++z) vf[z] = make_int2(n->r_step[q.vf_f + z], (int)n->pad_of(n->r_id[q.vf_f + z]));
+    want_count[(size_t)k] = q.vf_c;
+    // dl, first and vf lie before the gather lists in the arena: one copy
+    HIP_TRY(hipMemcpyAsync(d_lists + q.o_dl, h + q.o_dl, q.o_srcs - q.o_dl, hipMemcpyHostToDevice, n->stream));
     if (!record) {
       HIP_TRY(launch_adj_seed(xseg, ck_ring + k * ring_elems, st, s0, (int)(len + 101), n->stream));
-      const size_t nd = dl_off[k + 1] - dl_off[k];
-      if (nd)
-        HIP_TRY(launch_replay(d_dl + dl_off[k], d_first + first_off[k], (int)nd, dl_first[first_off[k] + nd],
+      if (q.dl_c)
+        HIP_TRY(launch_replay(reinterpret_cast<const int2*>(d_lists + q.o_dl),
+                              reinterpret_cast<const long long*>(d_lists + q.o_first), (int)q.dl_c, dl_chunks,
                               n->d_row_ptr, n->d_tgt, n->d_wq, n->d_dly, xseg, st, s0, grid, n->stream));
     }
-    AdjSeg sg{};
-    sg.a = s0; sg.len = (int)len; sg.R = R; sg.c = c; sg.ystar = ystar;
-    sg.ck_y = ck_y + k * st; sg.ck_I = ck_I + k * st; sg.ck_r = ck_r + k * st;
-    sg.xseg = record ? xrec + (size_t)(s0 - n0) * st : xseg;
-    sg.rec_y = rec_y; sg.rec_t = rec_t; sg.li_ring = li_ring;
-    sg.carry_ly = carry; sg.carry_li = carry + st; sg.loss_part = loss_part; sg.spike_count = seg_count + k;
-    HIP_TRY(launch_adj_segment(p, sg, n->stream));
-    HIP_TRY(launch_adj_verify(d_vf + vf_off[k], (int)(vf_off[k + 1] - vf_off[k]), rec_t, st, s0, mismatch, n->stream));
-    const int nsrc = (int)(it_off[k + 1] - it_off[k]);
-    HIP_TRY(launch_adj_gather(d_srcs + it_off[k], d_gfirst + fc_off[k], nsrc, gfirst[fc_off[k] + nsrc], d_times,
-                              n->d_row_ptr, n->d_tgt, n->d_dly, li_ring, st, R, n0 + S - 1, grad, fp32, grid, n->stream));
+    if (!(record && k == nseg - 1)) HIP_TRY(launch_adj_segment(p, seg_args(k), n->stream));
+    HIP_TRY(launch_adj_verify(reinterpret_cast<const int2*>(d_lists + q.o_vf), (int)q.vf_c, rec_t, st, s0, mismatch,
+                              n->stream));
+    // gather: group by source (ascending), times decreasing; per source its chunk range
+    keys.resize(q.ga_c);
+    for (size_t z = 0; z < q.ga_c; ++z)
+      keys[z] = (unsigned long long)(uint32_t)n->r_id[q.ga_f + z] << 32 | (uint32_t)(0x7FFFFFFF - n->r_step[q.ga_f + z]);
+    std::sort(keys.begin(), keys.end());
+    int4* srcs = reinterpret_cast<int4*>(h + q.o_srcs);
+    long long* gfirst = reinterpret_cast<long long*>(h + q.o_gfirst);
+    int* times = reinterpret_cast<int*>(h + q.o_times);
+    long long chunks = 0;
+    int nsrc = 0;
+    for (size_t z = 0; z < q.ga_c;) {
+      size_t e = z;
+      const uint32_t src = (uint32_t)(keys[z] >> 32);
+      while (e < q.ga_c && (uint32_t)(keys[e] >> 32) == src) ++e;
+      const int64_t rl = n->h.row_ptr[src + 1] - n->h.row_ptr[src];
+      for (size_t y = z; y < e; ++y) times[y] = 0x7FFFFFFF - (int)(uint32_t)(keys[y] & 0xFFFFFFFFu);
+      srcs[nsrc] = make_int4((int)n->pad_of(src), (int)z, (int)(e - z), 0);
+      gfirst[nsrc] = chunks;
+      chunks += (rl + kGatherChunkHost - 1) / kGatherChunkHost;
+      ++nsrc;
+      z = e;
+    }
+    gfirst[nsrc] = chunks;
+    if (nsrc == 0) continue;
+    HIP_TRY(hipMemcpyAsync(d_lists + q.o_srcs, h + q.o_srcs, sizeof(int4) * nsrc, hipMemcpyHostToDevice, n->stream));
+    HIP_TRY(hipMemcpyAsync(d_lists + q.o_gfirst, h + q.o_gfirst, sizeof(long long) * (nsrc + 1), hipMemcpyHostToDevice,
+                           n->stream));
+    HIP_TRY(hipMemcpyAsync(d_lists + q.o_times, h + q.o_times, sizeof(int) * q.ga_c, hipMemcpyHostToDevice, n->stream));
+    HIP_TRY(launch_adj_gather(reinterpret_cast<const int4*>(d_lists + q.o_srcs),
+                              reinterpret_cast<const long long*>(d_lists + q.o_gfirst), nsrc, chunks,
+                              reinterpret_cast<const int*>(d_lists + q.o_times), n->d_row_ptr, n->d_tgt, n->d_dly,
+                              li_ring, st, R, n0 + S - 1, grad, fp32, grid, n->stream));
   }
   HIP_TRY(hipEventRecord(n->ev1, n->stream));
   HIP_TRY(hipStreamSynchronize(n->stream));

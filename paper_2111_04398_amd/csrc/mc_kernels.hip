@@ -197,6 +197,16 @@ __global__ void k_set_weights(int32_t* wq, const double* w, long long M) {
     wq[k] = (int32_t)__double2ll_rn(w[k] * 65536.0);
 }
 
+// Packs the used prefixes of the per-workgroup raster segments (capacity
+// `cap` entries each) into one contiguous array: workgroup g's entries go to
+// out[off[g] .. off[g+1]).  One workgroup per segment.
+__global__ void k_raster_pack(const int2* raster, long long cap, const long long* off, int2* out) {
+  const int g = blockIdx.x;
+  const long long b = off[g], c = off[g + 1] - b;
+  const int2* src = raster + (size_t)g * cap;
+  for (long long k = threadIdx.x; k < c; k += blockDim.x) out[b + k] = src[k];
+}
+
 }  // namespace mc
 
 // ---------------------------------------------------------------------------
@@ -221,6 +231,13 @@ hipError_t launch_advance(long long* step_base, int steps, hipStream_t s) {
 
 hipError_t launch_inject(long long* ring, long long idx, long long value, hipStream_t s) {
   hipLaunchKernelGGL(k_inject, dim3(1), dim3(1), 0, s, ring, idx, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_raster_pack(const int2* raster, long long cap, const long long* off, int n_seg, int2* out,
+                              hipStream_t s) {
+  if (n_seg <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_raster_pack, dim3((unsigned)n_seg), dim3(256), 0, s, raster, cap, off, out);
   return hipGetLastError();
 }
 
