@@ -93,6 +93,58 @@ def test_launch_configuration_invariance(scheme, block, npw, spg):
     assert_same(net, o, what=f"{scheme},{block},{npw},{spg}")
 
 
+@pytest.mark.parametrize("scheme,block,npw,spg", [(0, 256, 256, 100), (1, 512, 0, 100), (1, 256, 64, 7),
+                                                   (2, 256, 256, 100)])
+def test_synchronous_bursts(scheme, block, npw, spg):
+    """A DC current far above threshold makes every neuron fire at its first
+    free step: all 5,000 fire together every 21 steps.  That is the densest
+    raster the refractory period allows (the raster bound is met exactly) and,
+    in the persistent scheme, more spikes in one step than its LDS spike list
+    holds (the branch that delivers every event of such a step at once)."""
+    w = workloads.balanced().replace(name="bursts", i_e=1.0e5)
+    net, o = mc.Network(w), oracle.Oracle(w.to_dict())
+    net.set_launch(scheme=scheme, block=block, neurons_per_wg=npw, steps_per_graph=spg)
+    net.simulate(300)
+    o.run(300)
+    s, _ = o.raster()
+    assert len(s) == 5000 * len(range(0, 300, 21)) and set(np.unique(s)) == set(range(0, 300, 21))
+    assert_same(net, o, what=f"bursts {scheme},{block},{npw},{spg}")
+
+
+@pytest.mark.parametrize("scheme", [0, 1, 2])
+def test_silent_network(scheme):
+    """No drive and no current: no neuron ever fires, nothing is delivered,
+    and the membrane decays by the same propagator bits on both sides."""
+    w = workloads.balanced().replace(name="silent", nu_ext=0.0, v0_lo=-65.0, v0_hi=-50.5)
+    net, o = mc.Network(w), oracle.Oracle(w.to_dict())
+    net.set_launch(scheme=scheme, block=512 if scheme == 1 else 256, neurons_per_wg=0 if scheme == 1 else 256,
+                   steps_per_graph=50)
+    net.simulate(400)
+    o.run(400)
+    assert len(o.raster()[0]) == 0 and o.counters()[1] == 0
+    assert_same(net, o, what=f"silent {scheme}")
+
+
+def test_persistent_scheme_at_its_largest_shape():
+    """131,072 neurons in 512 workgroups of 256 targets: the most workgroups
+    the persistent scheme runs (two per compute unit, each polling 512
+    records), leaving 7 steps of input in LDS, so most events take the far
+    path.  A shape that cannot be co-resident is refused before any launch."""
+    w = workloads.balanced().replace(name="max_persistent", pop_size=[104856, 26216],
+                                     conn=[[40.0, 10.0], [40.0, 10.0]])
+    net, o = mc.Network(w), oracle.Oracle(w.to_dict())
+    assert net.N == 131072
+    with pytest.raises(mc.MCError) as e:     # 512 workgroups of 512 threads: two per CU do not fit the registers
+        net.set_launch(scheme=1, block=512, neurons_per_wg=256, steps_per_graph=100)
+    assert e.value.code == -2 and "co-resident" in str(e.value)
+    net.set_launch(scheme=1, block=256, neurons_per_wg=256, steps_per_graph=100)
+    assert net.persist_shape()["workgroups"] == 512 and net.persist_shape()["targets_per_wg"] == 256
+    net.simulate(300)
+    o.run(300)
+    assert len(o.raster()[0]) > 1000
+    assert_same(net, o, ring_depth=16, what="max persistent")
+
+
 @pytest.mark.parametrize("mk", [tiny_fixed, tiny_bernoulli])
 def test_tiny_networks_persistent(mk):
     w = mk()
