@@ -49,6 +49,7 @@ namespace {
 constexpr int kListCap = 1024;       // spikes of one step kept in LDS (more: delivered at once)
 constexpr int kInline = 7;           // spike ids carried by a record (more: side array)
 constexpr int kW0Ids = 4;            // of which in word 0 (9-bit block-local indices)
+constexpr int kBigCap = 64;          // producers with more than kInline spikes listed per step
 constexpr int kUnroll = 4;           // entries in flight per lane
 constexpr int kPollPerLane = kPersistMaxBlock / 64;   // producers polled by one lane (G <= block <= 512)
 constexpr int kNearUnroll = 12;      // near-table rows in flight per wavefront (one round for <= 12 spikes per wave)
@@ -236,6 +237,8 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
   __shared__ int s_local[kPersistMaxB];
   __shared__ int s_cnt[kPersistMaxBlock];   // spike count of every producer in the current step
   __shared__ int s_abort;
+  __shared__ int s_nids, s_nbig;                 // ids listed by the poller this step; producers with more
+  __shared__ int2 s_big[kBigCap];                // (producer, list offset) of those producers
   __shared__ unsigned long long s_events;
   __shared__ unsigned long long s_popcnt[kMaxPops];
   long long* acc = reinterpret_cast<long long*>(s_raw);
@@ -364,6 +367,7 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
     }
     if (timing) { const long long t = wall_clock64(); ph[0] += t - tp0; tp0 = t; }
     // ---- compaction (ascending ids) and publication --------------------------
+    if (tid == 0) { s_nids = 0; s_nbig = 0; }   // read after the previous wait; next used after this barrier
     int nloc;
     const int pre = block_exscan(spiked, s_tmp[0], &nloc);
     if (spiked) s_local[pre] = (int)(j0 + tid);
@@ -433,6 +437,17 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
               if (kW0Ids + k < c) s_inl[h * kInline + kW0Ids + k] = (int)(wk[k] & 0xFFFFFFFFu);
           }
           s_cnt[h] = c;
+          // the step's id list in arrival order (the order of integer sums
+          // does not matter); ids beyond the seventh are fetched after the wait
+          if (c > 0) {
+            const int o = atomicAdd(&s_nids, c);
+            for (int k = 0; k < min(c, kInline); ++k)
+              if (o + k < kListCap) s_ids[par * kListCap + o + k] = s_inl[h * kInline + k];
+            if (c > kInline) {
+              const int b = atomicAdd(&s_nbig, 1);
+              if (b < kBigCap) s_big[b] = make_int2(h, o);
+            }
+          }
           todo &= ~(1u << r);
         }
         if (!todo) break;
@@ -488,21 +503,44 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
       if (ev) atomicAdd(&s_events, ev);
       if (timing) ph[5] += wall_clock64() - tp_wait;
     }
-    __syncthreads();                       // s_cnt and the inline ids complete
-    int S;
+    __syncthreads();                       // s_cnt, the inline ids and the poller's list complete
+    if (s_abort) break;
+    int S = s_nids;
+    int* ids_n = s_ids + par * kListCap;
+    if (S <= kListCap && s_nbig <= kBigCap) {
+      // ---- the spikes of step n are listed: fetch the ids beyond the
+      //      seventh of busy producers, then each wavefront delivers the near
+      //      events of its share -------------------------------------------
+      if (timing) { const long long t = wall_clock64(); ph[2] += t - tp0; tp0 = t; }
+      const int nbig = s_nbig;
+      if (nbig > 0) {
+        for (int e = 0; e < nbig; ++e) {
+          const int h = s_big[e].x, o = s_big[e].y, c = s_cnt[h];
+          for (int k = kInline + tid; k < c; k += nthr) ids_n[o + k] = ld_dev(&a.pub[((size_t)h * 2 + par) * a.B + k]);
+        }
+        __syncthreads();
+      }
+      const int k0 = (int)((long long)S * wave / nw), k1 = (int)((long long)S * (wave + 1) / nw);
+      if (timing) { const long long t = wall_clock64(); ph[3] += t - tp0; tp0 = t; }
+      wave_near(a, blk, ids_n, k0, k1, g, sn1, sn2);
+      __syncthreads();
+      if (timing) { const long long t = wall_clock64(); ph[4] += t - tp0; tp0 = t; }
+      S2 = S1;
+      S1 = S;
+      sn = sn1;
+      continue;
+    }
+    // ---- more spikes than the list holds: listing by producer order
+    //      (count scan), then every event of the step delivered at once ----
     // thread t sums producers 2t and 2t+1 (G <= 2 * threads)
     const int c0 = (2 * tid < a.G) ? s_cnt[2 * tid] : 0;
     const int c1 = (2 * tid + 1 < a.G) ? s_cnt[2 * tid + 1] : 0;
     const int pre_h = block_exscan(c0 + c1, s_tmp[1], &S);   // also a barrier
-    if (s_abort) break;
     if (2 * tid < a.G) s_pre[2 * tid] = pre_h;
     if (2 * tid + 1 < a.G) s_pre[2 * tid + 1] = pre_h + c0;
     if (tid == 0) s_pre[a.G] = S;
     __syncthreads();
     if (timing) { const long long t = wall_clock64(); ph[2] += t - tp0; tp0 = t; }
-    // ---- the spikes of step n: each wavefront lists its share of the ids in
-    //      LDS (for the pipeline) and delivers their near events -------------
-    int* ids_n = s_ids + par * kListCap;
     for (int base = 0; base < S; base += kListCap) {
       const int cnt = min(kListCap, S - base);
       const int k0 = (int)((long long)cnt * wave / nw), k1 = (int)((long long)cnt * (wave + 1) / nw);
