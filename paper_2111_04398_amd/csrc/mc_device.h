@@ -75,7 +75,9 @@ struct PersistArgs {
   long long spin_limit;        // polls before giving up
   unsigned long long* phase;   // optional [G*8]: summed wall_clock64 ticks per phase (nullptr: off)
   // near table: the delay-1/2 synapses of row i into workgroup g's block are
-  // ne[nb[i][g] .. nb[i][g+1]), each (delay-2 flag | target - bstart[g]) << 32 | weight
+  // ne[nb[i][p] .. nb[i][p+1]) with p the position of g when the workgroups
+  // are ordered by XCD (g mod 8, then g), each (delay-2 flag | target -
+  // bstart[g]) << 32 | weight
   const unsigned* nb;          // [n_pad][G+1]
   const unsigned long long* ne;
 };

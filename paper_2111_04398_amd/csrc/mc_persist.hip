@@ -55,6 +55,26 @@ constexpr int kPollPerLane = kPersistMaxBlock / 64;   // producers polled by one
 constexpr int kNearUnroll = 12;      // near-table rows in flight per wavefront (one round for <= 12 spikes per wave)
 constexpr unsigned kNearD2 = 0x80000000u;   // near-table flag: delay 2 (else 1)
 
+// Workgroups are dispatched to the XCDs round robin (workgroup g runs on XCD
+// g mod 8), and each XCD has its own L2.  Per-source tables indexed by
+// workgroup are laid out by XCD, so that the entries the workgroups of one
+// XCD read for a source share cache lines: position of workgroup g, and its
+// inverse.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_pos(int g, int G) {
+  const int x = g % kXcds;
+  int pos = g / kXcds;
+  for (int y = 0; y < x; ++y) pos += (G - y + kXcds - 1) / kXcds;
+  return pos;
+}
+__device__ __forceinline__ int xcd_wg(int pos, int G) {
+  for (int x = 0;; ++x) {
+    const int c = (G - x + kXcds - 1) / kXcds;
+    if (pos < c) return pos * kXcds + x;
+    pos -= c;
+  }
+}
+
 __device__ __forceinline__ int poisson_inv(const uint64_t* T, uint32_t u) {
   int k = 0;
   while ((uint64_t)u >= T[k]) ++k;
@@ -177,17 +197,18 @@ __device__ __forceinline__ void wave_entries(const DevNet& p, const Block& b, in
 
 // One wavefront adds the delay-1 and delay-2 events of spikes list[k0..k1)
 // that land in this workgroup's block: the near table holds them per
-// (source, workgroup) as a CSR (offsets nb[i][g], nb[i][g+1]; entries
+// (source, workgroup) as a CSR over workgroups in XCD order (offsets
+// nb[i][p], nb[i][p+1] at the workgroup's position p; entries
 // (delay-2 flag | local target) << 32 | weight).  Lanes load the offsets of 64
 // spikes, scan the counts and walk the concatenated entries.
-__device__ __forceinline__ void wave_near(const PersistArgs& a, const Block& b, const int* list, int k0, int k1, int g,
+__device__ __forceinline__ void wave_near(const PersistArgs& a, const Block& b, const int* list, int k0, int k1, int gpos,
                                           int slot1, int slot2) {
   const int lane = threadIdx.x & 63;
   for (int base = k0; base < k1; base += 64) {
     unsigned lo = 0;
     int len = 0;
     if (base + lane < k1) {
-      const unsigned* o = a.nb + (size_t)list[base + lane] * (a.G + 1) + g;
+      const unsigned* o = a.nb + (size_t)list[base + lane] * (a.G + 1) + gpos;
       lo = o[0];
       len = (int)(o[1] - lo);
     }
@@ -250,6 +271,7 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
   long long* s_lo = reinterpret_cast<long long*>(((uintptr_t)(s_len + 2 * kListCap) + 15) & ~(uintptr_t)15);
 
   const int g = blockIdx.x, tid = threadIdx.x, nthr = blockDim.x;
+  const int gpos = xcd_pos(g, a.G);                                 // column of this workgroup in the near table
   const int wave = tid >> 6, nw = nthr >> 6;
   const long long j0 = a.bstart[g];                                 // first owned target (padded id)
   const int Bg = a.bstart[g + 1] - a.bstart[g];                     // owned targets (multiple of 4, <= B)
@@ -522,7 +544,7 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
       }
       const int k0 = (int)((long long)S * wave / nw), k1 = (int)((long long)S * (wave + 1) / nw);
       if (timing) { const long long t = wall_clock64(); ph[3] += t - tp0; tp0 = t; }
-      wave_near(a, blk, ids_n, k0, k1, g, sn1, sn2);
+      wave_near(a, blk, ids_n, k0, k1, gpos, sn1, sn2);
       __syncthreads();
       if (timing) { const long long t = wall_clock64(); ph[4] += t - tp0; tp0 = t; }
       S2 = S1;
@@ -553,7 +575,7 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
       }
       if (timing) { const long long t = wall_clock64(); ph[3] += t - tp0; tp0 = t; }
       if (S <= kListCap) {
-        wave_near(a, blk, ids_n, k0, k1, g, sn1, sn2);   // reads the ids this wavefront wrote
+        wave_near(a, blk, ids_n, k0, k1, gpos, sn1, sn2);   // reads the ids this wavefront wrote
       } else {
         // too many spikes to keep: deliver all events of this chunk now
         unsigned long long ev = 0;
@@ -649,29 +671,36 @@ __device__ __forceinline__ void row_range(const int64_t* row_ptr, const int32_t*
   *e = lo;
 }
 
-// Superblock s covers the targets of workgroups [s*wps, min((s+1)*wps, G)).
-// Near (delay 1-2) synapses of row i that land in workgroup g's block:
-// counts into cnt[i][g] (g < G; cnt[i][G] = 0 for the exclusive scan).
+// Near (delay 1-2) synapses of row i that land in the block of the workgroup
+// at XCD-order position p: counts into cnt[i][p] (p < G; cnt[i][G] = 0 for
+// the exclusive scan).
 __global__ void k_near_count(const int32_t* tgt, const uint8_t* dly, const long long* blk, long long n_pad, int G,
                              unsigned* cnt) {
   const long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (idx >= n_pad * (G + 1)) return;
-  const int g = (int)(idx % (G + 1));
+  const long long i = idx / (G + 1);
+  const int pos = (int)(idx - i * (G + 1));
   unsigned c = 0;
-  if (g < G)
-    for (long long k = blk[idx]; k < blk[idx + 1]; ++k) c += (dly[k] <= 2);
+  if (pos < G) {
+    const long long* b = blk + i * (G + 1) + xcd_wg(pos, G);
+    for (long long k = b[0]; k < b[1]; ++k) c += (dly[k] <= 2);
+  }
   cnt[idx] = c;
 }
 
-// Entries at nb[i][g]...: (delay-2 flag | target - bstart[g]) << 32 | weight, in row order.
+// Entries at nb[i][p]...: (delay-2 flag | target - bstart[g]) << 32 | weight,
+// in row order, for the workgroup g at position p.
 __global__ void k_near_fill(const int32_t* tgt, const int32_t* wq, const uint8_t* dly, const long long* blk,
                             const int* bstart, long long n_pad, int G, const unsigned* nb, unsigned long long* ne) {
   const long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (idx >= n_pad * (G + 1)) return;
-  const int g = (int)(idx % (G + 1));
-  if (g == G) return;
+  const long long i = idx / (G + 1);
+  const int pos = (int)(idx - i * (G + 1));
+  if (pos == G) return;
+  const int g = xcd_wg(pos, G);
+  const long long* b = blk + i * (G + 1) + g;
   unsigned o = nb[idx];
-  for (long long k = blk[idx]; k < blk[idx + 1]; ++k)
+  for (long long k = b[0]; k < b[1]; ++k)
     if (dly[k] <= 2)
       ne[o++] = ((unsigned long long)((unsigned)(tgt[k] - bstart[g]) | (dly[k] == 2 ? kNearD2 : 0u)) << 32) |
                 (unsigned)wq[k];
