@@ -50,3 +50,30 @@ def window_loss(net: mc.Network, w: torch.Tensor, window: int, ckpt_every: int, 
     """Loss L = 1/(N S) sum (V - v_target)^2 over the next `window` steps of
     `net` (which advances by `window` steps), differentiable in `w`."""
     return _WindowLoss.apply(w, net, int(window), int(ckpt_every), float(v_target))
+
+
+def fit_weights(net: mc.Network, w: torch.Tensor, window: int, ckpt_every: int, v_target: float, iters: int,
+                rel_step: float = 0.01) -> list:
+    """Gradient descent on the explicitly stored weights (the Discussion of
+    the paper notes that storing every synapse keeps plasticity and learning
+    possible).  Every iteration restarts the window from the network state
+    at the call, takes dL/dw with the spike pattern frozen and moves w
+    against it by a step whose first-order decrease of L is `rel_step` of L;
+    `w` is updated in place.  The network ends at the state after the last
+    window.  Returns the loss of every iteration."""
+    if not w.requires_grad:
+        raise ValueError("w must require grad")
+    start = net.save_state()
+    losses = []
+    for it in range(iters):
+        if it:
+            net.load_state(start)
+        loss = window_loss(net, w, window, ckpt_every, v_target)
+        (g,) = torch.autograd.grad(loss, w)
+        lv = float(loss.item())
+        gg = float(torch.dot(g.double(), g.double()).item())
+        losses.append(lv)
+        if gg > 0.0:
+            with torch.no_grad():
+                w -= (rel_step * lv / gg) * g.to(w.dtype)
+    return losses

@@ -10,7 +10,7 @@ import torch
 
 import oracle
 from paper_2111_04398_amd import mc, workloads
-from paper_2111_04398_amd.autograd import window_loss
+from paper_2111_04398_amd.autograd import fit_weights, window_loss
 
 pytestmark = pytest.mark.gpu
 
@@ -224,3 +224,18 @@ def test_adjoint_full_scale_fp32():
     _, og64 = oracle.Oracle(w.to_dict()).adjoint(S, Y_STAR)
     rel = np.abs(gg[sel].astype(np.float64) - og64[sel]) / np.abs(og64[sel])
     assert np.median(rel) <= 1e-6 and rel.max() <= 1e-3, (np.median(rel), rel.max())
+
+
+def test_gradient_descent_on_the_weights_lowers_the_loss(small):
+    """Learning on the int32 store: a few gradient steps on the scale-0.1
+    microcircuit's weights (each window restarted from the same state) lower
+    the membrane-potential loss; the first gradient is the oracle's."""
+    w, S, loss, g, _, _, _, (rp, tg, wq, d) = small
+    net = mc.Network(w)
+    wt = torch.tensor(wq.astype(np.float64) / 65536.0, dtype=torch.float64, device="cuda", requires_grad=True)
+    losses = fit_weights(net, wt, S, w.adj_ckpt_every, V_TARGET, iters=4, rel_step=0.02)
+    assert abs(losses[0] - loss) <= 1e-12 * abs(loss)
+    assert losses[-1] < losses[0], losses      # measured: 20.33, 20.17, 20.12, 20.16
+    assert net.counters()["step"] == S
+    q = net.synapses()[2]
+    assert not np.array_equal(q, wq)       # the store holds the learnt, re-quantised weights
