@@ -16,12 +16,14 @@
 //
 // Critical path.  Only the events of step n with delay 1 must be in place
 // before the update of step n+1, and those with delay 2 before step n+2.
-// Both come from a "near" table (per source and target superblock, fixed
-// capacity, so one load finds them), delivered right after the spike list of
-// step n is known.  The other events are pipelined over the two following
-// steps, while the workgroup waits for the next spike lists: in step n+1 the
-// block bounds blk[i][g] of step n's spikes are loaded, in step n+2 their
-// entries (delay >= 3, landing at step n+3 or later) are added.
+// Both come from a "near" table (the delay-1/2 synapses per source and
+// workgroup, as a CSR), delivered right after the spike list of step n is
+// complete.  The other events are pipelined over the two following steps,
+// while the workgroup waits for the next spike lists: in step n+1 the block
+// bounds blk[i][g] of step n's spikes are loaded, in step n+2 their entries
+// (delay >= 3, landing at step n+3 or later) are added.  The poller lists the
+// ids of each record as it arrives, so the list is complete when the wait
+// ends.
 //
 // Spike exchange: workgroup g publishes a record per step (two records per
 // workgroup, alternating by step parity, so a record is never rewritten while
@@ -34,9 +36,9 @@
 // a tag, so a consumer accepts a record when all the words it needs show the
 // current step, whatever order the stores became visible in.  Spikes beyond
 // the seventh are written to a side array before word 0 (with a wait for
-// their completion), so they are visible once word 0 is.  All of these are device-scope atomic accesses
-// (coherent at the memory side), so the step needs no L2 writeback or
-// invalidate.  Every wait is bounded; on timeout the kernel sets an error bit
+// their completion), so they are visible once word 0 is.  All of these are
+// device-scope atomic accesses (coherent at the memory side), so the step
+// needs no L2 writeback or invalidate.  Every wait is bounded; on timeout the kernel sets an error bit
 // and every workgroup leaves the loop.
 #pragma clang fp contract(off)
 
