@@ -26,9 +26,12 @@
 //                      forward saw);
 //   3. k_adj_segment   one thread per neuron: re-runs the len steps from the
 //                      checkpoint (drive + exact integration, bit-identical
-//                      to the forward), keeps y and the step type of every
-//                      step, then runs the transposed recurrence backwards
-//                      over the segment, writing LI into a ring of R slots;
+//                      to the forward; the drive is redrawn only when the
+//                      input comes from the replay, the forward's input
+//                      record already holds it), keeps y and the step type
+//                      of every step, then runs the transposed recurrence
+//                      backwards over the segment, writing LI into a ring of
+//                      R slots;
 //   4. k_adj_verify    every recorded spike of the segment must be a spike
 //                      of the recompute (and the counts must agree);
 //   5. k_adj_gather    one wavefront per (source, chunk of 256 of its row): for
@@ -76,9 +79,11 @@ __global__ __launch_bounds__(kAdjBlock) void k_adj_segment(DevNet p, AdjSeg s) {
     int r = s.ck_r[i];
     for (int j = 0; j < s.len; ++j) {
       const long long n = s.a + j;
-      const U64x4 v = philox4x64_10((uint64_t)n, qlocal, 0, kTagDrive, qseed, 0);
-      const int cnt = poisson_from_u32(T, hi32(pick(v, word)));
-      const long long x_int = s.xseg[(size_t)j * st + i] + (long long)cnt * p.jext_q;
+      long long x_int = s.xseg[(size_t)j * st + i];
+      if (!s.x_has_drive) {
+        const U64x4 v = philox4x64_10((uint64_t)n, qlocal, 0, kTagDrive, qseed, 0);
+        x_int += (long long)poisson_from_u32(T, hi32(pick(v, word))) * p.jext_q;
+      }
       uint8_t type;
       if (lif_step(p, y, I, r, x_int, type)) ++spikes;
       s.rec_y[(size_t)j * st + i] = y;

@@ -1303,6 +1303,7 @@ int mc_adjoint(mc_net* n, const mc_adjoint_config* a, void* grad, double* loss) 
     sg.a = s0; sg.len = (int)len; sg.R = R; sg.c = c; sg.ystar = ystar;
     sg.ck_y = ck_y + k * st; sg.ck_I = ck_I + k * st; sg.ck_r = ck_r + k * st;
     sg.xseg = record ? xrec + (size_t)(s0 - n0) * st : xseg;
+    sg.x_has_drive = record ? 1 : 0;
     sg.rec_y = rec_y; sg.rec_t = rec_t; sg.li_ring = li_ring;
     sg.carry_ly = carry; sg.carry_li = carry + st; sg.loss_part = loss_part; sg.spike_count = seg_count + k;
     return sg;

@@ -44,8 +44,8 @@ struct DevNet {
   unsigned long long* wg_events;   // [n_wg]
   unsigned long long* wg_spikes;   // [n_wg * n_pops]
   unsigned* overflow;       // set if a raster segment would overflow
-  // adjoint forward: when xrec is set, the integer synaptic input (ring and
-  // far part, without the drive) of every neuron at step n in [xrec_step0,
+  // adjoint forward: when xrec is set, the integer input (ring, far part
+  // and the Poisson drive) of every neuron at step n in [xrec_step0,
   // xrec_step0 + xrec_steps) goes to xrec[(n - xrec_step0) * ring_stride + i]
   long long* xrec;
   long long xrec_step0;
@@ -115,7 +115,8 @@ struct AdjSeg {
   const double* ck_y;      // checkpoint state at step a
   const double* ck_I;
   const int32_t* ck_r;
-  const long long* xseg;   // [len][ring_stride] integer input without the drive
+  const long long* xseg;   // [len][ring_stride] integer input, with the drive if x_has_drive, else without
+  int x_has_drive;         // 1: xseg is the forward's full input record (no drive to redraw)
   double* rec_y;           // [len][ring_stride] post-step y
   uint8_t* rec_t;          // [len][ring_stride] step type
   double* li_ring;         // [R][ring_stride] LI(m) at slot m & (R-1)

@@ -77,11 +77,6 @@ __global__ __launch_bounds__(kMaxBlock) void k_step(DevNet p, int offset, int qp
     *reinterpret_cast<longlong2*>(slot) = make_longlong2(0, 0);
     *reinterpret_cast<longlong2*>(slot + 2) = make_longlong2(0, 0);
     const long long sl[4] = {s01.x, s01.y, s23.x, s23.y};
-    if (p.xrec && n - p.xrec_step0 >= 0 && n - p.xrec_step0 < p.xrec_steps) {
-      long long* xr = p.xrec + (size_t)(n - p.xrec_step0) * p.ring_stride + 4 * q;
-      *reinterpret_cast<longlong2*>(xr) = s01;
-      *reinterpret_cast<longlong2*>(xr + 2) = s23;
-    }
     double* yq = p.y + 4 * q;
     double* Iq = p.I + 4 * q;
     int* rq = p.r + 4 * q;
@@ -92,13 +87,19 @@ __global__ __launch_bounds__(kMaxBlock) void k_step(DevNet p, int offset, int qp
     double I[4] = {ia.x, ia.y, ib.x, ib.y};
     int r[4] = {r4.x, r4.y, r4.z, r4.w};
     uint8_t type[4];
+    long long xin[4] = {sl[0], sl[1], sl[2], sl[3]};
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const unsigned pop = (pops >> (8 * k)) & 0xFFu;
       if (pop == 0xFFu) continue;  // padding neuron: never updated, never spikes
       const int cnt = poisson_from_u32(s_table + pop * kTableLen, hi32(pick(v, k)));
-      const long long x_int = sl[k] + (long long)cnt * p.jext_q;
-      if (lif_step(p, y[k], I[k], r[k], x_int, type[k])) mask |= 1u << k;
+      xin[k] = sl[k] + (long long)cnt * p.jext_q;
+      if (lif_step(p, y[k], I[k], r[k], xin[k], type[k])) mask |= 1u << k;
+    }
+    if (p.xrec && n - p.xrec_step0 >= 0 && n - p.xrec_step0 < p.xrec_steps) {
+      long long* xr = p.xrec + (size_t)(n - p.xrec_step0) * p.ring_stride + 4 * q;
+      *reinterpret_cast<longlong2*>(xr) = make_longlong2(xin[0], xin[1]);
+      *reinterpret_cast<longlong2*>(xr + 2) = make_longlong2(xin[2], xin[3]);
     }
     *reinterpret_cast<double2*>(yq) = make_double2(y[0], y[1]);
     *reinterpret_cast<double2*>(yq + 2) = make_double2(y[2], y[3]);

@@ -367,10 +367,10 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
             reinterpret_cast<unsigned long long*>(p.ring + (size_t)fslot * p.ring_stride + j0 + jl), 0ull,
             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
+      if (pop != 0xFFu) x_int += (long long)kdrive * p.jext_q;
       if (p.xrec && n - p.xrec_step0 >= 0 && n - p.xrec_step0 < p.xrec_steps)
         p.xrec[(size_t)(n - p.xrec_step0) * p.ring_stride + j0 + jl] = x_int;
       if (pop != 0xFFu) {
-        x_int += (long long)kdrive * p.jext_q;
         const double x = (double)x_int * 0x1p-16;
         const bool free_ = (r == 0);
         if (free_) {
