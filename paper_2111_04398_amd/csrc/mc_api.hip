@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <memory>
 #include <new>
 #include <string>
@@ -137,7 +138,9 @@ struct mc_net {
   unsigned* d_overflow = nullptr;
   int64_t cap_steps = 0;               // steps the raster segments can absorb between drains
   int64_t steps_since_drain = 0;
-  std::vector<int32_t> r_step, r_id;   // drained raster (dense ids), sorted
+  // drained raster (dense ids), sorted by (step, id); a deque, so that growing
+  // it never copies the spikes already held (long runs hold tens of millions)
+  std::deque<int32_t> r_step, r_id;
   int64_t events_base = 0;
   std::vector<int64_t> spikes_base;
   int64_t step = 0;
@@ -811,8 +814,8 @@ int mc_get_spikes(mc_net* n, int64_t b, int64_t e, int32_t* st, int32_t* id, int
   if (cnt > 0 && (!st || !id)) return set_error(MC_ERR_INVALID_ARG, "NULL output arrays");
   const size_t o = lo - n->r_step.begin();
   if (cnt) {
-    std::memcpy(st, n->r_step.data() + o, sizeof(int32_t) * cnt);
-    std::memcpy(id, n->r_id.data() + o, sizeof(int32_t) * cnt);
+    std::copy(n->r_step.begin() + o, n->r_step.begin() + o + cnt, st);
+    std::copy(n->r_id.begin() + o, n->r_id.begin() + o + cnt, id);
   }
   return MC_OK;
 }
