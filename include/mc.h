@@ -137,9 +137,10 @@ typedef struct mc_adjoint_config {
   double v_target_mV;            /* loss target V* */
   int32_t grad_dtype;            /* MC_GRAD_F64 or MC_GRAD_F32 */
   int32_t input_mode;            /* how a segment's synaptic input is recovered for the recompute:
-                                    MC_ADJ_INPUT_AUTO, _RECORD (the forward stores every neuron's integer
-                                    input: 8 B per neuron-step), _REPLAY (the ring is kept with every
-                                    checkpoint and the recorded spikes are delivered again) */
+                                    MC_ADJ_INPUT_AUTO, _RECORD (the forward stores every neuron's whole
+                                    integer input, drive included: 8 B per neuron-step), _REPLAY (the
+                                    ring is kept with every checkpoint, the recorded spikes are
+                                    delivered again and the drive is redrawn) */
 } mc_adjoint_config;
 enum { MC_ADJ_INPUT_AUTO = 0, MC_ADJ_INPUT_RECORD = 1, MC_ADJ_INPUT_REPLAY = 2 };
 
@@ -177,12 +178,14 @@ int mc_get_spikes(mc_net* net, int64_t step_begin, int64_t step_end,
  * before n0, is the fixed initial condition.  The network advances by S
  * steps exactly as mc_simulate(S) would (same spikes, same raster).  The
  * forward state (y, I, r) is kept every ckpt_every steps and recomputed per
- * segment; the segment's synaptic input comes either from a record of every
- * neuron's integer input made by the forward (8 B per neuron-step: the
+ * segment; the segment's input comes either from a record of every
+ * neuron's whole integer input made by the forward (8 B per neuron-step: the
  * default up to 16 GiB) or from the ring kept with each checkpoint (about
- * 8 B x 128 x N) plus a second delivery of the recorded spikes.  A recompute
- * that does not reproduce the recorded spikes returns MISMATCH.  grad_dev: caller-owned device array of mc_get_sizes().n_synapses
- * elements (double for MC_GRAD_F64; float for MC_GRAD_F32, accumulated as
+ * 8 B x 128 x N) plus a second delivery of the recorded spikes and the
+ * redrawn drive.  A recompute that does not reproduce the recorded spikes
+ * returns MISMATCH.  grad_dev: caller-owned device array of
+ * mc_get_sizes().n_synapses elements (double for MC_GRAD_F64; float for
+ * MC_GRAD_F32, accumulated as
  * g = f32(g + f32(term)) from FP64 adjoint states), in the canonical synapse
  * order of mc_get_synapses; overwritten.  *loss_out (host): L.
  * Synchronizes the stream.  Errors: INVALID_ARG (NULL pointers, S outside
