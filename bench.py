@@ -426,6 +426,30 @@ def run_adjoint(args, mc, w) -> dict:
     }
 
 
+def run_build_compare(args, mc, w) -> dict:
+    """Instantiation of the workload with the connections drawn on the host
+    and on the device (MC_FLAG_DEVICE_CONNECT), timed by the host clock, and
+    the two synapse stores compared bit for bit."""
+    import numpy as np
+    t0 = time.perf_counter()
+    a = mc.Network(w)
+    host_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    b = mc.Network(w, device_connect=True)
+    dev_s = time.perf_counter() - t0
+    same = all(np.array_equal(x, y) for x, y in zip(a.synapses(), b.synapses()))
+    n, m = a.N, a.M
+    a.close()
+    b.close()
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    return {"metric": f"network instantiation seconds, {w.name} ({n} neurons, {m} synapses)", "value": dev_s,
+            "unit": "s", "n_gpus": 1, "steps": 0, "warmup": 0, "ms_per_step": None, "higher_is_better": False,
+            "scaling": "weak", "vs_baseline": None, "dtype": "u64 (Philox pair tests)", "data": "synthetic",
+            "config": {"workload": w.name, "neurons": n, "synapses": m},
+            "host_draws_s": host_s, "device_draws_s": dev_s, "speedup": host_s / dev_s, "host_threads": threads,
+            "identical_store": same}
+
+
 def copy_calibration(nbytes: int) -> None:
     """A plain device-to-device copy of known size (the HIP runtime's copy
     kernel, called through the runtime libmc already loaded): reads nbytes
@@ -466,6 +490,8 @@ def main() -> int:
     ap.add_argument("--seq-instances", type=int, default=0,
                     help="batched: instances timed sequentially (0: all; the total is scaled to all)")
     ap.add_argument("--seq-launch", default="", help="batched: launch of the sequential runs (default: autotuned)")
+    ap.add_argument("--compare-build", action="store_true",
+                    help="only time the workload's instantiation with host and with device connection draws")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="at the end, copy a MIB-MiB device buffer 3 times (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -479,7 +505,9 @@ def main() -> int:
         from paper_2111_04398_amd import build as _b
         _b.build()
     w = workloads.PRESETS[args.workload]()
-    if args.workload in ("microcircuit", "balanced"):
+    if args.compare_build:
+        out = run_build_compare(args, mc, w)
+    elif args.workload in ("microcircuit", "balanced"):
         out = run_plain(args, mc, w)
     elif args.workload == "batched":
         out = run_batched(args, mc, w)

@@ -58,7 +58,14 @@ typedef enum mc_status {
 
 enum { MC_RULE_FIXED_INDEGREE = 0, MC_RULE_BERNOULLI = 1 };
 enum { MC_GRAD_F64 = 0, MC_GRAD_F32 = 1 };
-enum { MC_FLAG_HOST_ONLY = 1u };  /* build the network on the host only (no device memory) */
+enum {
+  MC_FLAG_HOST_ONLY = 1u,       /* build the network on the host only (no device memory) */
+  MC_FLAG_DEVICE_CONNECT = 2u   /* draw the connections of MC_RULE_BERNOULLI on the device: the pair
+                                   tests (integer Philox draws) run as HIP kernels, weights, delays
+                                   and everything else on the host; the network is bit-identical to
+                                   the host build.  Ignored for MC_RULE_FIXED_INDEGREE; INVALID_ARG
+                                   with MC_FLAG_HOST_ONLY. */
+};
 
 typedef struct mc_net mc_net;
 

@@ -718,7 +718,26 @@ int mc_build_network(const mc_config* cfg, mc_net** out) {
   try { n.reset(new mc_net()); } catch (...) { return set_error(MC_ERR_OOM, "host allocation failed"); }
   std::string err;
   int rc;
-  try { rc = build_host(*cfg, n->h, err); } catch (const std::bad_alloc&) { rc = MC_ERR_OOM; err = "host allocation failed"; }
+  // connections of the Bernoulli rule drawn on the device, on request
+  std::unique_ptr<ConnBuilder> conn;
+  hipStream_t conn_stream = nullptr;
+  if ((cfg->flags & MC_FLAG_DEVICE_CONNECT) != 0) {
+    if ((cfg->flags & MC_FLAG_HOST_ONLY) != 0)
+      return set_error(MC_ERR_INVALID_ARG, "MC_FLAG_DEVICE_CONNECT needs the device (MC_FLAG_HOST_ONLY given)");
+    if (cfg->rule == MC_RULE_BERNOULLI) {
+      int ndev = 0, dev = 0;
+      hipDeviceProp_t prop;
+      if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1 || hipGetDevice(&dev) != hipSuccess ||
+          hipGetDeviceProperties(&prop, dev) != hipSuccess || std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return set_error(MC_ERR_NO_DEVICE, "MC_FLAG_DEVICE_CONNECT: no gfx950 device");
+      if (hipStreamCreateWithFlags(&conn_stream, hipStreamNonBlocking) != hipSuccess)
+        return set_error(MC_ERR_HIP, "stream creation failed");
+      conn.reset(new_device_conn(prop.multiProcessorCount * 8, conn_stream));
+    }
+  }
+  try { rc = build_host(*cfg, n->h, err, conn.get()); } catch (const std::bad_alloc&) { rc = MC_ERR_OOM; err = "host allocation failed"; }
+  conn.reset();
+  if (conn_stream) (void)hipStreamDestroy(conn_stream);
   if (rc != MC_OK) return set_error(rc, err);
   n->spikes_base.assign((size_t)n->h.n_pops, 0);
   n->host_only = (cfg->flags & MC_FLAG_HOST_ONLY) != 0;

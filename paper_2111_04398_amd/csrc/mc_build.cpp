@@ -114,7 +114,44 @@ bool build_bernoulli(const Params& p, const Instance& in, int64_t goff, HostNet&
 
 static int fail(std::string& err, int code, const char* msg) { err = msg; return code; }
 
-int build_host(const mc_config& c, HostNet& net, std::string& err) {
+// Connections of one Bernoulli instance from a connection builder, then the
+// weight and delay of every synapse on the host (the draws keyed (i, j) that
+// the host's own pass 2 makes).
+static int build_bernoulli_with(const Params& p, const Instance& in, int64_t goff, HostNet& net, ConnBuilder& conn,
+                         const std::vector<uint64_t>& thr, std::vector<int64_t>& counts, bool fill, std::string& err) {
+  BernoulliPlan plan;
+  plan.N = in.N;
+  plan.n_pops = p.n;
+  plan.off = in.off.data();
+  plan.pop = in.pop.data();
+  plan.thr = thr.data();
+  plan.seed = in.seed;
+  plan.goff = goff;
+  if (!fill) return conn.count(plan, counts.data(), err);
+  const int64_t base = net.row_ptr[goff];
+  std::vector<int64_t> rp((size_t)in.N + 1);
+  for (int64_t i = 0; i <= in.N; ++i) rp[i] = net.row_ptr[goff + i] - base;
+  int rc = conn.fill(plan, rp.data(), net.tgt.data() + base, err);
+  if (rc != MC_OK) return rc;
+  bool ok = true;
+#pragma omp parallel for schedule(dynamic, 32) reduction(&& : ok)
+  for (int64_t i = 0; i < in.N; ++i)
+    for (int64_t e = base + rp[i]; e < base + rp[i + 1]; ++e) {
+      const int64_t j = net.tgt[e] - goff;
+      if (!weight_and_delay(p, in.seed, (uint64_t)i, (uint64_t)j, in.pop[j], in.pop[i], net.wq[e], net.dly[e])) ok = false;
+    }
+  if (!ok) { err = "a quantised weight does not fit in int32"; return MC_ERR_RANGE; }
+  return MC_OK;
+}
+
+static std::vector<uint64_t> bernoulli_thresholds(const mc_config& c, int n) {
+  std::vector<uint64_t> thr((size_t)n * n);
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b) thr[a * n + b] = (uint64_t)std::floor(param(c.conn, n, a, b) * 4294967296.0);
+  return thr;
+}
+
+int build_host(const mc_config& c, HostNet& net, std::string& err, ConnBuilder* conn) {
   if (c.struct_size != sizeof(mc_config)) return fail(err, MC_ERR_INVALID_ARG, "mc_config.struct_size mismatch");
   const int n = c.n_pops;
   if (n < 1 || n > kMaxPops) return fail(err, MC_ERR_INVALID_ARG, "n_pops must be in [1, 16]");
@@ -227,9 +264,15 @@ int build_host(const mc_config& c, HostNet& net, std::string& err) {
   net.row_ptr.assign((size_t)net.N + 1, 0);
   if (c.rule == MC_RULE_BERNOULLI) {
     std::vector<std::vector<int64_t>> counts((size_t)c.n_instances);
+    const std::vector<uint64_t> thr = bernoulli_thresholds(c, n);
     for (int b = 0; b < c.n_instances; ++b) {
       counts[b].assign((size_t)inst[b].N, 0);
-      build_bernoulli(p, inst[b], net.inst_off[b], net, net.inst_off[b], 0, counts[b], false, err);
+      if (conn) {
+        const int rc = build_bernoulli_with(p, inst[b], net.inst_off[b], net, *conn, thr, counts[b], false, err);
+        if (rc != MC_OK) return rc;
+      } else {
+        build_bernoulli(p, inst[b], net.inst_off[b], net, net.inst_off[b], 0, counts[b], false, err);
+      }
       for (int64_t i = 0; i < inst[b].N; ++i)
         net.row_ptr[net.inst_off[b] + i + 1] = net.row_ptr[net.inst_off[b] + i] + counts[b][i];
       if (b + 1 < c.n_instances) net.row_ptr[net.inst_off[b + 1]] = net.row_ptr[net.inst_off[b] + inst[b].N];
@@ -238,9 +281,14 @@ int build_host(const mc_config& c, HostNet& net, std::string& err) {
     try {
       net.tgt.resize((size_t)net.M); net.wq.resize((size_t)net.M); net.dly.resize((size_t)net.M);
     } catch (...) { return fail(err, MC_ERR_OOM, "host allocation of the synapse store failed"); }
-    for (int b = 0; b < c.n_instances; ++b)
-      if (!build_bernoulli(p, inst[b], net.inst_off[b], net, net.inst_off[b], 0, counts[b], true, err))
+    for (int b = 0; b < c.n_instances; ++b) {
+      if (conn) {
+        const int rc = build_bernoulli_with(p, inst[b], net.inst_off[b], net, *conn, thr, counts[b], true, err);
+        if (rc != MC_OK) return rc;
+      } else if (!build_bernoulli(p, inst[b], net.inst_off[b], net, net.inst_off[b], 0, counts[b], true, err)) {
         return MC_ERR_RANGE;
+      }
+    }
   } else {
     // Fixed in-degree: target j draws, for each presynaptic population in
     // order, conn[a][b] sources uniformly with replacement; draw m of target j

@@ -34,8 +34,33 @@ struct HostNet {
   std::vector<double> y0;                // [N]
 };
 
-// Validates the configuration and builds the whole network.  Returns an
-// mc_status; on failure `err` holds a message.
-int build_host(const mc_config& cfg, HostNet& net, std::string& err);
+// One instance of the pairwise Bernoulli rule, as a connection builder on
+// another processor sees it: source i connects to target j (local ids) iff
+// the upper 32 bits of word j&3 of the Philox block keyed (i, j>>2, 0, CONN)
+// are below thr[pop(j) * n_pops + pop(i)].
+struct BernoulliPlan {
+  int64_t N = 0;               // neurons of the instance
+  int n_pops = 0;
+  const int64_t* off = nullptr;    // [n_pops+1] local population offsets
+  const uint8_t* pop = nullptr;    // [N] local population of every neuron
+  const uint64_t* thr = nullptr;   // [n_pops*n_pops] floor(p * 2^32), [post][pre]
+  uint64_t seed = 0;
+  int64_t goff = 0;            // global id of the instance's first neuron
+};
+
+// Draws the connections of a Bernoulli instance elsewhere (the HIP device):
+// count() gives every source's number of targets, fill() every source's
+// targets (global ids, ascending) at row_ptr_local[i] - row_ptr_local[0] of
+// tgt.  Both must equal the host's draws bit for bit.
+struct ConnBuilder {
+  virtual ~ConnBuilder() = default;
+  virtual int count(const BernoulliPlan& plan, int64_t* counts, std::string& err) = 0;
+  virtual int fill(const BernoulliPlan& plan, const int64_t* row_ptr_local, int32_t* tgt, std::string& err) = 0;
+};
+
+// Validates the configuration and builds the whole network.  With `conn`,
+// the connections of the Bernoulli rule come from it (weights and delays
+// stay on the host).  Returns an mc_status; on failure `err` holds a message.
+int build_host(const mc_config& cfg, HostNet& net, std::string& err, ConnBuilder* conn = nullptr);
 
 }  // namespace mc

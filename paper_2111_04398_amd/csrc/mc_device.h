@@ -163,6 +163,10 @@ hipError_t launch_step(const DevNet& p, int offset, int qpw, int n_wg, int block
 hipError_t launch_advance(long long* step_base, int steps, hipStream_t s);
 hipError_t launch_inject(long long* ring, long long idx, long long value, hipStream_t s);
 hipError_t launch_set_weights(int32_t* wq, const double* w, long long M, hipStream_t s);
+// Connections of the Bernoulli rule drawn on the device (the host builder's
+// ConnBuilder; grid: workgroups of 256 threads; s: the stream it uses).
+struct ConnBuilder;
+ConnBuilder* new_device_conn(int grid, hipStream_t s);
 // Raster segments' used prefixes -> one contiguous array (off: [n_seg+1] exclusive prefix of the counts).
 hipError_t launch_raster_pack(const int2* raster, long long cap, const long long* off, int n_seg, int2* out,
                               hipStream_t s);

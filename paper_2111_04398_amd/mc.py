@@ -30,6 +30,7 @@ RULE_FIXED_INDEGREE, RULE_BERNOULLI = 0, 1
 GRAD_F64, GRAD_F32 = 0, 1
 ADJ_INPUT_AUTO, ADJ_INPUT_RECORD, ADJ_INPUT_REPLAY = 0, 1, 2
 FLAG_HOST_ONLY = 1
+FLAG_DEVICE_CONNECT = 2
 SCHEME_STEP_KERNELS, SCHEME_PERSISTENT_LDS, SCHEME_TARGET_OWNER = 0, 1, 2
 
 ERROR_NAMES = {0: "MC_OK", -1: "MC_ERR_INVALID_ARG", -2: "MC_ERR_RANGE", -3: "MC_ERR_OOM", -4: "MC_ERR_HIP",
@@ -155,7 +156,8 @@ def _arr(a, dt):
 class Network:
     """An ``mc_net`` handle: build, simulate, observe, differentiate."""
 
-    def __init__(self, w: Workload, host_only: bool = False, stream: Optional[int] = None):
+    def __init__(self, w: Workload, host_only: bool = False, stream: Optional[int] = None,
+                 device_connect: bool = False):
         self.workload = w
         n = w.n_pops
         self._keep = [
@@ -188,7 +190,7 @@ class Network:
         c.inst_scale = scales.ctypes.data_as(C.POINTER(C.c_double))
         c.inst_seed = seeds.ctypes.data_as(C.POINTER(C.c_uint64))
         c.hip_stream = stream
-        c.flags = FLAG_HOST_ONLY if host_only else 0
+        c.flags = (FLAG_HOST_ONLY if host_only else 0) | (FLAG_DEVICE_CONNECT if device_connect else 0)
         h = C.c_void_p()
         _check(lib().mc_build_network(C.byref(c), C.byref(h)), "mc_build_network")
         self.h = h

@@ -145,6 +145,36 @@ def test_persistent_scheme_at_its_largest_shape():
     assert_same(net, o, ring_depth=16, what="max persistent")
 
 
+@pytest.mark.parametrize("name", ["tiny_bernoulli", "adjoint_small", "batched_4", "balanced", "microcircuit"])
+def test_device_connection_drawing_builds_the_same_network(name):
+    """MC_FLAG_DEVICE_CONNECT draws the Bernoulli pair tests on the device;
+    the synapse store (rows, targets, weights, delays) equals the host
+    build's bit for bit, and so does the trajectory.  The fixed in-degree
+    rule (balanced) ignores the flag."""
+    w = {"tiny_bernoulli": tiny_bernoulli, "adjoint_small": workloads.adjoint_small,
+         "batched_4": lambda: workloads.batched(n_instances=4, sim_steps=300),
+         "balanced": workloads.balanced, "microcircuit": workloads.microcircuit}[name]()
+    a = mc.Network(w)
+    b = mc.Network(w, device_connect=True)
+    sa, sb = a.synapses(), b.synapses()
+    for x, y in zip(sa, sb):
+        assert x.dtype == y.dtype and np.array_equal(x, y), name
+    del sa, sb
+    for net in (a, b):
+        net.set_launch(scheme=0, block=256, neurons_per_wg=256, steps_per_graph=100)
+        net.simulate(200)
+    s0, i0 = a.spikes()
+    s1, i1 = b.spikes()
+    assert np.array_equal(s0, s1) and np.array_equal(i0, i1)
+    assert np.array_equal(a.state()[0].view(np.uint64), b.state()[0].view(np.uint64))
+
+
+def test_device_connection_drawing_refuses_host_only():
+    with pytest.raises(mc.MCError) as e:
+        mc.Network(tiny_bernoulli(), host_only=True, device_connect=True)
+    assert e.value.code == mc.MC_ERR_INVALID_ARG
+
+
 @pytest.mark.parametrize("mk", [tiny_fixed, tiny_bernoulli])
 def test_tiny_networks_persistent(mk):
     w = mk()
