@@ -153,7 +153,8 @@ enum { MC_ADJ_INPUT_AUTO = 0, MC_ADJ_INPUT_RECORD = 1, MC_ADJ_INPUT_REPLAY = 2 }
 
 /* --- the four calls of the simulation --------------------------------- */
 
-/* Builds the network on the host (OpenMP), derives propagators and drive
+/* Builds the network on the host (OpenMP; with MC_FLAG_DEVICE_CONNECT the
+ * connection draws of MC_RULE_BERNOULLI on the device), derives propagators and drive
  * tables, uploads everything to the current HIP device.  Untimed
  * instantiation of the Methods section.  *out receives the handle (NULL on
  * failure).  Errors: INVALID_ARG (inconsistent config), RANGE (a quantised
