@@ -121,6 +121,11 @@ struct mc_net {
   // input record of an adjoint's forward (owned by that mc_adjoint call)
   long long* d_xrec = nullptr;
   long long xrec_step0 = 0, xrec_steps = 0;
+  // checkpoints of an adjoint's forward, stored by the update kernels
+  double* d_ck_y = nullptr;
+  double* d_ck_I = nullptr;
+  int32_t* d_ck_r = nullptr;
+  long long ck_step0 = 0, ck_every = 1, ck_count = 0;
   unsigned long long* d_phase = nullptr;
   bool phase_on = false;
   std::vector<double> phase_wg;        // per-workgroup phase times (us/step) of the last mc_profile_phases
@@ -172,6 +177,8 @@ struct mc_net {
     p.wg_events = d_wg_events; p.wg_spikes = d_wg_spikes; p.overflow = d_overflow;
     p.n_inst = h.n_inst; p.qinst = d_qinst; p.inst_base = d_inst_base; p.ilist = d_ilist; p.icnt = d_icnt;
     p.xrec = d_xrec; p.xrec_step0 = xrec_step0; p.xrec_steps = xrec_steps;
+    p.ck_y = d_ck_y; p.ck_I = d_ck_I; p.ck_r = d_ck_r;
+    p.ck_step0 = ck_step0; p.ck_every = ck_every; p.ck_count = ck_count;
     return p;
   }
 
@@ -1291,26 +1298,33 @@ int mc_adjoint(mc_net* n, const mc_adjoint_config* a, void* grad, double* loss) 
   HIP_TRY(hipMemsetAsync(mismatch, 0, sizeof(unsigned), n->stream));
   HIP_TRY(hipMemsetAsync(grad, 0, (fp32 ? sizeof(float) : sizeof(double)) * (size_t)M, n->stream));
 
-  // forward: checkpoint, then K steps, per segment (direct launches: a
-  // captured graph would carry the record-off arguments)
+  // forward (direct launches: a captured graph would carry the record-off
+  // arguments).  Record mode: the whole window at once, the update kernels
+  // storing the input record and the checkpoints.  Replay mode: checkpoint
+  // (state and ring), then K steps, per segment.
   HIP_TRY(hipEventRecord(n->ev0, n->stream));
   const int spg = n->launch.steps_per_graph;
   if (record) {
     n->launch.steps_per_graph = 0;
     n->d_xrec = xrec; n->xrec_step0 = n0; n->xrec_steps = S;
+    n->d_ck_y = ck_y; n->d_ck_I = ck_I; n->d_ck_r = ck_r;
+    n->ck_step0 = n0; n->ck_every = K; n->ck_count = nseg;
+    if ((rc = enqueue_steps(n, S)) != MC_OK) n->failed = true;
   }
-  for (int64_t k = 0; k < nseg && rc == MC_OK; ++k) {
+  for (int64_t k = 0; !record && k < nseg && rc == MC_OK; ++k) {
     const int64_t len = std::min(K, S - k * K);
     hipError_t e = hipMemcpyAsync(ck_y + k * st, n->d_y, sizeof(double) * n->n_pad, hipMemcpyDeviceToDevice, n->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(ck_I + k * st, n->d_I, sizeof(double) * n->n_pad, hipMemcpyDeviceToDevice, n->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(ck_r + k * st, n->d_r, sizeof(int32_t) * n->n_pad, hipMemcpyDeviceToDevice, n->stream);
-    if (e == hipSuccess && !record)
+    if (e == hipSuccess)
       e = hipMemcpyAsync(ck_ring + k * ring_elems, n->d_ring, sizeof(long long) * ring_elems, hipMemcpyDeviceToDevice,
                          n->stream);
     if (e != hipSuccess) rc = set_error(MC_ERR_HIP, std::string("checkpoint copy: ") + hipGetErrorString(e));
     else if ((rc = enqueue_steps(n, len)) != MC_OK) n->failed = true;
   }
   n->d_xrec = nullptr; n->xrec_step0 = 0; n->xrec_steps = 0;
+  n->d_ck_y = nullptr; n->d_ck_I = nullptr; n->d_ck_r = nullptr;
+  n->ck_step0 = 0; n->ck_every = 1; n->ck_count = 0;
   n->launch.steps_per_graph = spg;
   if (rc != MC_OK) return rc;
   HIP_TRY(hipEventRecord(n->ev_mid, n->stream));

@@ -50,6 +50,15 @@ struct DevNet {
   long long* xrec;
   long long xrec_step0;
   long long xrec_steps;
+  // adjoint forward: when ck_y is set, the state (y, I, r) of every neuron
+  // before the update of step ck_step0 + k * ck_every (k < ck_count) goes to
+  // ck_*[k * ring_stride + i]
+  double* ck_y;
+  double* ck_I;
+  int32_t* ck_r;
+  long long ck_step0;
+  long long ck_every;
+  long long ck_count;
   // target-owner scheme: per-instance spike lists of the current step
   int32_t n_inst;
   const int32_t* qinst;     // [n_quads] instance of each quad

@@ -83,6 +83,17 @@ __global__ __launch_bounds__(kMaxBlock) void k_step(DevNet p, int offset, int qp
     const double2 ya = *reinterpret_cast<const double2*>(yq), yb = *reinterpret_cast<const double2*>(yq + 2);
     const double2 ia = *reinterpret_cast<const double2*>(Iq), ib = *reinterpret_cast<const double2*>(Iq + 2);
     const int4 r4 = *reinterpret_cast<const int4*>(rq);
+    if (p.ck_y) {                        // adjoint forward: checkpoint before the update
+      const int k = (int)(n - p.ck_step0), every = (int)p.ck_every;   // windows hold at most 1e6 steps
+      if (k >= 0 && k % every == 0 && k / every < p.ck_count) {
+        const size_t at = (size_t)(k / every) * p.ring_stride + 4 * q;
+        *reinterpret_cast<double2*>(p.ck_y + at) = ya;
+        *reinterpret_cast<double2*>(p.ck_y + at + 2) = yb;
+        *reinterpret_cast<double2*>(p.ck_I + at) = ia;
+        *reinterpret_cast<double2*>(p.ck_I + at + 2) = ib;
+        *reinterpret_cast<int4*>(p.ck_r + at) = r4;
+      }
+    }
     double y[4] = {ya.x, ya.y, yb.x, yb.y};
     double I[4] = {ia.x, ia.y, ib.x, ib.y};
     int r[4] = {r4.x, r4.y, r4.z, r4.w};

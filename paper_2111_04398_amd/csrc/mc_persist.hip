@@ -334,6 +334,14 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
     pbs[r] = (h < a.G) ? a.bstart[h] : 0;
   }
   long long rcnt = p.raster_cnt[g];
+  // checkpoint schedule of an adjoint's forward: segment of step n0 and n0's
+  // phase in it (a checkpoint is due at phase 0)
+  long long ck_seg = -1, ck_phase = 1;
+  if (p.ck_y) {
+    const long long k = n0 - p.ck_step0;
+    ck_seg = (k >= 0) ? k / p.ck_every : -1;
+    ck_phase = (k >= 0) ? k % p.ck_every : 1;
+  }
   long long ph[7] = {0, 0, 0, 0, 0, 0, 0};
   int S1 = 0;                           // spikes of step n-1: ids kept, block bounds due
   int S2 = 0;                           // spikes of step n-2: bounds kept, entries due
@@ -355,6 +363,13 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
     const int par = (int)(n & 1);
     // ---- update -----------------------------------------------------------
     int spiked = 0;
+    if (p.ck_y) {                         // adjoint forward: checkpoint before the update
+      if (upd && ck_phase == 0 && ck_seg >= 0 && ck_seg < p.ck_count) {
+        const size_t at = (size_t)ck_seg * p.ring_stride + j0 + tid;
+        p.ck_y[at] = y; p.ck_I[at] = I; p.ck_r[at] = r;
+      }
+      if (++ck_phase == p.ck_every) { ck_phase = 0; ++ck_seg; }
+    }
     if (upd) {
       const int fslot = (int)(n & kRingMask);
       const int jl = tid;
