@@ -93,6 +93,42 @@ def test_launch_configuration_invariance(scheme, block, npw, spg):
     assert_same(net, o, what=f"{scheme},{block},{npw},{spg}")
 
 
+# the launch shapes mc_tune times (same list and steps per graph)
+TUNER_CANDIDATES = [(1, 512, 0, 10000), (1, 256, 0, 10000), (1, 512, 256, 10000), (1, 512, 512, 10000),
+                    (1, 256, 128, 10000), (2, 256, 256, 1000), (2, 256, 128, 1000), (2, 256, 64, 1000),
+                    (0, 256, 256, 1000), (0, 256, 1024, 1000), (0, 512, 512, 1000), (0, 128, 128, 1000)]
+
+
+def test_every_autotuner_candidate_gives_the_same_bits():
+    """Whatever mc_tune picks, the trajectory is the oracle's: every
+    candidate shape, run from the same state, gives identical bits."""
+    w = workloads.balanced()
+    o = oracle.Oracle(w.to_dict())
+    o.run(900)
+    for c in TUNER_CANDIDATES:
+        net = mc.Network(w)
+        net.set_launch(scheme=c[0], block=c[1], neurons_per_wg=c[2], steps_per_graph=c[3])
+        net.simulate(900)
+        assert_same(net, o, ring_depth=128, what=f"candidate {c}")
+        net.close()
+
+
+@pytest.mark.parametrize("scheme", [0, 1, 2])
+def test_all_delays_one_step(scheme):
+    """Every synapse with the smallest delay (one step): every event must be
+    in place by the next update, so a missing wait anywhere in the exchange
+    would show.  In the persistent scheme every event takes the near path."""
+    w = workloads.balanced().replace(name="delay1", d_max_steps=1)
+    net, o = mc.Network(w), oracle.Oracle(w.to_dict())
+    assert set(np.unique(net.synapses()[3])) == {1}
+    net.set_launch(scheme=scheme, block=512 if scheme == 1 else 256, neurons_per_wg=0 if scheme == 1 else 256,
+                   steps_per_graph=100)
+    net.simulate(1000)
+    o.run(1000)
+    assert o.counters()[1] > 1_000_000
+    assert_same(net, o, what=f"delay1 {scheme}")
+
+
 @pytest.mark.parametrize("scheme,block,npw,spg", [(0, 256, 256, 100), (1, 512, 0, 100), (1, 256, 64, 7),
                                                    (2, 256, 256, 100)])
 def test_synchronous_bursts(scheme, block, npw, spg):
