@@ -228,7 +228,10 @@ int mc_get_propagators(mc_net* net, double* p_host /* [4] */);
 /* Poisson inverse-CDF tables [n_pops][64] of instance 0 (tables are the same for every instance). */
 int mc_get_drive_tables(mc_net* net, uint64_t* t_host);
 int mc_get_counters(mc_net* net, mc_counters* out);
-/* Launch configuration; a change never changes results (integer sums). */
+/* Launch configuration; a change never changes results (integer sums).  A
+ * shape the device cannot run (RANGE, INVALID_ARG) leaves the current one;
+ * a failure while the new shape's tables are built (OOM, HIP) marks the
+ * handle failed. */
 int mc_set_launch(mc_net* net, const mc_launch* l);
 int mc_get_launch(mc_net* net, mc_launch* l);
 /* Times candidate launch configurations on copies of the current state for
@@ -271,8 +274,10 @@ int mc_last_simulate_ms(mc_net* net, double* ms_out);
  * (S steps with checkpoints) and its reverse pass (recompute, adjoint,
  * gather). */
 int mc_last_adjoint_ms(mc_net* net, double* forward_ms_out, double* reverse_ms_out);
-/* Makes room for the spikes of `steps` further steps so that mc_simulate
- * allocates nothing for them. */
+/* Makes room for the spikes of `steps` further steps (at most 2e6) so that
+ * mc_simulate allocates nothing for them; the room is the worst-case bound
+ * (one spike per refractory period per neuron).  OOM leaves the room there
+ * was, and the handle usable. */
 int mc_reserve(mc_net* net, int64_t steps);
 /* Full dynamic state (step, y, I, r, ring, counters) to/from a host blob. */
 int mc_save_state(mc_net* net, void* blob_host, size_t capacity, size_t* used_out);

@@ -45,6 +45,7 @@ int dev_alloc(T** p, size_t count) {
   hipError_t e = hipMalloc((void**)p, count * sizeof(T));
   if (e != hipSuccess) {
     *p = nullptr;
+    (void)hipGetLastError();   // the runtime keeps the failure as its last error: the next launch check would see it
     return set_error(e == hipErrorOutOfMemory ? MC_ERR_OOM : MC_ERR_HIP,
                      std::string("hipMalloc of ") + std::to_string(count * sizeof(T)) + " bytes: " + hipGetErrorString(e));
   }
@@ -345,20 +346,34 @@ int setup_recording(mc_net* n, int64_t steps) {
   if ((rc = fold_counters(n)) != MC_OK) return rc;
   // a captured graph holds the old buffer addresses
   if (n->graph) { (void)hipGraphExecDestroy(n->graph); n->graph = nullptr; }
+  const int64_t old_steps = n->cap_steps;
   release_recording(n);
-  const int64_t neurons = n->wg_neurons;
-  n->raster_cap = spike_bound(neurons, steps, n->h.ref_steps) + 1;
-  n->cap_steps = steps;
-  if ((rc = dev_alloc(&n->d_raster, (size_t)n->n_wg * n->raster_cap)) != MC_OK) return rc;
-  if ((rc = dev_alloc(&n->d_raster_cnt, (size_t)n->n_wg)) != MC_OK) return rc;
-  if ((rc = dev_alloc(&n->d_wg_events, (size_t)n->n_wg)) != MC_OK) return rc;
-  if ((rc = dev_alloc(&n->d_wg_spikes, (size_t)n->n_wg * n->h.n_pops)) != MC_OK) return rc;
+  auto alloc = [&](int64_t s) {
+    n->raster_cap = spike_bound(n->wg_neurons, s, n->h.ref_steps) + 1;
+    n->cap_steps = s;
+    int r = dev_alloc(&n->d_raster, (size_t)n->n_wg * n->raster_cap);
+    if (r == MC_OK) r = dev_alloc(&n->d_raster_cnt, (size_t)n->n_wg);
+    if (r == MC_OK) r = dev_alloc(&n->d_wg_events, (size_t)n->n_wg);
+    if (r == MC_OK) r = dev_alloc(&n->d_wg_spikes, (size_t)n->n_wg * n->h.n_pops);
+    if (r != MC_OK) { release_recording(n); n->cap_steps = 0; n->raster_cap = 0; }
+    return r;
+  };
+  if ((rc = alloc(steps)) != MC_OK) {
+    // keep the handle usable with the capacity it had, if there was one
+    const std::string msg = g_last_error;
+    if (old_steps > 0 && old_steps < steps && alloc(old_steps) == MC_OK) {
+      rc = set_error(rc, msg + " (recording capacity left at " + std::to_string(old_steps) + " steps)");
+    } else {
+      n->failed = true;
+      return rc;
+    }
+  }
   HIP_TRY(hipMemsetAsync(n->d_raster_cnt, 0, sizeof(long long) * n->n_wg, n->stream));
   HIP_TRY(hipMemsetAsync(n->d_wg_events, 0, sizeof(unsigned long long) * n->n_wg, n->stream));
   HIP_TRY(hipMemsetAsync(n->d_wg_spikes, 0, sizeof(unsigned long long) * n->n_wg * n->h.n_pops, n->stream));
   HIP_TRY(hipStreamSynchronize(n->stream));
   n->steps_since_drain = 0;
-  return MC_OK;
+  return rc;
 }
 
 int validate_launch(const mc_net* n, const mc_launch& l) {
@@ -492,6 +507,12 @@ int apply_launch(mc_net* n, const mc_launch& l) {
     n->graph = nullptr;
   }
   if (shape_changed || !n->d_raster) {
+    // the old shape's buffers go first: a failure from here on leaves no
+    // consistent shape, so it marks the handle failed
+    struct FailGuard {
+      mc_net* n; bool armed = true;
+      ~FailGuard() { if (armed) n->failed = true; }
+    } guard{n};
     if ((rc = drain(n)) != MC_OK) return rc;
     if ((rc = fold_counters(n)) != MC_OK) return rc;
     release_recording(n);   // sized for the old shape
@@ -530,6 +551,7 @@ int apply_launch(mc_net* n, const mc_launch& l) {
     n->wg_neurons = wg_neurons;
     n->pG = G; n->pB = B; n->pDL = DL;
     n->launch = l;
+    guard.armed = false;   // setup_recording keeps the handle usable on its own failures where it can
     if ((rc = setup_recording(n, std::max<int64_t>(n->cap_steps, 4096))) != MC_OK) return rc;
   }
   n->launch = l;

@@ -205,6 +205,25 @@ def test_device_connection_drawing_builds_the_same_network(name):
     assert np.array_equal(a.state()[0].view(np.uint64), b.state()[0].view(np.uint64))
 
 
+def test_recording_allocation_failure_keeps_the_handle_usable():
+    """A raster reservation beyond device memory (2e6 steps of the 64-instance
+    batch: ~570 GB at the worst-case spike bound) returns MC_ERR_OOM and
+    leaves the previous capacity in place: the network then simulates exactly
+    as an untouched twin does."""
+    w = workloads.batched(sim_steps=300)
+    net = mc.Network(w, device_connect=True)
+    twin = mc.Network(w, device_connect=True)
+    with pytest.raises(mc.MCError) as e:
+        net.reserve(2_000_000)
+    assert e.value.code == -3 and "capacity left" in str(e.value)
+    for x in (net, twin):
+        x.simulate(300)
+    s0, i0 = net.spikes()
+    s1, i1 = twin.spikes()
+    assert len(s0) > 0 and np.array_equal(s0, s1) and np.array_equal(i0, i1)
+    assert net.counters()["events"] == twin.counters()["events"]
+
+
 def test_device_connection_drawing_refuses_host_only():
     with pytest.raises(mc.MCError) as e:
         mc.Network(tiny_bernoulli(), host_only=True, device_connect=True)
