@@ -27,10 +27,13 @@ int set_error(int code, const std::string& msg) {
   return code;
 }
 
+// On failure the runtime's last-error state is read and cleared as well, so
+// that a later launch check does not report this failure again.
 #define HIP_TRY(expr)                                                                      \
   do {                                                                                     \
     hipError_t e__ = (expr);                                                               \
     if (e__ != hipSuccess) {                                                               \
+      (void)hipGetLastError();                                                             \
       return set_error(e__ == hipErrorOutOfMemory ? MC_ERR_OOM : MC_ERR_HIP,               \
                        std::string(#expr) + ": " + hipGetErrorString(e__));                \
     }                                                                                      \
