@@ -523,7 +523,7 @@ int apply_launch(mc_net* n, const mc_launch& l) {
       dev_free(n->d_blk); dev_free(n->d_flags); dev_free(n->d_pub); dev_free(n->d_bstart);
       if ((rc = dev_alloc(&n->d_blk, (size_t)n->n_pad * (G + 1))) != MC_OK) return rc;
       if ((rc = dev_alloc(&n->d_flags, persist_flag_words(G))) != MC_OK) return rc;
-      if ((rc = dev_alloc(&n->d_pub, (size_t)G * 2 * B)) != MC_OK) return rc;
+      if ((rc = dev_alloc(&n->d_pub, (size_t)G * kRecSlots * B)) != MC_OK) return rc;
       if ((rc = dev_alloc(&n->d_bstart, (size_t)G + 1)) != MC_OK) return rc;
       HIP_TRY(hipMemcpy(n->d_bstart, bs.data(), sizeof(int) * (G + 1), hipMemcpyHostToDevice));
       n->bstart_host = bs;

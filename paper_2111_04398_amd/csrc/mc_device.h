@@ -79,8 +79,8 @@ struct PersistArgs {
   int DL;                      // near slots held in LDS (2..101)
   int BW;                      // 32-bit words per far-bitmap row: ceil(B/32)
   const long long* blk;        // [n_pad][G+1] first synapse of each row with target >= bstart[g]
-  unsigned long long* flags;   // [G][2][8] spike records: (tag << 32) | count, (tag << 32) | id x7
-  int* pub;                    // [G][2][B] published spike ids
+  unsigned long long* flags;   // [G][kRecSlots][8] spike records by step mod kRecSlots
+  int* pub;                    // [G][kRecSlots][B] published spike ids beyond the seventh
   long long spin_limit;        // polls before giving up
   unsigned long long* phase;   // optional [G*8]: summed wall_clock64 ticks per phase (nullptr: off)
   // near table: the delay-1/2 synapses of row i into workgroup g's block are
@@ -91,7 +91,8 @@ struct PersistArgs {
   const unsigned long long* ne;
 };
 constexpr int kPersistFlagStride = 8;
-inline size_t persist_flag_words(int G) { return (size_t)G * 2 * kPersistFlagStride; }
+constexpr int kRecSlots = 4;            // spike records (and side arrays) per workgroup, by step mod 4
+inline size_t persist_flag_words(int G) { return (size_t)G * kRecSlots * kPersistFlagStride; }
 constexpr int kPersistMaxB = 512;       // owned targets per workgroup (one per thread)
 constexpr int kPersistMaxBlock = 512;   // threads per workgroup: 256 VGPRs per lane, no scratch spills
 size_t persist_lds_bytes(int G, int B, int DL);

@@ -353,73 +353,71 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
 
-  for (int it = 0; it < steps; ++it) {
-    const long long n = n0 + it;
-    const bool timing = (a.phase != nullptr) && tid == 0;
-    long long tp0 = timing ? wall_clock64() : 0;
-    const int sn1 = (sn + 1 == DL) ? 0 : sn + 1;
-    const int sn2 = (sn1 + 1 == DL) ? 0 : sn1 + 1;
-    const int snm2 = (sn >= 2) ? sn - 2 : sn - 2 + DL;   // slot of step n-2
-    const int par = (int)(n & 1);
-    // ---- update -----------------------------------------------------------
-    int spiked = 0;
-    if (p.ck_y) {                         // adjoint forward: checkpoint before the update
+  // The update of step m splits in two.  Its spike decision moves y and r
+  // with the I of before the step, so it does not need the input read at
+  // step m; only I = P11 I + x does.  The spike decision of step m+1 and its
+  // record therefore go out before the wait for step m's records, and every
+  // workgroup can run up to one step ahead of the slowest.
+  auto decide = [&](long long m) -> int {     // spike decision of step m
+    if (p.ck_y) {                           // adjoint forward: checkpoint before the update
       if (upd && ck_phase == 0 && ck_seg >= 0 && ck_seg < p.ck_count) {
         const size_t at = (size_t)ck_seg * p.ring_stride + j0 + tid;
         p.ck_y[at] = y; p.ck_I[at] = I; p.ck_r[at] = r;
       }
       if (++ck_phase == p.ck_every) { ck_phase = 0; ++ck_seg; }
     }
-    if (upd) {
-      const int fslot = (int)(n & kRingMask);
-      const int jl = tid;
-      long long x_int = acc[(size_t)sn * a.B + jl];
-      acc[(size_t)sn * a.B + jl] = 0;
-      unsigned* fb = &fbits[fslot * a.BW + (jl >> 5)];
-      if (*fb & (1u << (jl & 31))) {
-        atomicAnd(fb, ~(1u << (jl & 31)));
-        x_int += (long long)__hip_atomic_exchange(
-            reinterpret_cast<unsigned long long*>(p.ring + (size_t)fslot * p.ring_stride + j0 + jl), 0ull,
-            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int spiked = 0;
+    if (upd && pop != 0xFFu) {
+      const bool free_ = (r == 0);
+      if (free_) {
+        double yn = p.P22 * y + p.P21 * I;
+        if (p.i_e != 0.0) yn = yn + p.P20 * p.i_e;
+        y = yn;
+      } else {
+        r = r - 1;
       }
-      if (pop != 0xFFu) x_int += (long long)kdrive * p.jext_q;
-      if (p.xrec && n - p.xrec_step0 >= 0 && n - p.xrec_step0 < p.xrec_steps)
-        p.xrec[(size_t)(n - p.xrec_step0) * p.ring_stride + j0 + jl] = x_int;
-      if (pop != 0xFFu) {
-        const double x = (double)x_int * 0x1p-16;
-        const bool free_ = (r == 0);
-        if (free_) {
-          double yn = p.P22 * y + p.P21 * I;
-          if (p.i_e != 0.0) yn = yn + p.P20 * p.i_e;
-          y = yn;
-        } else {
-          r = r - 1;
-        }
-        I = p.P11 * I + x;
-        if (free_ && y >= p.theta) {
-          y = p.y_reset;
-          r = p.ref_steps;
-          spiked = 1;
-          atomicAdd(&s_popcnt[pop], 1ull);
-        }
+      if (free_ && y >= p.theta) {
+        y = p.y_reset;
+        r = p.ref_steps;
+        spiked = 1;
+        atomicAdd(&s_popcnt[pop], 1ull);
       }
     }
-    if (timing) { const long long t = wall_clock64(); ph[0] += t - tp0; tp0 = t; }
-    // ---- compaction (ascending ids) and publication --------------------------
-    if (tid == 0) { s_nids = 0; s_nbig = 0; }   // read after the previous wait; next used after this barrier
+    return spiked;
+  };
+  auto absorb = [&](long long m, int slot) {  // input of step m into I; its LDS slot cleared
+    if (!upd) return;
+    const int fslot = (int)(m & kRingMask);
+    const int jl = tid;
+    long long x_int = acc[(size_t)slot * a.B + jl];
+    acc[(size_t)slot * a.B + jl] = 0;
+    unsigned* fb = &fbits[fslot * a.BW + (jl >> 5)];
+    if (*fb & (1u << (jl & 31))) {
+      atomicAnd(fb, ~(1u << (jl & 31)));
+      x_int += (long long)__hip_atomic_exchange(
+          reinterpret_cast<unsigned long long*>(p.ring + (size_t)fslot * p.ring_stride + j0 + jl), 0ull,
+          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (pop != 0xFFu) x_int += (long long)kdrive * p.jext_q;
+    if (p.xrec && m - p.xrec_step0 >= 0 && m - p.xrec_step0 < p.xrec_steps)
+      p.xrec[(size_t)(m - p.xrec_step0) * p.ring_stride + j0 + jl] = x_int;
+    if (pop != 0xFFu) I = p.P11 * I + (double)x_int * 0x1p-16;
+  };
+  auto publish = [&](long long m, int spiked) {   // compaction (ascending ids), record of step m, raster
     int nloc;
     const int pre = block_exscan(spiked, s_tmp[0], &nloc);
     if (spiked) s_local[pre] = (int)(j0 + tid);
     __syncthreads();
-    const unsigned long long tag = (unsigned long long)(n + 1) << 32;
-    const unsigned long long tag16 = (unsigned long long)((n + 1) % 65535 + 1) << 48;
-    unsigned long long* myrec = a.flags + ((size_t)g * 2 + par) * kPersistFlagStride;   // double-buffered by parity
+    const unsigned long long tag = (unsigned long long)(m + 1) << 32;
+    const unsigned long long tag16 = (unsigned long long)((m + 1) % 65535 + 1) << 48;
+    const size_t rec = (size_t)g * kRecSlots + (size_t)(m % kRecSlots);
+    unsigned long long* myrec = a.flags + rec * kPersistFlagStride;
     for (int k = tid; k < nloc; k += nthr) {
       const int id = s_local[k];
-      if (k >= kInline) st_dev(&a.pub[((size_t)g * 2 + par) * a.B + k], id);
-      if (rcnt + nloc <= p.raster_cap) p.raster[(size_t)g * p.raster_cap + rcnt + k] = make_int2((int)n, id);
+      if (k >= kInline) st_dev(&a.pub[rec * a.B + k], id);
+      if (rcnt + nloc <= p.raster_cap) p.raster[(size_t)g * p.raster_cap + rcnt + k] = make_int2((int)m, id);
     }
-    if (nloc > kInline) {                 // side-array ids complete before word 0
+    if (nloc > kInline) {                   // side-array ids complete before word 0
       __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
     }
@@ -431,7 +429,34 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
     }
     if (rcnt + nloc <= p.raster_cap) rcnt += nloc;
     else if (tid == 0) atomicOr(p.overflow, 1u);
+  };
+
+  if (steps > 0) {                            // step n0's spike decision and record
+    const int sp = decide(n0);
+    publish(n0, sp);
+  }
+  for (int it = 0; it < steps; ++it) {
+    const long long n = n0 + it;
+    const bool timing = (a.phase != nullptr) && tid == 0;
+    long long tp0 = timing ? wall_clock64() : 0;
+    const int sn1 = (sn + 1 == DL) ? 0 : sn + 1;
+    const int sn2 = (sn1 + 1 == DL) ? 0 : sn1 + 1;
+    const int snm2 = (sn >= 2) ? sn - 2 : sn - 2 + DL;   // slot of step n-2
+    const int par = (int)(n & 1);
+    const size_t rslot = (size_t)(n % kRecSlots);        // record slot of step n
+    // ---- rest of the update of step n (its input into I), spike decision of
+    //      step n+1 ------------------------------------------------------------
+    absorb(n, sn);
+    int spiked = 0;
+    if (it + 1 < steps) spiked = decide(n + 1);
+    if (tid == 0) { s_nids = 0; s_nbig = 0; }   // read after the previous wait; next used after a barrier below
+    if (timing) { const long long t = wall_clock64(); ph[0] += t - tp0; tp0 = t; }
+    // ---- record of step n+1 ---------------------------------------------------
+    if (it + 1 < steps) publish(n + 1, spiked);
+    else __syncthreads();
     if (timing) { const long long t = wall_clock64(); ph[1] += t - tp0; tp0 = t; }
+    const unsigned long long tag = (unsigned long long)(n + 1) << 32;              // records of step n
+    const unsigned long long tag16 = (unsigned long long)((n + 1) % 65535 + 1) << 48;
     // ---- while the records of step n arrive: drive of step n+1 (updaters);
     //      block bounds of step n-1 and entries of step n-2 (working
     //      wavefronts); polling (poller wavefronts) -----------------------------
@@ -449,7 +474,8 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
         unsigned long long w0[kPollPerLane];
 #pragma unroll
         for (int r = 0; r < kPollPerLane; ++r)
-          w0[r] = ((todo >> r) & 1u) ? ld_dev(&a.flags[((size_t)(lane + 64 * r) * 2 + par) * kPersistFlagStride]) : 0ull;
+          w0[r] = ((todo >> r) & 1u) ? ld_dev(&a.flags[((size_t)(lane + 64 * r) * kRecSlots + rslot) * kPersistFlagStride])
+                                     : 0ull;
 #pragma unroll
         for (int r = 0; r < kPollPerLane; ++r) {
           if (!((todo >> r) & 1u) || (w0[r] & 0xFFFF000000000000ull) != tag16) continue;
@@ -459,7 +485,7 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
           unsigned long long wk[kInline - kW0Ids];
           bool ok = true;
           if (c > kW0Ids) {
-            const unsigned long long* rec = a.flags + ((size_t)h * 2 + par) * kPersistFlagStride;
+            const unsigned long long* rec = a.flags + ((size_t)h * kRecSlots + rslot) * kPersistFlagStride;
 #pragma unroll
             for (int k = 0; k < kInline - kW0Ids; ++k) wk[k] = ld_dev(&rec[1 + k]);
 #pragma unroll
@@ -555,7 +581,7 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
       if (nbig > 0) {
         for (int e = 0; e < nbig; ++e) {
           const int h = s_big[e].x, o = s_big[e].y, c = s_cnt[h];
-          for (int k = kInline + tid; k < c; k += nthr) ids_n[o + k] = ld_dev(&a.pub[((size_t)h * 2 + par) * a.B + k]);
+          for (int k = kInline + tid; k < c; k += nthr) ids_n[o + k] = ld_dev(&a.pub[((size_t)h * kRecSlots + rslot) * a.B + k]);
         }
         __syncthreads();
       }
@@ -588,7 +614,7 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
         int lo = 0, hi = a.G;                 // producer h: s_pre[h] <= gk < s_pre[h+1]
         while (hi - lo > 1) { const int mid = (lo + hi) >> 1; if (s_pre[mid] <= gk) lo = mid; else hi = mid; }
         const int kk = gk - s_pre[lo];
-        ids_n[k] = (kk < kInline) ? s_inl[lo * kInline + kk] : ld_dev(&a.pub[((size_t)lo * 2 + par) * a.B + kk]);
+        ids_n[k] = (kk < kInline) ? s_inl[lo * kInline + kk] : ld_dev(&a.pub[((size_t)lo * kRecSlots + rslot) * a.B + kk]);
       }
       if (timing) { const long long t = wall_clock64(); ph[3] += t - tp0; tp0 = t; }
       if (S <= kListCap) {
@@ -744,7 +770,7 @@ hipError_t persist_occupancy(int block, size_t lds, int* blocks_per_cu) {
 
 hipError_t launch_persist(const DevNet& p, const PersistArgs& a, int steps, int block, hipStream_t s) {
   const size_t lds = persist_lds_bytes(a.G, a.B, a.DL);
-  hipLaunchKernelGGL(k_zero_flags, dim3(1), dim3(256), 0, s, a.flags, a.G * 2 * kPersistFlagStride);
+  hipLaunchKernelGGL(k_zero_flags, dim3(1), dim3(256), 0, s, a.flags, (int)persist_flag_words(a.G));
   hipLaunchKernelGGL(k_persist, dim3(a.G), dim3(block), lds, s, p, a, steps);
   return hipGetLastError();
 }
