@@ -15,7 +15,9 @@
 // the spike list.
 //
 // Critical path.  Only the events of step n with delay 1 must be in place
-// before the update of step n+1, and those with delay 2 before step n+2.
+// before the input of step n+1 enters I, and those with delay 2 before step
+// n+2's.  (The spike decision of a step needs I from before the step, so it
+// runs one step earlier: see the loop.)
 // Both come from a "near" table (the delay-1/2 synapses per source and
 // workgroup, as a CSR), delivered right after the spike list of step n is
 // complete.  The other events are pipelined over the two following steps,
@@ -25,9 +27,9 @@
 // ids of each record as it arrives, so the list is complete when the wait
 // ends.
 //
-// Spike exchange: workgroup g publishes a record per step (two records per
-// workgroup, alternating by step parity, so a record is never rewritten while
-// a slower consumer may still be reading it).  Word 0 = tag16 << 48 | count
+// Spike exchange: workgroup g publishes a record per step (four per
+// workgroup, by step mod 4, so a record is never rewritten while a consumer
+// one step behind may still read it).  Word 0 = tag16 << 48 | count
 // << 36 | the block-local indices (9 bits each) of the first four spikes,
 // with tag16 = (step + 1) mod 65535 + 1 (never 0, distinct for consecutive
 // steps); words 1..3 = (step + 1) << 32 | id of spikes 5..7.  About four in
