@@ -79,12 +79,15 @@ def test_balanced_network_full_protocol():
 @pytest.mark.parametrize("scheme,block,npw,spg", [
     (0, 64, 64, 1), (0, 256, 256, 1000), (0, 256, 1024, 7), (0, 1024, 512, 333), (0, 128, 16, 50), (0, 256, 256, 0),
     (1, 512, 0, 1000), (1, 256, 0, 100), (1, 512, 64, 7), (1, 512, 512, 250), (1, 512, 200, 0), (1, 128, 24, 50),
+    (1, 64, 64, 50),
     (2, 256, 256, 1000), (2, 64, 16, 7), (2, 1024, 1024, 0), (2, 128, 100, 33)])
 def test_launch_configuration_invariance(scheme, block, npw, spg):
     """Every launch shape of every scheme gives identical bits (integer sums,
-    fixed FP order).  Persistent neurons_per_wg = 512 leaves room for only ~30
-    delay steps in LDS, so most events take the far (global) path; the
-    target-owner shapes range from 16 to 1024 targets per delivery block."""
+    fixed FP order).  (1, 64, 64) runs the persistent scheme with one
+    wavefront per workgroup, which polls and then delivers by itself.
+    Persistent neurons_per_wg = 512 leaves room for only ~30 delay steps in
+    LDS, so most events take the far (global) path; the target-owner shapes
+    range from 16 to 1024 targets per delivery block."""
     w = workloads.balanced()
     net, o = mc.Network(w), oracle.Oracle(w.to_dict())
     net.set_launch(scheme=scheme, block=block, neurons_per_wg=npw, steps_per_graph=spg)
