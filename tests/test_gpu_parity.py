@@ -277,6 +277,46 @@ def test_resume_and_checkpoint():
     assert np.array_equal(s_first, s2) and np.array_equal(i_first, i2)
 
 
+def test_short_rewinds_onto_other_states():
+    """Loading a state a few steps back, alternately the network's own and
+    that of another seed (same shape), then simulating: every run matches
+    the oracle started from that state.  In the persistent scheme the spike
+    records of the abandoned steps carry the same step tags as the steps
+    simulated again, so they must not survive the load."""
+    wa, wb = workloads.balanced(seed=1), workloads.balanced(seed=2)
+    a, b = mc.Network(wa), mc.Network(wb)
+    for net in (a, b):
+        net.set_launch(scheme=1, block=512, neurons_per_wg=0, steps_per_graph=1000)
+        net.simulate(100)
+    blob_a, blob_b = a.save_state(), b.save_state()
+    # expected: seed-1 network continued from its own state and from seed 2's
+    own = oracle.Oracle(wa.to_dict())
+    own.run(100)
+    other = oracle.Oracle(wa.to_dict())
+    other.run(100)
+    other.set_state(*b.state())
+    diff = b.ring() - other.ring()
+    for k, i in zip(*np.nonzero(diff)):
+        other.inject(int(k), int(i), int(diff[k, i]))
+    assert np.array_equal(other.ring(), b.ring())
+    runs = 4
+    own.run(runs)
+    other.run(runs)
+    expect = {}
+    for name, o in (("own", own), ("other", other)):
+        s, i = o.raster()
+        keep = s >= 100
+        expect[name] = (s[keep], i[keep])
+    for rep in range(8):
+        name = ("other", "own")[rep % 2]
+        a.load_state(blob_b if name == "other" else blob_a)
+        a.simulate(1 + rep % runs)
+        s, i = a.spikes(100, 200)
+        es, ei = expect[name]
+        m = es < 100 + 1 + rep % runs
+        assert np.array_equal(s, es[m]) and np.array_equal(i, ei[m]), (rep, name)
+
+
 @pytest.mark.parametrize("scheme", [0, 1, 2])
 def test_batched_instances_match_standalone(scheme):
     """Instances of a batch are bit-identical to their standalone runs, in
