@@ -1064,12 +1064,6 @@ int mc_load_state(mc_net* n, const void* blob, size_t size) {
   HIP_TRY(hipMemcpy(n->d_ring, o, sizeof(long long) * kRingSlots * n->ring_stride, hipMemcpyHostToDevice));
   long long st = hd.step;
   HIP_TRY(hipMemcpy(n->d_step, &st, sizeof(long long), hipMemcpyHostToDevice));
-  // The persistent scheme's spike records are tagged with their step only:
-  // after a rewind, records a run left beyond the restored step would match
-  // steps about to be simulated again (from another state), so they go.
-  if (n->d_flags && n->bstart_host.size() > 1)
-    HIP_TRY(hipMemsetAsync(n->d_flags, 0, sizeof(unsigned long long) * persist_flag_words((int)n->bstart_host.size() - 1),
-                           n->stream));
   n->step = hd.step;
   // counters: base = saved totals, device accumulators cleared
   HIP_TRY(hipMemset(n->d_wg_events, 0, sizeof(unsigned long long) * n->n_wg));

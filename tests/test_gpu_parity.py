@@ -282,7 +282,7 @@ def test_short_rewinds_onto_other_states():
     that of another seed (same shape), then simulating: every run matches
     the oracle started from that state.  In the persistent scheme the spike
     records of the abandoned steps carry the same step tags as the steps
-    simulated again, so they must not survive the load."""
+    simulated again; they are cleared before every launch."""
     wa, wb = workloads.balanced(seed=1), workloads.balanced(seed=2)
     a, b = mc.Network(wa), mc.Network(wb)
     for net in (a, b):
