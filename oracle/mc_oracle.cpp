@@ -334,8 +334,9 @@ int poisson_count(const Net& n, int64_t step, int64_t i) {
 // this step's input slot), then deliver every spike of the step through its
 // source's synapses into the slot `delay` steps ahead.
 void run_one_step(Net& n, std::vector<int64_t>* x_record, std::vector<uint8_t>* type_record,
-                  std::vector<double>* y_record) {
+                  std::vector<double>* y_record, int64_t rec0 = 0) {
   const int64_t s = n.step;
+  const int64_t row = s - rec0;                   // record row of this step
   std::vector<int64_t>& slot = n.ring[(size_t)(s % n.D)];
   std::vector<uint8_t> spiked((size_t)n.N, 0);
   const double Ie = n.cfg.i_e;
@@ -360,9 +361,9 @@ void run_one_step(Net& n, std::vector<int64_t>* x_record, std::vector<uint8_t>* 
       n.r[i] = n.ref_steps;
       type = 1;
     }
-    if (x_record) (*x_record)[(size_t)s * n.N + i] = x_int;
-    if (type_record) (*type_record)[(size_t)s * n.N + i] = type;
-    if (y_record) (*y_record)[(size_t)(s + 1) * n.N + i] = n.y[i];
+    if (x_record) (*x_record)[(size_t)row * n.N + i] = x_int;
+    if (type_record) (*type_record)[(size_t)row * n.N + i] = type;
+    if (y_record) (*y_record)[(size_t)(row + 1) * n.N + i] = n.y[i];
   }
   for (int64_t i = 0; i < n.N; ++i) {
     if (!spiked[i]) continue;
@@ -548,8 +549,11 @@ void orc_counters(void* h, int64_t* spikes_per_pop, int64_t* events) {
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint of L = 1/(N*S) * sum_i sum_{n<S} (y_i(n+1) - y*)^2 over a window of S
-// steps from a freshly initialised network, spikes frozen.  Step n maps
+// Adjoint of L = 1/(N*S) * sum_i sum_{n<S} (y_i(n+1) - y*)^2 over the window of
+// S steps that starts at the current step n0 (n counts from n0), spikes
+// frozen.  The state at n0, with the input still pending from spikes before
+// n0, is the fixed initial condition: only the window's own spikes carry
+// weights that the gradient sees.  Step n maps
 // (y_n, I_n) -> (y_{n+1}, I_{n+1}):
 //   free, no spike : y' = P22 y + P21 I,  I' = P11 I + x_n
 //   spike (reset)  : y' = y_reset (constant),  I' = P11 I + x_n
@@ -557,18 +561,18 @@ void orc_counters(void* h, int64_t* spikes_per_pop, int64_t* events) {
 // The adjoint runs backwards with lam = Ly_{n+1} + g_n, g_n = c*(y_{n+1}-y*),
 // c = 2/(N*S):  Ly_n = P22*lam | 0 | lam,  LI_n = P11*LI_{n+1} + [free]*P21*lam,
 // LI_S = Ly_S = 0.  A weight w_s (pA) of a synapse from i to j with delay d
-// enters x_j(t+d) for each spike (t, i), so dL/dw_s = sum_t LI_j(t+d+1),
-// accumulated per synapse in decreasing t.
+// enters x_j(t+d) for each spike (t, i) of the window, so dL/dw_s =
+// sum_t LI_j(t+d+1), accumulated per synapse in decreasing t.
 // grad_mode 0: double accumulation; 1: float accumulation g = f(g + f(LI)).
 // ---------------------------------------------------------------------------
 int orc_adjoint(void* h, int64_t S, double y_star_rel, int grad_mode, void* grad_out, double* loss_out) {
   Net* n = (Net*)h;
-  if (n->step != 0) return -1;
-  const int64_t N = n->N;
+  const int64_t N = n->N, n0 = n->step;
+  const int64_t q0 = (int64_t)n->raster_step.size();   // the window's spikes follow
   std::vector<double> yrec((size_t)(S + 1) * N);
   std::vector<uint8_t> types((size_t)S * N);
   for (int64_t i = 0; i < N; ++i) yrec[i] = n->y[i];
-  for (int64_t s = 0; s < S; ++s) run_one_step(*n, nullptr, &types, &yrec);
+  for (int64_t s = 0; s < S; ++s) run_one_step(*n, nullptr, &types, &yrec, n0);
   const double c = 2.0 / ((double)N * (double)S);
   double loss = 0.0;
   for (int64_t s = 0; s < S; ++s)
@@ -595,9 +599,9 @@ int orc_adjoint(void* h, int64_t S, double y_star_rel, int grad_mode, void* grad
   const int64_t M = n->row_ptr[N];
   if (grad_mode == 0) { double* g = (double*)grad_out; for (int64_t k = 0; k < M; ++k) g[k] = 0.0; }
   else { float* g = (float*)grad_out; for (int64_t k = 0; k < M; ++k) g[k] = 0.0f; }
-  // spikes in decreasing step order
-  for (int64_t q = (int64_t)n->raster_step.size() - 1; q >= 0; --q) {
-    int64_t t = n->raster_step[q], i = n->raster_id[q];
+  // the window's spikes in decreasing step order (t counted from n0)
+  for (int64_t q = (int64_t)n->raster_step.size() - 1; q >= q0; --q) {
+    int64_t t = n->raster_step[q] - n0, i = n->raster_id[q];
     for (int64_t k = n->row_ptr[i]; k < n->row_ptr[i + 1]; ++k) {
       int64_t m = t + n->dly[k] + 1;
       if (m > S - 1) continue;
@@ -612,29 +616,30 @@ int orc_adjoint(void* h, int64_t S, double y_star_rel, int grad_mode, void* grad
 // Central difference of the same loss with respect to the weight of synapse
 // k, in quad precision, spikes frozen: only target j's trajectory depends on
 // w_k, so it is recomputed from its recorded integer inputs with x_j(t+d)
-// shifted by +-eps pA at every arrival of synapse k inside the window.  The
-// network must be fresh; the forward is run here.  Returns results in `out`.
+// shifted by +-eps pA at every arrival, inside the window, from a spike of
+// the window (the window starts at the current step, as in orc_adjoint; the
+// forward is run here).  Returns results in `out`.
 int orc_fd(void* h, int64_t S, double y_star_rel, double eps, const int64_t* syn, int64_t count, double* out) {
   Net* n = (Net*)h;
-  if (n->step != 0) return -1;
-  const int64_t N = n->N;
+  const int64_t N = n->N, n0 = n->step;
+  const size_t q0 = n->raster_step.size();
   std::vector<int64_t> xrec((size_t)S * N);
   std::vector<uint8_t> types((size_t)S * N);
-  std::vector<double> y0(n->y);
-  for (int64_t s = 0; s < S; ++s) run_one_step(*n, &xrec, &types, nullptr);
+  std::vector<double> y0(n->y), I0(n->I);
+  for (int64_t s = 0; s < S; ++s) run_one_step(*n, &xrec, &types, nullptr, n0);
   for (int64_t q = 0; q < count; ++q) {
     int64_t k = syn[q];
     int64_t i = (int64_t)(std::upper_bound(n->row_ptr.begin(), n->row_ptr.end(), k) - n->row_ptr.begin()) - 1;
     int64_t j = n->tgt[k];
     int64_t d = n->dly[k];
     std::vector<uint8_t> hit((size_t)S, 0);
-    for (size_t z = 0; z < n->raster_step.size(); ++z)
-      if (n->raster_id[z] == i) { int64_t m = n->raster_step[z] + d; if (m <= S - 1) hit[m] = 1; }
+    for (size_t z = q0; z < n->raster_step.size(); ++z)
+      if (n->raster_id[z] == i) { int64_t m = n->raster_step[z] - n0 + d; if (m <= S - 1) hit[m] = 1; }
     __float128 P11 = n->P11, P21 = n->P21, P22 = n->P22, P20 = n->P20;
     __float128 Lpm[2];
     for (int sg = 0; sg < 2; ++sg) {
       __float128 e = (sg == 0) ? (__float128)eps : -(__float128)eps;
-      __float128 y = y0[j], I = 0, L = 0;
+      __float128 y = y0[j], I = I0[j], L = 0;
       for (int64_t s = 0; s < S; ++s) {
         __float128 x = (__float128)xrec[(size_t)s * N + j] / (__float128)65536.0;
         if (hit[s]) x += e;
@@ -653,17 +658,17 @@ int orc_fd(void* h, int64_t S, double y_star_rel, double eps, const int64_t* syn
   return 0;
 }
 
-// The recorded step types of neuron i after a forward of S steps from fresh
-// (0 free, 1 spike, 2 refractory) and its integer inputs: for tests.
+// The recorded step types of neuron i over a forward of S steps from the
+// current step (0 free, 1 spike, 2 refractory), its integer inputs and its
+// y before and after each step: for tests.
 int orc_trace(void* h, int64_t S, int64_t i, uint8_t* types_out, int64_t* x_out, double* y_out) {
   Net* n = (Net*)h;
-  if (n->step != 0) return -1;
-  const int64_t N = n->N;
+  const int64_t N = n->N, n0 = n->step;
   std::vector<int64_t> xrec((size_t)S * N);
   std::vector<uint8_t> types((size_t)S * N);
   std::vector<double> yrec((size_t)(S + 1) * N);
   for (int64_t k = 0; k < N; ++k) yrec[k] = n->y[k];
-  for (int64_t s = 0; s < S; ++s) run_one_step(*n, &xrec, &types, &yrec);
+  for (int64_t s = 0; s < S; ++s) run_one_step(*n, &xrec, &types, &yrec, n0);
   for (int64_t s = 0; s < S; ++s) { types_out[s] = types[(size_t)s * N + i]; x_out[s] = xrec[(size_t)s * N + i]; }
   for (int64_t s = 0; s <= S; ++s) y_out[s] = yrec[(size_t)s * N + i];
   return 0;

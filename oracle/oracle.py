@@ -269,19 +269,24 @@ class Oracle:
         return sp, ev.value
 
     def adjoint(self, S: int, y_star_rel: float, fp32: bool = False):
+        """Loss and dL/dw (pA) over the S steps from the current step, spikes
+        frozen; the state there, pending input included, is held fixed.  The
+        network advances by S steps."""
         g = np.zeros(self.M, np.float32 if fp32 else np.float64)
         loss = C.c_double()
         rc = lib().orc_adjoint(self.h, S, y_star_rel, 1 if fp32 else 0, g.ctypes.data_as(C.c_void_p), C.byref(loss))
         if rc != 0:
-            raise RuntimeError("oracle adjoint needs a fresh network")
+            raise RuntimeError("oracle adjoint failed")
         return loss.value, g
 
     def fd(self, S: int, y_star_rel: float, eps: float, syn) -> np.ndarray:
+        """Quad-precision central differences of the same loss (same window)
+        for the synapses `syn`."""
         syn = np.ascontiguousarray(syn, np.int64)
         out = np.zeros(len(syn), np.float64)
         rc = lib().orc_fd(self.h, S, y_star_rel, eps, syn, len(syn), out)
         if rc != 0:
-            raise RuntimeError("oracle fd needs a fresh network")
+            raise RuntimeError("oracle fd failed")
         return out
 
     def trace(self, S: int, i: int):
@@ -290,5 +295,5 @@ class Oracle:
         y = np.zeros(S + 1, np.float64)
         rc = lib().orc_trace(self.h, S, i, t, x, y)
         if rc != 0:
-            raise RuntimeError("oracle trace needs a fresh network")
+            raise RuntimeError("oracle trace failed")
         return t, x, y
