@@ -112,9 +112,10 @@ def test_adjoint_checkpoint_interval_invariance(small, K, mode):
 
 def test_adjoint_window_after_presimulation(small):
     """Window from a non-fresh state (inputs still pending from earlier
-    spikes are part of the initial condition): the trajectory equals plain
-    simulation, the gradient does not depend on K and vanishes exactly
-    without arrivals inside the window."""
+    spikes are part of the initial condition): the gradient is the oracle's
+    from the same step, bit for bit, for any K; the trajectory equals plain
+    simulation; the gradient vanishes exactly without arrivals inside the
+    window."""
     w = small[0]
     n0, S = 500, 400
     a, b, c = mc.Network(w), mc.Network(w), mc.Network(w)
@@ -122,6 +123,11 @@ def test_adjoint_window_after_presimulation(small):
         x.simulate(n0)
     la, ga = gpu_adjoint(a, S, 100)
     lb, gb = gpu_adjoint(b, S, 33)
+    o = oracle.Oracle(w.to_dict())
+    o.run(n0)
+    ol, og = o.adjoint(S, Y_STAR)
+    assert np.array_equal(ga.view(np.uint64), og.view(np.uint64))
+    assert abs(la - ol) <= 1e-12 * abs(ol)
     assert np.array_equal(ga.view(np.uint64), gb.view(np.uint64))
     c.simulate(S)
     sa, ia = a.spikes()
@@ -130,6 +136,28 @@ def test_adjoint_window_after_presimulation(small):
     rp, tg, wq, d = a.synapses()
     has = arrival_mask(rp, d, sa, ia, n0, S)
     assert np.all(ga[~has] == 0.0) and np.count_nonzero(ga) > 1000
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+@pytest.mark.parametrize("S", [1, 2, 3, 5, 17])
+def test_adjoint_tiny_windows_after_presimulation(small, S, scheme):
+    """Windows of 1 to 17 steps after 500 steps: the shortest delay is one
+    step, so only from S = 3 on can a spike of the window reach a later
+    step of it; loss and gradient equal the oracle's, bit for bit."""
+    w = small[0]
+    n0 = 500
+    net = mc.Network(w)
+    if scheme == 1:
+        net.set_launch(scheme=1, block=512, neurons_per_wg=0, steps_per_graph=0)
+    net.simulate(n0)
+    gl, gg = gpu_adjoint(net, S, 2)
+    o = oracle.Oracle(w.to_dict())
+    o.run(n0)
+    ol, og = o.adjoint(S, Y_STAR)
+    assert abs(gl - ol) <= 1e-12 * abs(ol)
+    assert np.array_equal(gg.view(np.uint64), og.view(np.uint64))
+    assert (np.count_nonzero(og) > 0) == (S >= 3)
+    assert net.counters()["step"] == n0 + S
 
 
 def test_autograd_window_loss(small):
