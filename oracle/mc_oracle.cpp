@@ -674,4 +674,35 @@ int orc_trace(void* h, int64_t S, int64_t i, uint8_t* types_out, int64_t* x_out,
   return 0;
 }
 
+// ---------------------------------------------------------------------------
+// Learning on the stored weights (Discussion: with every synapse's weight
+// stored explicitly, plasticity and learning can act on each one).  Plain
+// gradient descent with step eta: w <- w - eta * g, with w in pA (the stored
+// integer times 2^-16) and g the gradient orc_adjoint returns; the result is
+// stored again in units of 2^-16 pA, rounded to the nearest integer with
+// ties to even.  A step that would make any weight non-finite or take it
+// beyond the int32 range changes nothing and returns -1.
+// ---------------------------------------------------------------------------
+int orc_apply_gradient(void* h, const void* grad, int grad_mode, double eta) {
+  Net* n = (Net*)h;
+  const int64_t M = (int64_t)n->wq.size();
+  std::vector<int32_t> next((size_t)M);
+  for (int64_t k = 0; k < M; ++k) {
+    double g = (grad_mode == 0) ? ((const double*)grad)[k] : (double)((const float*)grad)[k];
+    double w_pA = (double)n->wq[k] / 65536.0;      // exact: a power-of-two scaling
+    double w_new = w_pA - eta * g;
+    double units = w_new * 65536.0;                 // exact
+    if (!(std::fabs(units) <= 2147483647.0)) return -1;
+    next[(size_t)k] = (int32_t)std::llrint(units);  // default rounding mode: nearest, ties to even
+  }
+  n->wq.swap(next);
+  return 0;
+}
+
+// Back to the initial state of a freshly built network (membrane potentials
+// drawn again from the same keys, currents, refractory counts and input
+// buffers zero, step 0, raster and counters empty); the synapse store, with
+// any weights changed since the build, is kept.
+void orc_reset(void* h) { init_state(*(Net*)h); }
+
 }  // extern "C"

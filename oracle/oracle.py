@@ -110,6 +110,10 @@ def lib():
         L.orc_fd.restype = C.c_int
         L.orc_trace.argtypes = [vp, i64, i64, P(np.uint8), P(np.int64), P(np.float64)]
         L.orc_trace.restype = C.c_int
+        L.orc_apply_gradient.argtypes = [vp, vp, C.c_int, f64]
+        L.orc_apply_gradient.restype = C.c_int
+        L.orc_reset.argtypes = [vp]
+        L.orc_reset.restype = None
         _lib = L
     return _lib
 
@@ -288,6 +292,21 @@ class Oracle:
         if rc != 0:
             raise RuntimeError("oracle fd failed")
         return out
+
+    def apply_gradient(self, g: np.ndarray, eta: float) -> bool:
+        """One gradient-descent step on the stored weights, w <- w - eta g
+        (pA), stored again in 2^-16 pA with ties to even; g float64 or
+        float32 of M elements.  False (weights unchanged) if a new weight
+        would not be finite or would not fit int32."""
+        if g.dtype not in (np.float64, np.float32) or g.shape != (self.M,):
+            raise ValueError("gradient must be float64 or float32 of M elements")
+        g = np.ascontiguousarray(g)
+        return lib().orc_apply_gradient(self.h, g.ctypes.data_as(C.c_void_p), 1 if g.dtype == np.float32 else 0,
+                                        float(eta)) == 0
+
+    def reset(self):
+        """Back to the initial state (step 0), keeping the current weights."""
+        lib().orc_reset(self.h)
 
     def trace(self, S: int, i: int):
         t = np.zeros(S, np.uint8)
