@@ -34,6 +34,8 @@ import re
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -43,13 +45,18 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_persist_microcircuit_hbm_traffi
 PERSIST_SRC = os.path.join(ROOT, "paper_2111_04398_amd", "csrc", "mc_persist.hip")
 
 
+BYTES_PER_EVENT = 9 + 8          # synapse record (target 4, weight 4, delay 1) + one int64 atomic add
+BYTES_PER_SPIKE = 16 + 4 + 8     # two row offsets, a spike-list entry, a raster entry
+BYTES_PER_NEURON_STEP = 50       # y, I (8 B each) and r (1 B) read and written; ring slot read and cleared
+
+
 def algorithmic_bytes(events: int, spikes: int, neuron_steps: int) -> int:
-    """Bytes the method must move: per synaptic event the 9-byte synapse
-    record (target 4, weight 4, delay 1) plus an 8-byte read-modify-write of
-    the ring entry (16 B); per spike its two row offsets (16 B), a list entry
-    (4 B) and a raster entry (8 B); per neuron-step y, I, r read and written
-    (2 x 20 B) and its ring slot read and cleared (2 x 8 B)."""
-    return events * (9 + 16) + spikes * (16 + 4 + 8) + neuron_steps * (40 + 16)
+    """Bytes the method must move (only what the method itself needs): per
+    synaptic event the 9-byte synapse record plus one 8-byte atomic add into
+    the ring; per spike its two row offsets, a list entry and a raster
+    entry; per neuron-step y, I (8 B) and r (1 B) read and written and its
+    ring slot read and cleared."""
+    return events * BYTES_PER_EVENT + spikes * BYTES_PER_SPIKE + neuron_steps * BYTES_PER_NEURON_STEP
 
 
 def measured_traffic(kernel: str, steps_per_launch: int):
@@ -210,23 +217,68 @@ def energy_run(net, meter, wall_s_target: float, ms_per_step: float, idle_s: flo
     return out
 
 
-def cpu_baseline(workload, presim: int, steps: int) -> dict:
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(mc, workload, launch: dict, presim: int, steps: int, steps_1t: int) -> dict:
     """The CPU oracle as it stands, on this host's cores, over a bounded
-    sample of the same workload: `presim` untimed steps, then `steps` timed."""
+    sample of the same workload: `presim` untimed steps, then `steps` timed
+    with all threads, then `steps_1t` timed with one thread.  The GPU runs
+    the same span from a fresh network (same launch) and its integer event
+    and spike counts over the timed span must equal the oracle's."""
     sys.path.insert(0, os.path.join(ROOT, "oracle"))
     import oracle  # test infrastructure; only this leg of the benchmark uses it
     if not os.path.exists(os.path.join(ROOT, "oracle", "libmc_oracle.so")):
         oracle.build()
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    oracle.set_threads(threads)
     o = oracle.Oracle(workload.to_dict())
     o.run(presim)
-    ev0 = o.counters()[1]
+    sp0, ev0 = o.counters()
     t = o.run(steps)
-    ev = o.counters()[1] - ev0
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    sp1, ev1 = o.counters()
+    oracle.set_threads(1)
+    t1 = o.run(steps_1t)
+    sp2, ev2 = o.counters()
+    oracle.set_threads(threads)
+    # the same span on the GPU
+    g = mc.Network(workload, device_connect=True)
+    g.set_launch(**launch)
+    g.reserve(presim + steps + steps_1t)
+    g.simulate(presim)
+    c0 = g.counters()
+    g.simulate(steps)
+    c1 = g.counters()
+    g.simulate(steps_1t)
+    c2 = g.counters()
+    g.close()
+    same = (c1["events"] - c0["events"] == ev1 - ev0 and c2["events"] - c1["events"] == ev2 - ev1 and
+            bool(np.array_equal(c1["spikes_per_pop"] - c0["spikes_per_pop"], sp1 - sp0)) and
+            bool(np.array_equal(c2["spikes_per_pop"] - c1["spikes_per_pop"], sp2 - sp1)))
+    ev, ev_1 = ev1 - ev0, ev2 - ev1
     return {"value": ev / t, "unit": "synaptic events/s", "cores": threads, "kind": "oracle",
-            "rtf": t / (steps * H_MS * 1e-3),
+            "rtf": t / (steps * H_MS * 1e-3), "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+            "one_thread": {"value": ev_1 / t1, "rtf": t1 / (steps_1t * H_MS * 1e-3), "steps": steps_1t,
+                           "events": ev_1, "seconds": t1},
+            "events_equal_gpu": same,
             "sample": f"{workload.name}: {presim} untimed presim steps, then {steps} timed steps "
-                      f"({steps * H_MS:g} ms of model time), {ev} synaptic events, {t:.2f} s"}
+                      f"({steps * H_MS:g} ms of model time) with {threads} threads ({ev} synaptic events, {t:.2f} s), "
+                      f"then {steps_1t} steps with 1 thread ({ev_1} events, {t1:.2f} s)"}
+
+
+def parse_launch(text: str) -> tuple:
+    """scheme,block,neurons_per_wg,steps_per_graph[,rows_per_wave]"""
+    v = [int(x) for x in text.split(",")]
+    if len(v) not in (4, 5):
+        raise SystemExit("--launch takes scheme,block,neurons_per_wg,steps_per_graph[,rows_per_wave]")
+    return tuple(v)
 
 
 def timed_run(net, steps: int, warmup: int, launch: str, tune_steps: int):
@@ -234,8 +286,7 @@ def timed_run(net, steps: int, warmup: int, launch: str, tune_steps: int):
     (gpu ms, events, spikes, host s, autotuned)."""
     net.simulate(warmup)                      # presimulation, discarded from timing
     if launch:
-        s, b, npw, spg = (int(v) for v in launch.split(","))
-        net.set_launch(scheme=s, block=b, neurons_per_wg=npw, steps_per_graph=spg)
+        net.set_launch(*parse_launch(launch))
         tuned = False
     else:
         net.tune(tune_steps)                  # restores the state it started from
@@ -250,10 +301,17 @@ def timed_run(net, steps: int, warmup: int, launch: str, tune_steps: int):
     return gpu_ms, c1["events"] - c0["events"], c1["spikes"] - c0["spikes"], host_s, tuned
 
 
-def adjoint_cost(net, window: int, ckpt_every: int, v_target: float, fp32: bool, plain_ms_per_step: float) -> dict:
-    """One adjoint window from the network's current state: GPU time of its
-    forward (with checkpoints) and reverse pass per step, against the plain
-    forward per step."""
+def adjoint_cost(net, window: int, ckpt_every: int, v_target: float, fp32: bool) -> dict:
+    """One adjoint window from the network's current state against the plain
+    forward of the same window from the same state (same launch): GPU time
+    per step of each (the adjoint's forward with checkpoints and its reverse
+    pass), with the state restored in between."""
+    start = net.save_state()
+    net.reserve(window)
+    net.counters()
+    net.simulate(window)
+    plain_ms = net.last_simulate_ms()
+    net.load_state(start)
     buf = DeviceBuffer(net.M * (4 if fp32 else 8))
     try:
         t0 = time.perf_counter()
@@ -264,27 +322,84 @@ def adjoint_cost(net, window: int, ckpt_every: int, v_target: float, fp32: bool,
         buf.free()
     return {"window_steps": window, "ckpt_every": ckpt_every, "grad": "f32" if fp32 else "f64", "loss": loss,
             "forward_ms_per_step": fwd / window, "reverse_ms_per_step": rev / window,
-            "plain_forward_ms_per_step": plain_ms_per_step,
-            "adjoint_vs_plain": (fwd + rev) / window / plain_ms_per_step,
+            "plain_forward_ms_per_step": plain_ms / window,
+            "adjoint_vs_plain": (fwd + rev) / plain_ms,
             "host_s": host_s}
+
+
+def probes(net, replay_slots: int) -> dict:
+    """What the memory system achieves for the delivery's two costs and for
+    the persistent kernel's exchange (library microbenchmarks, this run):
+    a 4 GiB streaming read; int64 atomic adds into slot-major tables of this
+    network's ring stride -- 128 slots (the ring, 79 MB at full scale), the
+    replay ring, and ~759 MB (the batched workload's ring) -- uniformly
+    random and in the delivery's own row/delay pattern; and the empty
+    persistent loop of the scheme in use."""
+    out = {"stream_read_gbs": net.probe_stream(4 << 30)}
+    stride = (net.N + 63) // 64 * 64
+    big = max(128, int(759e6 / 8 / stride))
+    atomic = {}
+    for slots in sorted({128, replay_slots, big}):
+        for pattern, name in ((0, "uniform"), (1, "rows")):
+            atomic[f"{slots}x{stride}_{name}"] = net.probe_atomics(slots, pattern) * 1e9
+    out["atomic_adds_per_s"] = atomic
+    out["atomic_ceiling_per_s"] = max(atomic.values())
+    if net.get_launch()["scheme"] == 1:
+        out["exchange_us_per_step"] = net.probe_exchange(10000)
+    return out
 
 
 def run_plain(args, mc, w) -> dict:
     t0 = time.perf_counter()
-    net = mc.Network(w)
+    net = mc.Network(w, device_connect=True)
     build_s = time.perf_counter() - t0
     steps = args.steps or w.sim_steps
     gpu_ms, events, spikes, host_s, tuned = timed_run(net, steps, args.warmup, args.launch, args.tune_steps)
+    kern = net.last_kernel_ms()
     wall_s = gpu_ms * 1e-3
     t_model = steps * H_MS * 1e-3
     launch = net.get_launch()
+    persistent = launch["scheme"] == mc.SCHEME_PERSISTENT_LDS and kern["launches"] > 0
+    kernel = "k_persist" if persistent else ("k_step" if launch["scheme"] == mc.SCHEME_STEP_KERNELS else "k_step+k_owner")
     alg_bytes_per_step = algorithmic_bytes(events, spikes, net.N * steps) / steps
-    achieved_gbs = alg_bytes_per_step / (wall_s / steps) / 1e9
-    kernel = "k_step" if launch["scheme"] == mc.SCHEME_STEP_KERNELS else "k_persist"
-    steps_per_launch = launch["steps_per_graph"] if kernel == "k_persist" and launch["steps_per_graph"] else (
-        steps if kernel == "k_persist" else 1)
+    # the dominant kernel's own time: the persistent kernel's launches (HIP
+    # events around each launch on the simulation stream), else the whole span
+    k_ms = kern["ms"] if persistent else gpu_ms
+    k_launches = kern["launches"] if persistent else 1
+    k_us_per_step = k_ms * 1e3 / steps
+    avg_launch_ms = k_ms / k_launches
+    steps_per_launch = steps / k_launches
+    achieved_gbs = alg_bytes_per_step * steps_per_launch / (avg_launch_ms * 1e-3) / 1e9
     full = w.name == "microcircuit"
-    tr = measured_traffic(kernel, steps_per_launch) if full else None   # counters were taken on this workload
+    tr = measured_traffic(kernel, int(round(steps_per_launch))) if full else None   # counters were taken on this workload
+    # replay span: 1000 recorded steps after the presim, simulated (untimed) if the timed span was shorter
+    rs = args.replay_steps
+    need = args.warmup + rs - net.counters()["step"]
+    if need > 0:
+        net.reserve(need)
+        net.simulate(need)
+    pr = probes(net, rs + 101) if not args.no_probes else {}
+    hbm = {"achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved_gbs / HBM_PEAK_GBS,
+           "alg_bytes_per_step": alg_bytes_per_step,
+           "bytes_per_unit": {"event": BYTES_PER_EVENT, "spike": BYTES_PER_SPIKE, "neuron_step": BYTES_PER_NEURON_STEP},
+           "traffic": tr["per_launch"] if tr else None,
+           "traffic_per_step": tr["per_step"] if tr else None,
+           "traffic_source": os.path.relpath(TRAFFIC_FILE, ROOT) if tr else None}
+    if pr:
+        hbm["measured_stream_read_gbs"] = pr["stream_read_gbs"]
+        hbm["frac_of_measured_read"] = achieved_gbs / pr["stream_read_gbs"]
+    if persistent and pr.get("exchange_us_per_step"):
+        floor = pr["exchange_us_per_step"]
+        roofline = {"bound": "latency", "kernel": kernel, "achieved": 1e6 / k_us_per_step,
+                    "peak": 1e6 / floor, "unit": "steps/s", "frac": floor / k_us_per_step,
+                    "traffic": hbm["traffic"], "kernel_us_per_step": k_us_per_step,
+                    "floor_us_per_step": floor,
+                    "floor": "empty persistent loop of the same workgroups exchanging one record per step",
+                    "launches": k_launches, "steps_per_launch": steps_per_launch, "avg_launch_ms": avg_launch_ms,
+                    "hbm": hbm}
+    else:
+        roofline = {"bound": "hbm", "kernel": kernel, **hbm, "kernel_us_per_step": k_us_per_step,
+                    "launches": k_launches, "steps_per_launch": steps_per_launch, "avg_launch_ms": avg_launch_ms}
     out = {
         "metric": "realtime factor + synaptic events/s, full microcircuit 77k neurons/3e8 syn" if full else
                   f"realtime factor + synaptic events/s, {w.name} ({net.N} neurons, {net.M} synapses)",
@@ -306,44 +421,37 @@ def run_plain(args, mc, w) -> dict:
         "rtf_host_clock": host_s / t_model,
         "events": events,
         "spikes": spikes,
+        "events_per_s": events / wall_s,
         "mean_rate_hz": spikes / net.N / t_model,
         "build_s": build_s,
-        "roofline": {
-            "bound": "hbm",
-            "kernel": kernel,
-            "achieved": achieved_gbs,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved_gbs / HBM_PEAK_GBS,
-            "traffic": tr["per_launch"] if tr else None,
-            "traffic_per_step": tr["per_step"] if tr else None,
-            "steps_per_launch": steps_per_launch,
-            "alg_bytes_per_step": alg_bytes_per_step,
-            "atomics_per_s": events / wall_s,
-        },
+        "roofline": roofline,
         "paper_context": {"rtf_2x64_core_epyc_node": 0.67, "rtf_2_nodes": 0.53},
     }
+    if pr:
+        out["probes"] = pr
     if args.energy_wall > 0:
         out["energy"] = energy_run(net, EnergyMeter(), args.energy_wall, gpu_ms / steps)
-    # throughput form of the delivery: recorded spikes of replay-steps steps in one launch
-    rs = min(args.replay_steps, steps)
+    # throughput form of the delivery: the recorded spikes of rs steps in one launch
     if rs > 0:
         r_ms, r_ev, _ = net.replay_delivery(args.warmup, args.warmup + rs)
-        peak = net.atomic_rate(net.N * (rs + 101))
         r_rate = r_ev / (r_ms * 1e-3)
-        r_gbs = r_ev * (9 + 16) / (r_ms * 1e-3) / 1e9
-        out["delivery_replay"] = {
-            "kernel": "k_replay", "steps": rs, "events": r_ev, "ms": r_ms,
-            "events_per_s": r_rate, "atomic_peak_per_s": peak * 1e9, "frac_atomic": r_rate / (peak * 1e9),
-            "achieved_gbs": r_gbs, "frac_hbm": r_gbs / HBM_PEAK_GBS,
-        }
+        r_gbs = r_ev * BYTES_PER_EVENT / (r_ms * 1e-3) / 1e9
+        rep = {"kernel": "k_replay", "steps": rs, "events": r_ev, "ms": r_ms, "events_per_s": r_rate,
+               "achieved_gbs": r_gbs, "frac_hbm": r_gbs / HBM_PEAK_GBS}
+        if pr:
+            key = f"{rs + 101}x{(net.N + 63) // 64 * 64}_rows"
+            rep["atomic_ceiling_per_s"] = pr["atomic_ceiling_per_s"]
+            rep["frac_atomic"] = r_rate / pr["atomic_ceiling_per_s"]
+            rep["same_table_rows_probe_per_s"] = pr["atomic_adds_per_s"].get(key)
+            rep["frac_hbm_measured"] = r_gbs / pr["stream_read_gbs"]
+        out["delivery_replay"] = rep
     if args.phases and launch["scheme"] == mc.SCHEME_PERSISTENT_LDS:
         out["phases_us_per_step"] = net.profile_phases(args.phases)
     if args.adjoint_window > 0 and full:
-        out["adjoint"] = adjoint_cost(net, args.adjoint_window, 100, -58.0, True, gpu_ms / steps)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, presim=1000, steps=args.cpu_steps)
+        out["adjoint"] = adjoint_cost(net, args.adjoint_window, 100, -58.0, True)
     net.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(mc, w, launch, presim=1000, steps=args.cpu_steps, steps_1t=args.cpu_steps_1t)
     return out
 
 
@@ -387,31 +495,21 @@ def run_batched(args, mc, w) -> dict:
                        "instances_per_s": n_inst / (seq_ms_all * 1e-3), "events": seq_events,
                        "launches": seq_launch},
         "speedup_vs_sequential": (seq_ms_all * 1e-3) / wall_s,
-        "atomics_per_s": events / wall_s,
         "energy": energy,
     }
 
 
 def run_adjoint(args, mc, w) -> dict:
     """Adjoint over the workload's window from a fresh network against the
-    plain forward of the same window on a twin network (same launch)."""
+    plain forward of the same window from the same state (same launch)."""
     S, K = w.adj_window, w.adj_ckpt_every
-    plain = mc.Network(w)
+    net = mc.Network(w, device_connect=True)
     if args.launch:
-        s, b, npw, spg = (int(v) for v in args.launch.split(","))
-        plain.set_launch(scheme=s, block=b, neurons_per_wg=npw, steps_per_graph=spg)
+        net.set_launch(*parse_launch(args.launch))
     else:
-        plain.tune(min(args.tune_steps, S))
-    launch = plain.get_launch()
-    plain.reserve(S)
-    plain.counters()
-    plain.simulate(S)
-    plain_ms = plain.last_simulate_ms()
-    plain.close()
-    net = mc.Network(w)
-    net.set_launch(scheme=launch["scheme"], block=launch["block"], neurons_per_wg=launch["neurons_per_wg"],
-                   steps_per_graph=launch["steps_per_graph"])
-    a = adjoint_cost(net, S, K, w.adj_v_target, w.adj_fp32, plain_ms / S)
+        net.tune(min(args.tune_steps, S))
+    launch = net.get_launch()
+    a = adjoint_cost(net, S, K, w.adj_v_target, w.adj_fp32)
     c = net.counters()
     net.close()
     return {
@@ -480,8 +578,11 @@ def main() -> int:
     ap.add_argument("--energy-wall", type=float, default=12.0, metavar="S",
                     help="after timing: idle power, then about S seconds of simulation under the package "
                          "energy counter for the energy per synaptic event (0: skip)")
-    ap.add_argument("--cpu-steps", type=int, default=15000)
-    ap.add_argument("--launch", default="", help="scheme,block,neurons_per_wg,steps_per_graph (default: autotuned)")
+    ap.add_argument("--cpu-steps", type=int, default=15000, help="oracle steps timed with all host threads")
+    ap.add_argument("--cpu-steps-1t", type=int, default=600, help="oracle steps timed with one thread")
+    ap.add_argument("--no-probes", action="store_true", help="skip the stream/atomic/exchange microbenchmarks")
+    ap.add_argument("--launch", default="",
+                    help="scheme,block,neurons_per_wg,steps_per_graph[,rows_per_wave] (default: autotuned)")
     ap.add_argument("--tune-steps", type=int, default=2000, help="steps per autotuner candidate")
     ap.add_argument("--replay-steps", type=int, default=1000, help="steps of raster replayed in one launch")
     ap.add_argument("--phases", type=int, default=0, help="after timing, profile this many steps per phase")

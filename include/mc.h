@@ -53,18 +53,21 @@ typedef enum mc_status {
   MC_ERR_STATE = -5,             /* handle in the wrong state (freed, host-only, failed, or not fresh) */
   MC_ERR_BUFFER_TOO_SMALL = -6,  /* *count_out holds the required element count */
   MC_ERR_NO_DEVICE = -7,         /* no usable gfx950 device */
-  MC_ERR_MISMATCH = -8           /* adjoint recomputation did not reproduce the recorded spikes */
+  MC_ERR_MISMATCH = -8,          /* adjoint recomputation did not reproduce the recorded spikes */
+  MC_ERR_TIMEOUT = -9            /* the persistent kernel's wait for a step's spike records exceeded its
+                                    time limit (a workgroup never published); the handle is marked failed */
 } mc_status;
 
 enum { MC_RULE_FIXED_INDEGREE = 0, MC_RULE_BERNOULLI = 1 };
 enum { MC_GRAD_F64 = 0, MC_GRAD_F32 = 1 };
 enum {
   MC_FLAG_HOST_ONLY = 1u,       /* build the network on the host only (no device memory) */
-  MC_FLAG_DEVICE_CONNECT = 2u   /* draw the connections of MC_RULE_BERNOULLI on the device: the pair
-                                   tests (integer Philox draws) run as HIP kernels, weights, delays
-                                   and everything else on the host; the network is bit-identical to
-                                   the host build.  Ignored for MC_RULE_FIXED_INDEGREE; INVALID_ARG
-                                   with MC_FLAG_HOST_ONLY. */
+  MC_FLAG_DEVICE_CONNECT = 2u   /* draw the connections on the device: the pair tests of
+                                   MC_RULE_BERNOULLI and the source draws of MC_RULE_FIXED_INDEGREE
+                                   (integer Philox draws) run as HIP kernels; the sort into rows,
+                                   weights, delays and everything else stay on the host; the network is
+                                   bit-identical to the host build.  INVALID_ARG with
+                                   MC_FLAG_HOST_ONLY. */
 };
 
 typedef struct mc_net mc_net;
@@ -112,22 +115,42 @@ typedef struct mc_config {
   const uint64_t* inst_seed;     /* [n_instances]; required */
   void* hip_stream;              /* hipStream_t to run on; NULL: a stream owned by the library */
   uint32_t flags;                /* MC_FLAG_* */
+  /* Optional device allocator (e.g. a framework's caching allocator): every
+   * device buffer that belongs to the network (synapse store, state, ring,
+   * tables, raster, adjoint buffers, probe buffers) comes from
+   * dev_alloc(bytes, alloc_ctx), which must return device memory of the
+   * current device aligned to 256 bytes, or NULL (the call then fails with
+   * OOM); it is returned with dev_free(ptr, alloc_ctx) after the network's
+   * stream has finished with it.  Both NULL: hipMalloc / hipFree.  Giving
+   * one without the other is INVALID_ARG.  Temporary buffers of the device
+   * connection draws during mc_build_network use hipMalloc. */
+  void* (*dev_alloc)(size_t bytes, void* alloc_ctx);
+  void (*dev_free)(void* ptr, void* alloc_ctx);
+  void* alloc_ctx;
 } mc_config;
 
 /* Launch configuration of the simulation loop (see mc_set_launch). */
 enum { MC_SCHEME_STEP_KERNELS = 0,   /* one kernel per step (update, then source-owner delivery with device
                                         atomics), replayed from a HIP graph */
        MC_SCHEME_PERSISTENT_LDS = 1,  /* one persistent kernel per chunk; near-future input held in LDS */
-       MC_SCHEME_TARGET_OWNER = 2 };  /* two kernels per step: update, then target-owner delivery combined
+       MC_SCHEME_TARGET_OWNER = 2,    /* two kernels per step: update, then target-owner delivery combined
                                         in LDS (no device atomics); replayed from a HIP graph */
+       MC_SCHEME_PERSISTENT_BUCKETS = 3 };  /* one persistent kernel per chunk; workgroups own target blocks of
+                                        one instance and exchange spikes with their own instance only;
+                                        events go to per-workgroup buckets by arrival step (batches of
+                                        instances, networks too large for the LDS window) */
 typedef struct mc_launch {
   uint32_t struct_size;
   int32_t scheme;
   int32_t block;                 /* threads per workgroup: 64..1024, multiple of 64 */
   int32_t neurons_per_wg;        /* neurons updated by one workgroup: multiple of 4, <= 4*block, <= 1024
                                     (persistent: <= block; target owner: the targets of one delivery block,
-                                    its update kernel takes one quad per thread); 0: automatic */
+                                    its update kernel takes one quad per thread; buckets: <= min(2048,
+                                    6*block)); 0: automatic */
   int32_t steps_per_graph;       /* steps captured per graph replay / per persistent launch (>= 1) */
+  int32_t rows_per_wave;         /* step kernels' delivery: 0 = all threads of a workgroup walk each
+                                    spiking row in turn; 1 = each wavefront walks whole rows (short rows);
+                                    ignored by the other schemes */
 } mc_launch;
 
 typedef struct mc_counters {
@@ -154,7 +177,7 @@ enum { MC_ADJ_INPUT_AUTO = 0, MC_ADJ_INPUT_RECORD = 1, MC_ADJ_INPUT_REPLAY = 2 }
 /* --- the four calls of the simulation --------------------------------- */
 
 /* Builds the network on the host (OpenMP; with MC_FLAG_DEVICE_CONNECT the
- * connection draws of MC_RULE_BERNOULLI on the device), derives propagators and drive
+ * connection draws on the device), derives propagators and drive
  * tables, uploads everything to the current HIP device.  Untimed
  * instantiation of the Methods section.  *out receives the handle (NULL on
  * failure).  Errors: INVALID_ARG (inconsistent config), RANGE (a quantised
@@ -235,11 +258,16 @@ int mc_get_counters(mc_net* net, mc_counters* out);
 int mc_set_launch(mc_net* net, const mc_launch* l);
 int mc_get_launch(mc_net* net, mc_launch* l);
 /* Times candidate launch configurations on copies of the current state for
- * `steps` steps each, keeps the fastest (state and raster are restored). */
+ * `steps` steps each, keeps the fastest (state and raster are restored).
+ * If the environment variable MC_TUNE_CACHE names a file, the choice is
+ * kept there keyed by the network's shape (neurons, synapses, instance and
+ * population sizes, largest delay and row) and the device (name and compute
+ * units); a later call for the same key applies the stored choice without
+ * timing anything.  *best_out: the launch chosen. */
 int mc_tune(mc_net* net, int64_t steps, mc_launch* best_out);
 /* Shape of the persistent scheme in use: workgroups, target neurons per
- * workgroup and steps of pending input held in LDS (all 0 under the step
- * kernels). */
+ * workgroup and steps of pending input held in LDS (the bucket scheme: 0
+ * steps; all 0 under the step kernels). */
 int mc_get_persist_shape(mc_net* net, int32_t* workgroups_out, int32_t* targets_per_wg_out, int32_t* lds_steps_out);
 /* Simulates `steps` steps with per-phase device timestamps (persistent
  * scheme only) and returns the mean time per step in microseconds, averaged
@@ -268,8 +296,37 @@ int mc_replay_delivery(mc_net* net, int64_t step_begin, int64_t step_end, int64_
  * atomic adds into a table of `entries` elements: the achievable peak the
  * delivery's atomics are compared with. */
 int mc_atomic_rate(mc_net* net, int64_t entries, double* gops_out);
+/* Achievable memory rates the delivery is measured against (Methods: the
+ * simulation's time goes to updating neurons and delivering spikes; here
+ * the delivery streams the synapse records and adds into a slot-major ring):
+ *   mc_probe_stream   -- streaming read of `bytes` (>= 1 MiB, rounded down to
+ *                        16 B) of device memory it allocates; *gbs_out GB/s
+ *                        (1e9 B/s) of the second of two launches;
+ *   mc_probe_atomics  -- int64 atomic adds into a table of slots x (the
+ *                        network's ring stride) entries it allocates;
+ *                        pattern 0: uniformly random (slot, target);
+ *                        pattern 1: the delivery's own pattern (chunks of 256
+ *                        events of a row: ascending targets at the store's
+ *                        mean spacing N/mean out-degree, delays drawn from the
+ *                        store's delay histogram, spike steps advancing over
+ *                        the table); *gops_out 1e9 adds per second;
+ *   mc_probe_exchange -- the persistent scheme in use with nothing but its
+ *                        exchange: its workgroups publish and poll one record
+ *                        per step; *us_per_step_out the time per step, the
+ *                        floor of the persistent kernel's step (STATE under
+ *                        another scheme; TIMEOUT if a record never arrived).
+ * Each synchronizes and leaves the network untouched. */
+int mc_probe_stream(mc_net* net, int64_t bytes, double* gbs_out);
+int mc_probe_atomics(mc_net* net, int64_t slots, int32_t pattern, double* gops_out);
+int mc_probe_exchange(mc_net* net, int64_t steps, double* us_per_step_out);
 /* Wall time (ms) of the GPU work of the most recent mc_simulate, from HIP events. */
 int mc_last_simulate_ms(mc_net* net, double* ms_out);
+/* Persistent scheme: the summed durations (ms, HIP events recorded on the
+ * simulation stream right before and after each launch) of the persistent
+ * kernel's launches in the most recent mc_simulate, how many launches were
+ * timed (at most 64) and the steps they covered.  Zero launches under the
+ * other schemes.  Synchronizes on that mc_simulate. */
+int mc_last_kernel_ms(mc_net* net, double* ms_out, int64_t* launches_out, int64_t* steps_out);
 /* GPU time (ms, HIP events) of the most recent mc_adjoint: its forward
  * (S steps with checkpoints) and its reverse pass (recompute, adjoint,
  * gather). */
@@ -282,8 +339,22 @@ int mc_reserve(mc_net* net, int64_t steps);
 /* Full dynamic state (step, y, I, r, ring, counters) to/from a host blob. */
 int mc_save_state(mc_net* net, void* blob_host, size_t capacity, size_t* used_out);
 int mc_load_state(mc_net* net, const void* blob_host, size_t size);
-/* Replaces every weight by rint(w_pA_dev[k] * 2^16) (device array, canonical order). */
+/* Replaces every weight by rint(w_pA_dev[k] * 2^16) (device array of
+ * mc_get_sizes().n_synapses doubles in pA, canonical order; round to nearest
+ * even).  RANGE if a value is not finite or its quantised weight does not fit
+ * int32 (|w| >= 32768 pA): then the store is unchanged.  Synchronizes. */
 int mc_set_weights(mc_net* net, const double* w_pA_dev);
+/* One gradient-descent step on the stored weights (Discussion: explicit
+ * per-synapse weights keep plasticity and learning possible; with the
+ * gradient of mc_adjoint this is learning on the store itself): every weight
+ * becomes rint((w_q[k] 2^-16 - eta g[k]) 2^16) in units of 2^-16 pA (round to
+ * nearest even), the difference evaluated in FP64 as fl(w - fl(eta g)).
+ * grad_dev: device array of n_synapses elements in canonical order, double
+ * for MC_GRAD_F64, float for MC_GRAD_F32 (as mc_adjoint writes it); eta: pA
+ * per unit of g.  RANGE (store unchanged) if a new weight is not finite or
+ * does not fit int32; INVALID_ARG for a NULL gradient, an unknown dtype or a
+ * non-finite eta.  Synchronizes. */
+int mc_apply_gradient(mc_net* net, const void* grad_dev, int32_t grad_dtype, double eta);
 int mc_stream(mc_net* net, void** hip_stream_out);
 
 #ifdef __cplusplus

@@ -52,28 +52,22 @@ def window_loss(net: mc.Network, w: torch.Tensor, window: int, ckpt_every: int, 
     return _WindowLoss.apply(w, net, int(window), int(ckpt_every), float(v_target))
 
 
-def fit_weights(net: mc.Network, w: torch.Tensor, window: int, ckpt_every: int, v_target: float, iters: int,
-                rel_step: float = 0.01) -> list:
+def fit_weights(net: mc.Network, window: int, ckpt_every: int, v_target: float, iters: int, eta: float,
+                fp32: bool = False) -> list:
     """Gradient descent on the explicitly stored weights (the Discussion of
     the paper notes that storing every synapse keeps plasticity and learning
     possible).  Every iteration restarts the window from the network state
-    at the call, takes dL/dw with the spike pattern frozen and moves w
-    against it by a step whose first-order decrease of L is `rel_step` of L;
-    `w` is updated in place.  The network ends at the state after the last
-    window.  Returns the loss of every iteration."""
-    if not w.requires_grad:
-        raise ValueError("w must require grad")
+    at the call, takes dL/dw with the spike pattern frozen (``mc_adjoint``)
+    and moves every weight by -eta * dL/dw, re-quantised on the device
+    (``mc_apply_gradient``); the weights live in the library's store.  torch
+    only provides the gradient buffer.  The network ends at the state after
+    the last window.  Returns the loss of every iteration (before its step)."""
     start = net.save_state()
+    grad = torch.empty(net.M, dtype=torch.float32 if fp32 else torch.float64, device="cuda")
     losses = []
     for it in range(iters):
         if it:
             net.load_state(start)
-        loss = window_loss(net, w, window, ckpt_every, v_target)
-        (g,) = torch.autograd.grad(loss, w)
-        lv = float(loss.item())
-        gg = float(torch.dot(g.double(), g.double()).item())
-        losses.append(lv)
-        if gg > 0.0:
-            with torch.no_grad():
-                w -= (rel_step * lv / gg) * g.to(w.dtype)
+        losses.append(net.adjoint(window, ckpt_every, v_target, fp32, grad.data_ptr()))
+        net.apply_gradient(grad.data_ptr(), fp32, eta)
     return losses

@@ -4,7 +4,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <memory>
@@ -41,37 +43,74 @@ int set_error(int code, const std::string& msg) {
 
 inline int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
+// Longest wait of a persistent workgroup for one step's spike records before
+// the kernel gives up (error bit 2): a step takes microseconds, so seconds
+// mean a workgroup that never publishes.
+constexpr long long kWaitSeconds = 5;
+
+// Entries per delay bucket of the bucket scheme (a full bucket sends further
+// events of that arrival step to the ring with device atomics).
+constexpr int kBucketCap = 8192;
+
+// Error bits the kernels set in the overflow word.
+constexpr unsigned kErrRasterOverflow = 1u, kErrWaitTimeout = 2u;
+
+// Device memory of a network: from the caller's allocator hooks if the
+// configuration gives them (e.g. a framework's caching allocator), else
+// hipMalloc / hipFree.
+struct Alloc {
+  void* (*fn)(size_t, void*) = nullptr;
+  void (*fr)(void*, void*) = nullptr;
+  void* ctx = nullptr;
+};
+
 template <class T>
-int dev_alloc(T** p, size_t count) {
+int dev_alloc(const Alloc& A, T** p, size_t count) {
   *p = nullptr;
   if (count == 0) count = 1;
-  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+  const size_t bytes = count * sizeof(T);
+  if (A.fn) {
+    *p = static_cast<T*>(A.fn(bytes, A.ctx));
+    if (!*p) return set_error(MC_ERR_OOM, "the allocator hook returned NULL for " + std::to_string(bytes) + " bytes");
+    if (reinterpret_cast<uintptr_t>(*p) % 256) {
+      A.fr(*p, A.ctx);
+      *p = nullptr;
+      return set_error(MC_ERR_INVALID_ARG, "the allocator hook returned memory not aligned to 256 bytes");
+    }
+    return MC_OK;
+  }
+  hipError_t e = hipMalloc((void**)p, bytes);
   if (e != hipSuccess) {
     *p = nullptr;
     (void)hipGetLastError();   // the runtime keeps the failure as its last error: the next launch check would see it
     return set_error(e == hipErrorOutOfMemory ? MC_ERR_OOM : MC_ERR_HIP,
-                     std::string("hipMalloc of ") + std::to_string(count * sizeof(T)) + " bytes: " + hipGetErrorString(e));
+                     std::string("hipMalloc of ") + std::to_string(bytes) + " bytes: " + hipGetErrorString(e));
   }
   return MC_OK;
 }
 
 template <class T>
-void dev_free(T*& p) {
-  if (p) (void)hipFree((void*)p);
+void dev_free(const Alloc& A, T*& p) {
+  if (p) {
+    if (A.fr) A.fr((void*)p, A.ctx);
+    else (void)hipFree((void*)p);
+  }
   p = nullptr;
 }
 
 // Device buffers of one adjoint call, freed on every exit path.
 struct AdjBuffers {
+  const Alloc& A;
   std::vector<void*> ptrs;
+  explicit AdjBuffers(const Alloc& a) : A(a) {}
   template <class T>
   int alloc(T** p, size_t count) {
-    int rc = dev_alloc(p, count);
+    int rc = dev_alloc(A, p, count);
     if (rc == MC_OK) ptrs.push_back((void*)*p);
     return rc;
   }
   ~AdjBuffers() {
-    for (void* p : ptrs) (void)hipFree(p);
+    for (void* p : ptrs) dev_free(A, p);
   }
 };
 
@@ -79,6 +118,7 @@ struct AdjBuffers {
 
 struct mc_net {
   HostNet h;
+  Alloc alloc;                         // device memory of this network
   bool host_only = false;
   bool failed = false;
   int device = 0;
@@ -103,10 +143,14 @@ struct mc_net {
   long long* d_step = nullptr;
   // persistent LDS scheme
   int n_cu = 0;
+  int wall_khz = 100000;               // wall_clock64 rate (kHz)
   int lds_max = 65536;
   int pG = 0, pB = 0, pDL = 0;
+  int horizon = kRingSlots - 1;        // ring slots ahead of the current step that may hold input
   long long* d_blk = nullptr;
   unsigned long long* d_flags = nullptr;
+  unsigned long long* d_bk = nullptr;  // bucket scheme: [G][128][bk_cap] entries
+  int bk_cap = 0;
   int* d_pub = nullptr;
   int* d_bstart = nullptr;
   std::vector<int> bstart_host;        // [pG+1] target blocks of the persistent workgroups
@@ -145,6 +189,7 @@ struct mc_net {
   unsigned long long* d_wg_events = nullptr;
   unsigned long long* d_wg_spikes = nullptr;
   unsigned* d_overflow = nullptr;
+  unsigned* d_wbad = nullptr;          // weight update check flag
   int64_t cap_steps = 0;               // steps the raster segments can absorb between drains
   int64_t steps_since_drain = 0;
   // drained raster (dense ids), sorted by (step, id); a deque, so that growing
@@ -158,6 +203,12 @@ struct mc_net {
   hipGraphExec_t graph = nullptr;
   int graph_steps = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_mid = nullptr;
+  // HIP events around every persistent-kernel launch of the latest
+  // mc_simulate (pairs k, k+1; at most kLaunchEvents / 2 launches timed)
+  std::vector<hipEvent_t> ev_launch;
+  std::vector<unsigned> dcdf;          // delay histogram of the store, cumulative, 32-bit (atomic probe)
+  int launches_timed = 0;
+  int64_t steps_timed = 0;
   hipStream_t aux = nullptr;           // read-back of the raster beside the simulation stream
   int2* d_pack = nullptr;              // raster prefixes packed for one read-back
   int64_t pack_cap = 0;
@@ -186,6 +237,16 @@ struct mc_net {
     return p;
   }
 
+  BucketArgs bucket() const {
+    BucketArgs a{};
+    a.G = own_blocks; a.B = wg_neurons;
+    a.bt0 = d_bt0; a.binst = d_binst; a.blb = d_blb; a.ifb = d_ifb; a.boff = d_boff; a.blk2 = d_blk2;
+    a.flags = d_flags; a.pub = d_pub; a.bk = d_bk; a.cap = bk_cap;
+    a.wait_ticks = (long long)wall_khz * 1000 * kWaitSeconds;
+    a.horizon = horizon;
+    return a;
+  }
+
   OwnerArgs owner() const {
     OwnerArgs a{};
     a.n_blocks = own_blocks; a.bmax = own_bmax;
@@ -196,9 +257,10 @@ struct mc_net {
   PersistArgs persist() const {
     PersistArgs a{};
     a.G = pG; a.B = pB; a.DL = pDL; a.BW = (pB + 31) / 32;
+    a.horizon = horizon;
     a.bstart = d_bstart;
     a.blk = d_blk; a.flags = d_flags; a.pub = d_pub;
-    a.spin_limit = 1LL << 24;
+    a.wait_ticks = (long long)wall_khz * 1000 * kWaitSeconds;
     a.phase = phase_on ? d_phase : nullptr;
     a.nb = d_nb; a.ne = d_ne;
     return a;
@@ -226,30 +288,34 @@ bool usable(mc_net* n) { return n && !n->failed; }
 bool device_ready(mc_net* n) { return usable(n) && !n->host_only; }
 
 int release_recording(mc_net* n) {
-  dev_free(n->d_raster);
-  dev_free(n->d_raster_cnt);
-  dev_free(n->d_wg_events);
-  dev_free(n->d_wg_spikes);
+  dev_free(n->alloc, n->d_raster);
+  dev_free(n->alloc, n->d_raster_cnt);
+  dev_free(n->alloc, n->d_wg_events);
+  dev_free(n->alloc, n->d_wg_spikes);
   return MC_OK;
 }
 
 void release_all(mc_net* n) {
   if (n->graph) { (void)hipGraphExecDestroy(n->graph); n->graph = nullptr; }
   release_recording(n);
-  dev_free(n->d_blk); dev_free(n->d_flags); dev_free(n->d_pub); dev_free(n->d_phase); dev_free(n->d_nb);
-  dev_free(n->d_ne);
-  dev_free(n->d_bstart);
-  dev_free(n->d_qinst); dev_free(n->d_inst_base); dev_free(n->d_ilist); dev_free(n->d_icnt);
-  dev_free(n->d_bt0); dev_free(n->d_binst); dev_free(n->d_blb); dev_free(n->d_ifb); dev_free(n->d_boff);
-  dev_free(n->d_blk2);
-  dev_free(n->d_overflow);
-  dev_free(n->d_row_ptr); dev_free(n->d_tgt); dev_free(n->d_wq); dev_free(n->d_dly);
-  dev_free(n->d_y); dev_free(n->d_I); dev_free(n->d_r); dev_free(n->d_ring);
-  dev_free(n->d_qseed); dev_free(n->d_qlocal); dev_free(n->d_qpops); dev_free(n->d_table); dev_free(n->d_step);
+  dev_free(n->alloc, n->d_blk); dev_free(n->alloc, n->d_flags); dev_free(n->alloc, n->d_pub); dev_free(n->alloc, n->d_phase); dev_free(n->alloc, n->d_nb);
+  dev_free(n->alloc, n->d_bk);
+  dev_free(n->alloc, n->d_ne);
+  dev_free(n->alloc, n->d_bstart);
+  dev_free(n->alloc, n->d_qinst); dev_free(n->alloc, n->d_inst_base); dev_free(n->alloc, n->d_ilist); dev_free(n->alloc, n->d_icnt);
+  dev_free(n->alloc, n->d_bt0); dev_free(n->alloc, n->d_binst); dev_free(n->alloc, n->d_blb); dev_free(n->alloc, n->d_ifb); dev_free(n->alloc, n->d_boff);
+  dev_free(n->alloc, n->d_blk2);
+  dev_free(n->alloc, n->d_overflow);
+  dev_free(n->alloc, n->d_wbad);
+  dev_free(n->alloc, n->d_row_ptr); dev_free(n->alloc, n->d_tgt); dev_free(n->alloc, n->d_wq); dev_free(n->alloc, n->d_dly);
+  dev_free(n->alloc, n->d_y); dev_free(n->alloc, n->d_I); dev_free(n->alloc, n->d_r); dev_free(n->alloc, n->d_ring);
+  dev_free(n->alloc, n->d_qseed); dev_free(n->alloc, n->d_qlocal); dev_free(n->alloc, n->d_qpops); dev_free(n->alloc, n->d_table); dev_free(n->alloc, n->d_step);
   if (n->ev0) { (void)hipEventDestroy(n->ev0); n->ev0 = nullptr; }
   if (n->ev1) { (void)hipEventDestroy(n->ev1); n->ev1 = nullptr; }
   if (n->ev_mid) { (void)hipEventDestroy(n->ev_mid); n->ev_mid = nullptr; }
-  dev_free(n->d_pack); dev_free(n->d_pack_off);
+  for (hipEvent_t e : n->ev_launch) (void)hipEventDestroy(e);
+  n->ev_launch.clear();
+  dev_free(n->alloc, n->d_pack); dev_free(n->alloc, n->d_pack_off);
   n->pack_cap = 0; n->pack_off_cap = 0;
   if (n->h_stage) { (void)hipHostFree(n->h_stage); n->h_stage = nullptr; n->stage_bytes = 0; }
   if (n->aux) { (void)hipStreamDestroy(n->aux); n->aux = nullptr; }
@@ -276,6 +342,11 @@ int drain(mc_net* n, hipEvent_t upto = nullptr) {
   HIP_TRY(hipMemcpyAsync(&ovf, n->d_overflow, sizeof(unsigned), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipMemcpyAsync(cnt.data(), n->d_raster_cnt, sizeof(long long) * n->n_wg, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
+  if (ovf & kErrWaitTimeout) {
+    n->failed = true;
+    return set_error(MC_ERR_TIMEOUT, "persistent kernel: a workgroup waited more than " + std::to_string(kWaitSeconds) +
+                                         " s for the spike records of a step and the launch was abandoned");
+  }
   if (ovf) { n->failed = true; return set_error(MC_ERR_STATE, "raster segment overflow (internal capacity error)"); }
   std::vector<long long> seg_off((size_t)n->n_wg + 1, 0);
   for (int g = 0; g < n->n_wg; ++g) seg_off[g + 1] = seg_off[g] + cnt[g];
@@ -285,15 +356,15 @@ int drain(mc_net* n, hipEvent_t upto = nullptr) {
     // the used prefixes packed on the device, then one copy
     int rc;
     if (n->pack_off_cap < n->n_wg + 1) {
-      dev_free(n->d_pack_off);
+      dev_free(n->alloc, n->d_pack_off);
       n->pack_off_cap = 0;
-      if ((rc = dev_alloc(&n->d_pack_off, (size_t)n->n_wg + 1)) != MC_OK) return rc;
+      if ((rc = dev_alloc(n->alloc, &n->d_pack_off, (size_t)n->n_wg + 1)) != MC_OK) return rc;
       n->pack_off_cap = n->n_wg + 1;
     }
     if (n->pack_cap < total) {
-      dev_free(n->d_pack);
+      dev_free(n->alloc, n->d_pack);
       n->pack_cap = 0;
-      if ((rc = dev_alloc(&n->d_pack, (size_t)total)) != MC_OK) return rc;
+      if ((rc = dev_alloc(n->alloc, &n->d_pack, (size_t)total)) != MC_OK) return rc;
       n->pack_cap = total;
     }
     HIP_TRY(hipMemcpyAsync(n->d_pack_off, seg_off.data(), sizeof(long long) * (n->n_wg + 1), hipMemcpyHostToDevice, s));
@@ -354,10 +425,10 @@ int setup_recording(mc_net* n, int64_t steps) {
   auto alloc = [&](int64_t s) {
     n->raster_cap = spike_bound(n->wg_neurons, s, n->h.ref_steps) + 1;
     n->cap_steps = s;
-    int r = dev_alloc(&n->d_raster, (size_t)n->n_wg * n->raster_cap);
-    if (r == MC_OK) r = dev_alloc(&n->d_raster_cnt, (size_t)n->n_wg);
-    if (r == MC_OK) r = dev_alloc(&n->d_wg_events, (size_t)n->n_wg);
-    if (r == MC_OK) r = dev_alloc(&n->d_wg_spikes, (size_t)n->n_wg * n->h.n_pops);
+    int r = dev_alloc(n->alloc, &n->d_raster, (size_t)n->n_wg * n->raster_cap);
+    if (r == MC_OK) r = dev_alloc(n->alloc, &n->d_raster_cnt, (size_t)n->n_wg);
+    if (r == MC_OK) r = dev_alloc(n->alloc, &n->d_wg_events, (size_t)n->n_wg);
+    if (r == MC_OK) r = dev_alloc(n->alloc, &n->d_wg_spikes, (size_t)n->n_wg * n->h.n_pops);
     if (r != MC_OK) { release_recording(n); n->cap_steps = 0; n->raster_cap = 0; }
     return r;
   };
@@ -381,8 +452,18 @@ int setup_recording(mc_net* n, int64_t steps) {
 
 int validate_launch(const mc_net* n, const mc_launch& l) {
   if (l.struct_size != sizeof(mc_launch)) return set_error(MC_ERR_INVALID_ARG, "mc_launch.struct_size mismatch");
-  if (l.scheme != MC_SCHEME_STEP_KERNELS && l.scheme != MC_SCHEME_PERSISTENT_LDS && l.scheme != MC_SCHEME_TARGET_OWNER)
+  if (l.scheme != MC_SCHEME_STEP_KERNELS && l.scheme != MC_SCHEME_PERSISTENT_LDS && l.scheme != MC_SCHEME_TARGET_OWNER &&
+      l.scheme != MC_SCHEME_PERSISTENT_BUCKETS)
     return set_error(MC_ERR_INVALID_ARG, "unknown scheme");
+  if (l.scheme == MC_SCHEME_PERSISTENT_BUCKETS) {
+    if (l.block < 64 || l.block > kBucketMaxBlock || l.block % 64)
+      return set_error(MC_ERR_INVALID_ARG, "the bucket scheme runs 64..512 threads per workgroup");
+    if (l.neurons_per_wg < 0 || l.neurons_per_wg % 4 || l.neurons_per_wg > std::min(kBucketMaxB, 6 * l.block))
+      return set_error(MC_ERR_INVALID_ARG, "bucket scheme: neurons_per_wg must be a multiple of 4, <= min(2048, 6 x block)");
+    if (l.steps_per_graph < 0 || l.steps_per_graph > 100000) return set_error(MC_ERR_INVALID_ARG, "steps_per_graph out of [0, 100000]");
+    if (l.rows_per_wave != 0 && l.rows_per_wave != 1) return set_error(MC_ERR_INVALID_ARG, "rows_per_wave must be 0 or 1");
+    return MC_OK;
+  }
   if (l.block < 64 || l.block > 1024 || l.block % 64) return set_error(MC_ERR_INVALID_ARG, "block must be a multiple of 64 in [64, 1024]");
   if (l.scheme == MC_SCHEME_PERSISTENT_LDS && l.block > kPersistMaxBlock)
     return set_error(MC_ERR_INVALID_ARG, "the persistent scheme runs at most 512 threads per workgroup");
@@ -393,6 +474,7 @@ int validate_launch(const mc_net* n, const mc_launch& l) {
     return set_error(MC_ERR_INVALID_ARG, "neurons_per_wg must be a multiple of 4, <= min(4*block, 1024) (step "
                                          "kernels) or <= block (persistent)");
   if (l.steps_per_graph < 0 || l.steps_per_graph > 100000) return set_error(MC_ERR_INVALID_ARG, "steps_per_graph out of [0, 100000]");
+  if (l.rows_per_wave != 0 && l.rows_per_wave != 1) return set_error(MC_ERR_INVALID_ARG, "rows_per_wave must be 0 or 1");
   (void)n;
   return MC_OK;
 }
@@ -435,10 +517,60 @@ int persist_shape(mc_net* n, const mc_launch& l, int* G, int* B, int* DL, std::v
   return MC_OK;
 }
 
-// Target blocks of the owner kernel: every instance's padded range split
-// into blocks of at most `targets` targets (no block spans two instances),
-// and each row's sub-row bounds for the blocks of its own instance.
-int setup_owner(mc_net* n, int targets) {
+// Blocks of at most `targets` targets (a multiple of 4) that every
+// instance's padded range is split into (no block spans two instances).
+int64_t owner_block_count(const mc_net* n, int targets) {
+  int64_t G = 0;
+  for (int b = 0; b < n->h.n_inst; ++b)
+    G += std::max<int64_t>(1, (n->inst_off_pad[b + 1] - n->inst_off_pad[b] + targets - 1) / targets);
+  return G;
+}
+
+// Targets per workgroup of the bucket scheme: neurons_per_wg, or (0) the
+// smallest multiple of 4 for which all workgroups are co-resident.  Every
+// instance may have at most kBucketMaxProducers workgroups and at most two
+// per thread (the listing of a step with more spikes than the LDS list
+// holds sums two producers per thread).
+int bucket_shape(mc_net* n, const mc_launch& l, int* B_out) {
+  const int bmax = std::min(kBucketMaxB, 6 * l.block);
+  auto fits = [&](int B, std::string* why) -> bool {
+    int occ = 0;
+    if (bucket_occupancy(B, l.block, &occ) != hipSuccess) { (void)hipGetLastError(); occ = 0; }
+    const int64_t G = owner_block_count(n, B);
+    int64_t gmax = 0;
+    for (int b = 0; b < n->h.n_inst; ++b)
+      gmax = std::max<int64_t>(gmax, (n->inst_off_pad[b + 1] - n->inst_off_pad[b] + B - 1) / B);
+    if (gmax > kBucketMaxProducers || gmax > 2 * l.block) {
+      if (why) *why = "an instance would have more than min(512, 2 x threads) workgroups";
+      return false;
+    }
+    if (occ < 1 || G > (int64_t)n->n_cu * occ) {
+      if (why) *why = "bucket workgroups would not all be co-resident";
+      return false;
+    }
+    return true;
+  };
+  std::string why;
+  if (l.neurons_per_wg) {
+    if (l.neurons_per_wg > bmax) return set_error(MC_ERR_RANGE, "bucket scheme: at most min(2048, 6 x threads) targets per workgroup");
+    if (!fits(l.neurons_per_wg, &why)) return set_error(MC_ERR_RANGE, "bucket scheme: " + why);
+    *B_out = l.neurons_per_wg;
+    return MC_OK;
+  }
+  int occ = 1;
+  (void)bucket_occupancy(bmax, l.block, &occ);
+  int B = (int)align_up(std::max<int64_t>(4, (n->n_pad + (int64_t)n->n_cu * std::max(occ, 1) - 1) /
+                                                  ((int64_t)n->n_cu * std::max(occ, 1))), 4);
+  for (; B <= bmax; B += 4)
+    if (fits(B, &why)) { *B_out = B; return MC_OK; }
+  return set_error(MC_ERR_RANGE, "bucket scheme: no co-resident shape for this network at this block size");
+}
+
+// Target blocks of the owner kernel and of the bucket kernel: every
+// instance's padded range split into owner_block_count blocks of whole quads
+// of at most `targets` targets, and each row's sub-row bounds for the blocks
+// of its own instance.
+int setup_owner(mc_net* n, int targets, int max_targets) {
   const int ni = n->h.n_inst;
   std::vector<int> bt0, binst, blb, ifb((size_t)ni);
   for (int b = 0; b < ni; ++b) {
@@ -446,7 +578,7 @@ int setup_owner(mc_net* n, int targets) {
     const int64_t G = std::max<int64_t>(1, (L + targets - 1) / targets);
     ifb[b] = (int)bt0.size();
     for (int64_t j = 0; j < G; ++j) {
-      bt0.push_back((int)(p0 + L * j / G));
+      bt0.push_back((int)(p0 + 4 * ((L / 4) * j / G)));
       binst.push_back(b);
       blb.push_back((int)j);
     }
@@ -455,21 +587,21 @@ int setup_owner(mc_net* n, int targets) {
   bt0.push_back((int)n->n_pad);
   int bmax = 1;
   for (int k = 0; k < nb; ++k) bmax = std::max(bmax, bt0[k + 1] - bt0[k]);
-  if (bmax > kOwnerMaxTargets) return set_error(MC_ERR_INVALID_ARG, "owner blocks hold at most 1024 targets");
+  if (bmax > max_targets) return set_error(MC_ERR_INVALID_ARG, "target blocks hold at most " + std::to_string(max_targets) + " targets");
   std::vector<int64_t> boff((size_t)n->n_pad + 1, 0);
   for (int b = 0; b < ni; ++b) {
     const int nblk = ((b + 1 < ni) ? ifb[b + 1] : nb) - ifb[b];
     for (int64_t i = n->inst_off_pad[b]; i < n->inst_off_pad[b + 1]; ++i) boff[i + 1] = boff[i] + nblk + 1;
   }
   int rc;
-  dev_free(n->d_bt0); dev_free(n->d_binst); dev_free(n->d_blb); dev_free(n->d_ifb); dev_free(n->d_boff);
-  dev_free(n->d_blk2);
-  if ((rc = dev_alloc(&n->d_bt0, (size_t)nb + 1)) != MC_OK) return rc;
-  if ((rc = dev_alloc(&n->d_binst, (size_t)nb)) != MC_OK) return rc;
-  if ((rc = dev_alloc(&n->d_blb, (size_t)nb)) != MC_OK) return rc;
-  if ((rc = dev_alloc(&n->d_ifb, (size_t)ni)) != MC_OK) return rc;
-  if ((rc = dev_alloc(&n->d_boff, (size_t)n->n_pad + 1)) != MC_OK) return rc;
-  if ((rc = dev_alloc(&n->d_blk2, (size_t)boff[n->n_pad])) != MC_OK) return rc;
+  dev_free(n->alloc, n->d_bt0); dev_free(n->alloc, n->d_binst); dev_free(n->alloc, n->d_blb); dev_free(n->alloc, n->d_ifb); dev_free(n->alloc, n->d_boff);
+  dev_free(n->alloc, n->d_blk2);
+  if ((rc = dev_alloc(n->alloc, &n->d_bt0, (size_t)nb + 1)) != MC_OK) return rc;
+  if ((rc = dev_alloc(n->alloc, &n->d_binst, (size_t)nb)) != MC_OK) return rc;
+  if ((rc = dev_alloc(n->alloc, &n->d_blb, (size_t)nb)) != MC_OK) return rc;
+  if ((rc = dev_alloc(n->alloc, &n->d_ifb, (size_t)ni)) != MC_OK) return rc;
+  if ((rc = dev_alloc(n->alloc, &n->d_boff, (size_t)n->n_pad + 1)) != MC_OK) return rc;
+  if ((rc = dev_alloc(n->alloc, &n->d_blk2, (size_t)boff[n->n_pad])) != MC_OK) return rc;
   HIP_TRY(hipMemcpy(n->d_bt0, bt0.data(), sizeof(int) * (nb + 1), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(n->d_binst, binst.data(), sizeof(int) * nb, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(n->d_blb, blb.data(), sizeof(int) * nb, hipMemcpyHostToDevice));
@@ -496,16 +628,23 @@ int apply_launch(mc_net* n, const mc_launch& l) {
     if (qpw == 0) qpw = std::min<int>(l.block, 64);
     n_wg = (int)((n->n_quads + qpw - 1) / qpw);
     wg_neurons = 4 * qpw;
-  } else {
+  } else if (l.scheme == MC_SCHEME_PERSISTENT_LDS) {
     if ((rc = persist_shape(n, l, &G, &B, &DL, bs)) != MC_OK) return rc;
+    n_wg = G;
+    wg_neurons = B;
+  } else {
+    if ((rc = bucket_shape(n, l, &B)) != MC_OK) return rc;
+    G = (int)owner_block_count(n, B);
     n_wg = G;
     wg_neurons = B;
   }
   const bool shape_changed = (l.scheme != n->launch.scheme || n_wg != n->n_wg || wg_neurons != n->wg_neurons ||
                               (l.scheme == MC_SCHEME_PERSISTENT_LDS && bs != n->bstart_host) ||
                               (l.scheme == MC_SCHEME_TARGET_OWNER &&
-                               n->own_targets != (l.neurons_per_wg ? l.neurons_per_wg : 256)));
-  if (n->graph && (shape_changed || l.steps_per_graph != n->graph_steps || l.block != n->launch.block)) {
+                               n->own_targets != (l.neurons_per_wg ? l.neurons_per_wg : 256)) ||
+                              (l.scheme == MC_SCHEME_PERSISTENT_BUCKETS && n->own_targets != B));
+  if (n->graph && (shape_changed || l.steps_per_graph != n->graph_steps || l.block != n->launch.block ||
+                   l.rows_per_wave != n->launch.rows_per_wave)) {
     (void)hipGraphExecDestroy(n->graph);
     n->graph = nullptr;
   }
@@ -520,19 +659,19 @@ int apply_launch(mc_net* n, const mc_launch& l) {
     if ((rc = fold_counters(n)) != MC_OK) return rc;
     release_recording(n);   // sized for the old shape
     if (l.scheme == MC_SCHEME_PERSISTENT_LDS) {
-      dev_free(n->d_blk); dev_free(n->d_flags); dev_free(n->d_pub); dev_free(n->d_bstart);
-      if ((rc = dev_alloc(&n->d_blk, (size_t)n->n_pad * (G + 1))) != MC_OK) return rc;
-      if ((rc = dev_alloc(&n->d_flags, persist_flag_words(G))) != MC_OK) return rc;
-      if ((rc = dev_alloc(&n->d_pub, (size_t)G * kRecSlots * B)) != MC_OK) return rc;
-      if ((rc = dev_alloc(&n->d_bstart, (size_t)G + 1)) != MC_OK) return rc;
+      dev_free(n->alloc, n->d_blk); dev_free(n->alloc, n->d_flags); dev_free(n->alloc, n->d_pub); dev_free(n->alloc, n->d_bstart);
+      if ((rc = dev_alloc(n->alloc, &n->d_blk, (size_t)n->n_pad * (G + 1))) != MC_OK) return rc;
+      if ((rc = dev_alloc(n->alloc, &n->d_flags, persist_flag_words(G))) != MC_OK) return rc;
+      if ((rc = dev_alloc(n->alloc, &n->d_pub, (size_t)G * kRecSlots * B)) != MC_OK) return rc;
+      if ((rc = dev_alloc(n->alloc, &n->d_bstart, (size_t)G + 1)) != MC_OK) return rc;
       HIP_TRY(hipMemcpy(n->d_bstart, bs.data(), sizeof(int) * (G + 1), hipMemcpyHostToDevice));
       n->bstart_host = bs;
       HIP_TRY(launch_build_blk(n->d_row_ptr, n->d_tgt, n->n_pad, G, n->d_bstart, n->d_blk, n->stream));
       HIP_TRY(hipMemsetAsync(n->d_flags, 0, sizeof(unsigned long long) * persist_flag_words(G), n->stream));
       // near table: the delay-1/2 synapses per (source, workgroup), CSR
-      dev_free(n->d_nb); dev_free(n->d_ne);
+      dev_free(n->alloc, n->d_nb); dev_free(n->alloc, n->d_ne);
       const size_t cells = (size_t)n->n_pad * (G + 1);
-      if ((rc = dev_alloc(&n->d_nb, cells)) != MC_OK) return rc;
+      if ((rc = dev_alloc(n->alloc, &n->d_nb, cells)) != MC_OK) return rc;
       HIP_TRY(launch_near_count(n->d_tgt, n->d_dly, n->d_blk, n->n_pad, G, n->d_nb, n->stream));
       std::vector<unsigned> hc;
       try { hc.resize(cells); } catch (...) { return set_error(MC_ERR_OOM, "host allocation of the near-table offsets failed"); }
@@ -542,13 +681,25 @@ int apply_launch(mc_net* n, const mc_launch& l) {
       for (size_t k = 0; k < cells; ++k) { const unsigned c = hc[k]; hc[k] = (unsigned)total; total += c; }
       if (total >= ((uint64_t)1 << 32)) return set_error(MC_ERR_RANGE, "more than 2^32 delay-1/2 synapses");
       HIP_TRY(hipMemcpy(n->d_nb, hc.data(), sizeof(unsigned) * cells, hipMemcpyHostToDevice));
-      if ((rc = dev_alloc(&n->d_ne, (size_t)std::max<uint64_t>(total, 1))) != MC_OK) return rc;
+      if ((rc = dev_alloc(n->alloc, &n->d_ne, (size_t)std::max<uint64_t>(total, 1))) != MC_OK) return rc;
       HIP_TRY(launch_near_fill(n->d_tgt, n->d_wq, n->d_dly, n->d_blk, n->d_bstart, n->n_pad, G, n->d_nb, n->d_ne,
                                n->stream));
       HIP_TRY(hipStreamSynchronize(n->stream));
     }
-    if (l.scheme == MC_SCHEME_TARGET_OWNER && (rc = setup_owner(n, l.neurons_per_wg ? l.neurons_per_wg : 256)) != MC_OK)
+    if (l.scheme == MC_SCHEME_TARGET_OWNER &&
+        (rc = setup_owner(n, l.neurons_per_wg ? l.neurons_per_wg : 256, kOwnerMaxTargets)) != MC_OK)
       return rc;
+    if (l.scheme == MC_SCHEME_PERSISTENT_BUCKETS) {
+      if ((rc = setup_owner(n, B, kBucketMaxB)) != MC_OK) return rc;
+      G = n->own_blocks;
+      dev_free(n->alloc, n->d_flags); dev_free(n->alloc, n->d_pub); dev_free(n->alloc, n->d_bk);
+      n->bk_cap = kBucketCap;
+      if ((rc = dev_alloc(n->alloc, &n->d_flags, persist_flag_words(G))) != MC_OK) return rc;
+      if ((rc = dev_alloc(n->alloc, &n->d_pub, (size_t)G * kRecSlots * B)) != MC_OK) return rc;
+      if ((rc = dev_alloc(n->alloc, &n->d_bk, (size_t)G * kRingSlots * n->bk_cap)) != MC_OK) return rc;
+      HIP_TRY(hipMemsetAsync(n->d_flags, 0, sizeof(unsigned long long) * persist_flag_words(G), n->stream));
+      HIP_TRY(hipStreamSynchronize(n->stream));
+    }
     n->qpw = qpw;
     n->n_wg = n_wg;
     n->wg_neurons = wg_neurons;
@@ -566,7 +717,8 @@ hipError_t enqueue_direct(mc_net* n, int count, hipStream_t s) {
   const DevNet p = n->dev();
   hipError_t e = hipSuccess;
   if (n->launch.scheme == MC_SCHEME_STEP_KERNELS) {
-    for (int k = 0; k < count && e == hipSuccess; ++k) e = launch_step(p, k, n->qpw, n->n_wg, n->launch.block, s);
+    for (int k = 0; k < count && e == hipSuccess; ++k)
+      e = launch_step(p, k, n->qpw, n->n_wg, n->launch.block, n->launch.rows_per_wave, s);
   } else if (n->launch.scheme == MC_SCHEME_TARGET_OWNER) {
     const OwnerArgs a = n->owner();
     e = launch_zero_lists(n->d_icnt, 2 * n->h.n_inst, s);
@@ -574,8 +726,10 @@ hipError_t enqueue_direct(mc_net* n, int count, hipStream_t s) {
       e = launch_step_lists(p, k, n->qpw, n->n_wg, n->launch.block, s);
       if (e == hipSuccess) e = launch_owner(p, a, k, s);
     }
+  } else if (n->launch.scheme == MC_SCHEME_PERSISTENT_BUCKETS) {
+    return launch_bucket(p, n->bucket(), count, n->launch.block, s);     // advances the step counter itself
   } else {
-    e = launch_persist(p, n->persist(), count, n->launch.block, s);
+    return launch_persist(p, n->persist(), count, n->launch.block, s);   // advances the step counter itself
   }
   if (e == hipSuccess) e = launch_advance(n->d_step, count, s);
   return e;
@@ -601,6 +755,21 @@ int build_graph(mc_net* n) {
   return MC_OK;
 }
 
+constexpr int kLaunchEvents = 128;
+
+// Records the event that opens (begin) or closes a timed persistent launch on
+// the simulation stream; beyond kLaunchEvents / 2 launches nothing is timed.
+int launch_event(mc_net* n, bool begin, int64_t steps) {
+  if ((n->launch.scheme != MC_SCHEME_PERSISTENT_LDS && n->launch.scheme != MC_SCHEME_PERSISTENT_BUCKETS) ||
+      n->ev_launch.size() < (size_t)kLaunchEvents)
+    return MC_OK;
+  const int k = 2 * n->launches_timed + (begin ? 0 : 1);
+  if (k >= kLaunchEvents) return MC_OK;
+  HIP_TRY(hipEventRecord(n->ev_launch[(size_t)k], n->stream));
+  if (!begin) { ++n->launches_timed; n->steps_timed += steps; }
+  return MC_OK;
+}
+
 // Enqueues `steps` steps (no synchronization).  Steps are replayed from a
 // graph of steps_per_graph steps where possible (0: never).
 int enqueue_steps(mc_net* n, int64_t steps) {
@@ -617,11 +786,17 @@ int enqueue_steps(mc_net* n, int64_t steps) {
     if (S > 0 && chunk >= S) {
       if ((rc = build_graph(n)) != MC_OK) return rc;
       const int64_t reps = chunk / S;
-      for (int64_t k = 0; k < reps; ++k) HIP_TRY(hipGraphLaunch(n->graph, n->stream));
+      for (int64_t k = 0; k < reps; ++k) {
+        if ((rc = launch_event(n, true, S)) != MC_OK) return rc;
+        HIP_TRY(hipGraphLaunch(n->graph, n->stream));
+        if ((rc = launch_event(n, false, S)) != MC_OK) return rc;
+      }
       chunk = reps * S;
     } else {
       chunk = std::min<int64_t>(chunk, 1 << 20);
+      if ((rc = launch_event(n, true, chunk)) != MC_OK) return rc;
       HIP_TRY(enqueue_direct(n, (int)chunk, n->stream));
+      if ((rc = launch_event(n, false, chunk)) != MC_OK) return rc;
     }
     n->steps_since_drain += chunk;
     n->step += chunk;
@@ -674,27 +849,28 @@ int upload_network(mc_net* n) {
     for (int64_t e = h.row_ptr[h.inst_off[b]]; e < h.row_ptr[h.inst_off[b + 1]]; ++e) tg[e] += (int32_t)shift;
   }
   (void)N;
-  if ((rc = dev_alloc(&n->d_row_ptr, (size_t)P + 1)) != MC_OK) return rc;
-  if ((rc = dev_alloc(&n->d_tgt, (size_t)M)) != MC_OK) return rc;
-  if ((rc = dev_alloc(&n->d_wq, (size_t)M)) != MC_OK) return rc;
-  if ((rc = dev_alloc(&n->d_dly, (size_t)M)) != MC_OK) return rc;
-  if ((rc = dev_alloc(&n->d_y, (size_t)P)) != MC_OK) return rc;
-  if ((rc = dev_alloc(&n->d_I, (size_t)P)) != MC_OK) return rc;
-  if ((rc = dev_alloc(&n->d_r, (size_t)P)) != MC_OK) return rc;
-  if ((rc = dev_alloc(&n->d_ring, (size_t)kRingSlots * n->ring_stride)) != MC_OK) return rc;
-  if ((rc = dev_alloc(&n->d_qseed, (size_t)n->n_quads)) != MC_OK) return rc;
-  if ((rc = dev_alloc(&n->d_qlocal, (size_t)n->n_quads)) != MC_OK) return rc;
-  if ((rc = dev_alloc(&n->d_qpops, (size_t)n->n_quads)) != MC_OK) return rc;
-  if ((rc = dev_alloc(&n->d_table, h.table.size())) != MC_OK) return rc;
-  if ((rc = dev_alloc(&n->d_step, 1)) != MC_OK) return rc;
-  if ((rc = dev_alloc(&n->d_overflow, 1)) != MC_OK) return rc;
+  if ((rc = dev_alloc(n->alloc, &n->d_row_ptr, (size_t)P + 1)) != MC_OK) return rc;
+  if ((rc = dev_alloc(n->alloc, &n->d_tgt, (size_t)M)) != MC_OK) return rc;
+  if ((rc = dev_alloc(n->alloc, &n->d_wq, (size_t)M)) != MC_OK) return rc;
+  if ((rc = dev_alloc(n->alloc, &n->d_dly, (size_t)M)) != MC_OK) return rc;
+  if ((rc = dev_alloc(n->alloc, &n->d_y, (size_t)P)) != MC_OK) return rc;
+  if ((rc = dev_alloc(n->alloc, &n->d_I, (size_t)P)) != MC_OK) return rc;
+  if ((rc = dev_alloc(n->alloc, &n->d_r, (size_t)P)) != MC_OK) return rc;
+  if ((rc = dev_alloc(n->alloc, &n->d_ring, (size_t)kRingSlots * n->ring_stride)) != MC_OK) return rc;
+  if ((rc = dev_alloc(n->alloc, &n->d_qseed, (size_t)n->n_quads)) != MC_OK) return rc;
+  if ((rc = dev_alloc(n->alloc, &n->d_qlocal, (size_t)n->n_quads)) != MC_OK) return rc;
+  if ((rc = dev_alloc(n->alloc, &n->d_qpops, (size_t)n->n_quads)) != MC_OK) return rc;
+  if ((rc = dev_alloc(n->alloc, &n->d_table, h.table.size())) != MC_OK) return rc;
+  if ((rc = dev_alloc(n->alloc, &n->d_step, 1)) != MC_OK) return rc;
+  if ((rc = dev_alloc(n->alloc, &n->d_overflow, 1)) != MC_OK) return rc;
+  if ((rc = dev_alloc(n->alloc, &n->d_wbad, 1)) != MC_OK) return rc;
   std::vector<int32_t> qinst((size_t)n->n_quads);
   for (int b = 0; b < h.n_inst; ++b)
     for (int64_t qq = n->inst_off_pad[b] / 4; qq < n->inst_off_pad[b + 1] / 4; ++qq) qinst[qq] = b;
-  if ((rc = dev_alloc(&n->d_qinst, (size_t)n->n_quads)) != MC_OK) return rc;
-  if ((rc = dev_alloc(&n->d_inst_base, (size_t)h.n_inst + 1)) != MC_OK) return rc;
-  if ((rc = dev_alloc(&n->d_ilist, (size_t)2 * P)) != MC_OK) return rc;
-  if ((rc = dev_alloc(&n->d_icnt, (size_t)2 * h.n_inst)) != MC_OK) return rc;
+  if ((rc = dev_alloc(n->alloc, &n->d_qinst, (size_t)n->n_quads)) != MC_OK) return rc;
+  if ((rc = dev_alloc(n->alloc, &n->d_inst_base, (size_t)h.n_inst + 1)) != MC_OK) return rc;
+  if ((rc = dev_alloc(n->alloc, &n->d_ilist, (size_t)2 * P)) != MC_OK) return rc;
+  if ((rc = dev_alloc(n->alloc, &n->d_icnt, (size_t)2 * h.n_inst)) != MC_OK) return rc;
   HIP_TRY(hipMemcpy(n->d_qinst, qinst.data(), sizeof(int32_t) * n->n_quads, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(n->d_inst_base, n->inst_off_pad.data(), sizeof(int64_t) * (h.n_inst + 1), hipMemcpyHostToDevice));
   HIP_TRY(hipMemset(n->d_icnt, 0, sizeof(int) * 2 * h.n_inst));
@@ -738,6 +914,7 @@ const char* mc_strerror(int code) {
     case MC_ERR_BUFFER_TOO_SMALL: return "buffer too small";
     case MC_ERR_NO_DEVICE: return "no usable gfx950 device";
     case MC_ERR_MISMATCH: return "recomputation did not reproduce the recorded spikes";
+    case MC_ERR_TIMEOUT: return "persistent kernel timed out waiting for spike records";
     default: return "unknown error";
   }
 }
@@ -748,15 +925,22 @@ int mc_build_network(const mc_config* cfg, mc_net** out) {
   if (!cfg) return set_error(MC_ERR_INVALID_ARG, "cfg is NULL");
   std::unique_ptr<mc_net> n;
   try { n.reset(new mc_net()); } catch (...) { return set_error(MC_ERR_OOM, "host allocation failed"); }
+  if ((cfg->dev_alloc == nullptr) != (cfg->dev_free == nullptr))
+    return set_error(MC_ERR_INVALID_ARG, "dev_alloc and dev_free must be given together");
+  if (cfg->struct_size == sizeof(mc_config)) {
+    n->alloc.fn = cfg->dev_alloc;
+    n->alloc.fr = cfg->dev_free;
+    n->alloc.ctx = cfg->alloc_ctx;
+  }
   std::string err;
   int rc;
-  // connections of the Bernoulli rule drawn on the device, on request
+  // connections drawn on the device, on request
   std::unique_ptr<ConnBuilder> conn;
   hipStream_t conn_stream = nullptr;
   if ((cfg->flags & MC_FLAG_DEVICE_CONNECT) != 0) {
     if ((cfg->flags & MC_FLAG_HOST_ONLY) != 0)
       return set_error(MC_ERR_INVALID_ARG, "MC_FLAG_DEVICE_CONNECT needs the device (MC_FLAG_HOST_ONLY given)");
-    if (cfg->rule == MC_RULE_BERNOULLI) {
+    {
       int ndev = 0, dev = 0;
       hipDeviceProp_t prop;
       if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1 || hipGetDevice(&dev) != hipSuccess ||
@@ -782,6 +966,8 @@ int mc_build_network(const mc_config* cfg, mc_net** out) {
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
       return set_error(MC_ERR_NO_DEVICE, std::string("device is ") + prop.gcnArchName + ", library built for gfx950");
     n->n_cu = prop.multiProcessorCount;
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, n->device) == hipSuccess && khz > 0) n->wall_khz = khz;
     int optin = 0;
     if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, n->device) == hipSuccess && optin > 0)
       n->lds_max = optin;
@@ -797,9 +983,16 @@ int mc_build_network(const mc_config* cfg, mc_net** out) {
       return set_error(MC_ERR_HIP, "stream creation failed");
     }
     rc = upload_network(n.get());
+    // pending input lies at most max_delay slots ahead (until an injection or a loaded state)
+    n->horizon = std::max(1, n->h.max_delay);
     if (rc == MC_OK && hipEventCreate(&n->ev0) != hipSuccess) rc = set_error(MC_ERR_HIP, "event creation failed");
     if (rc == MC_OK && hipEventCreate(&n->ev1) != hipSuccess) rc = set_error(MC_ERR_HIP, "event creation failed");
     if (rc == MC_OK && hipEventCreate(&n->ev_mid) != hipSuccess) rc = set_error(MC_ERR_HIP, "event creation failed");
+    for (int k = 0; rc == MC_OK && k < kLaunchEvents; ++k) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) rc = set_error(MC_ERR_HIP, "event creation failed");
+      else n->ev_launch.push_back(e);
+    }
     if (rc == MC_OK) {
       mc_launch l{};
       l.struct_size = sizeof(mc_launch);
@@ -830,9 +1023,26 @@ int mc_simulate(mc_net* n, int64_t steps) {
   if (steps < 0) return set_error(MC_ERR_INVALID_ARG, "steps < 0");
   if (n->step + steps > 2147483647LL) return set_error(MC_ERR_RANGE, "step count beyond int32 raster steps");
   HIP_TRY(hipEventRecord(n->ev0, n->stream));
+  n->launches_timed = 0;
+  n->steps_timed = 0;
   int rc = enqueue_steps(n, steps);
   if (rc != MC_OK) { n->failed = true; return rc; }
   HIP_TRY(hipEventRecord(n->ev1, n->stream));
+  return MC_OK;
+}
+
+int mc_last_kernel_ms(mc_net* n, double* ms_out, int64_t* launches_out, int64_t* steps_out) {
+  if (!device_ready(n) || !ms_out || !launches_out || !steps_out) return set_error(MC_ERR_INVALID_ARG, "bad handle or NULL output");
+  HIP_TRY(hipEventSynchronize(n->ev1));
+  double total = 0.0;
+  for (int k = 0; k < n->launches_timed; ++k) {
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, n->ev_launch[(size_t)2 * k], n->ev_launch[(size_t)2 * k + 1]));
+    total += ms;
+  }
+  *ms_out = total;
+  *launches_out = n->launches_timed;
+  *steps_out = n->steps_timed;
   return MC_OK;
 }
 
@@ -966,6 +1176,7 @@ int mc_inject(mc_net* n, int64_t k, int64_t neuron, int64_t value) {
   if (k < 0 || k >= kRingSlots - 1 || neuron < 0 || neuron >= n->h.N) return set_error(MC_ERR_INVALID_ARG, "k or neuron out of range");
   const int64_t s = (n->step + k) & kRingMask;
   HIP_TRY(launch_inject(n->d_ring, s * n->ring_stride + n->pad_of(neuron), value, n->stream));
+  n->horizon = std::max(n->horizon, (int)k + 1);
   return MC_OK;
 }
 
@@ -1006,15 +1217,37 @@ int mc_stream(mc_net* n, void** s) {
   return MC_OK;
 }
 
-int mc_set_weights(mc_net* n, const double* w_dev) {
-  if (!device_ready(n) || !w_dev) return set_error(MC_ERR_INVALID_ARG, "bad handle or NULL");
-  HIP_TRY(launch_set_weights(n->d_wq, w_dev, n->h.M, n->stream));
-  if (n->d_ne)   // the persistent scheme's near table holds copies of the delay-1/2 weights
+// Replaces every weight (mode 0: from pA values; 1/2: one gradient step):
+// a check pass first, so that a rejected update leaves the store unchanged;
+// then the store, the persistent scheme's near-table copies of the delay-1/2
+// weights and the host copy.
+static int update_weights(mc_net* n, const void* src, int mode, double eta) {
+  HIP_TRY(hipMemsetAsync(n->d_wbad, 0, sizeof(unsigned), n->stream));
+  HIP_TRY(launch_weights(n->d_wq, src, mode, eta, n->h.M, n->d_wbad, true, n->stream));
+  unsigned bad = 0;
+  HIP_TRY(hipMemcpyAsync(&bad, n->d_wbad, sizeof(unsigned), hipMemcpyDeviceToHost, n->stream));
+  HIP_TRY(hipStreamSynchronize(n->stream));
+  if (bad) return set_error(MC_ERR_RANGE, "a new weight is not finite or does not fit int32 in units of 2^-16 pA "
+                                          "(|w| < 32768 pA); the store is unchanged");
+  HIP_TRY(launch_weights(n->d_wq, src, mode, eta, n->h.M, n->d_wbad, false, n->stream));
+  if (n->d_ne)
     HIP_TRY(launch_near_fill(n->d_tgt, n->d_wq, n->d_dly, n->d_blk, n->d_bstart, n->n_pad, n->pG, n->d_nb, n->d_ne,
                              n->stream));
   HIP_TRY(hipStreamSynchronize(n->stream));
   HIP_TRY(hipMemcpy(n->h.wq.data(), n->d_wq, sizeof(int32_t) * n->h.M, hipMemcpyDeviceToHost));
   return MC_OK;
+}
+
+int mc_set_weights(mc_net* n, const double* w_dev) {
+  if (!device_ready(n) || !w_dev) return set_error(MC_ERR_INVALID_ARG, "bad handle or NULL");
+  return update_weights(n, w_dev, 0, 0.0);
+}
+
+int mc_apply_gradient(mc_net* n, const void* grad_dev, int32_t grad_dtype, double eta) {
+  if (!device_ready(n) || !grad_dev) return set_error(MC_ERR_INVALID_ARG, "bad handle or NULL gradient");
+  if (grad_dtype != MC_GRAD_F64 && grad_dtype != MC_GRAD_F32) return set_error(MC_ERR_INVALID_ARG, "unknown grad_dtype");
+  if (!std::isfinite(eta)) return set_error(MC_ERR_INVALID_ARG, "eta is not finite");
+  return update_weights(n, grad_dev, grad_dtype == MC_GRAD_F64 ? 1 : 2, eta);
 }
 
 // Blob: header, y/I/r (padded), ring (all slots), counters.
@@ -1062,6 +1295,7 @@ int mc_load_state(mc_net* n, const void* blob, size_t size) {
   HIP_TRY(hipMemcpy(n->d_I, o, sizeof(double) * P, hipMemcpyHostToDevice)); o += sizeof(double) * P;
   HIP_TRY(hipMemcpy(n->d_r, o, sizeof(int32_t) * P, hipMemcpyHostToDevice)); o += sizeof(int32_t) * P;
   HIP_TRY(hipMemcpy(n->d_ring, o, sizeof(long long) * kRingSlots * n->ring_stride, hipMemcpyHostToDevice));
+  n->horizon = kRingSlots - 1;         // a loaded ring may hold input anywhere
   long long st = hd.step;
   HIP_TRY(hipMemcpy(n->d_step, &st, sizeof(long long), hipMemcpyHostToDevice));
   n->step = hd.step;
@@ -1084,8 +1318,8 @@ int mc_profile_phases(mc_net* n, int64_t steps, double* us) {
   if (n->launch.scheme != MC_SCHEME_PERSISTENT_LDS) return set_error(MC_ERR_STATE, "phase timing needs the persistent scheme");
   if (steps < 1 || n->step + steps > 2147483647LL) return set_error(MC_ERR_INVALID_ARG, "steps out of range");
   int rc;
-  dev_free(n->d_phase);
-  if ((rc = dev_alloc(&n->d_phase, (size_t)n->pG * 8)) != MC_OK) return rc;
+  dev_free(n->alloc, n->d_phase);
+  if ((rc = dev_alloc(n->alloc, &n->d_phase, (size_t)n->pG * 8)) != MC_OK) return rc;
   HIP_TRY(hipMemsetAsync(n->d_phase, 0, sizeof(unsigned long long) * n->pG * 8, n->stream));
   // direct launches: a captured graph would carry the timing-off arguments
   if (n->graph) { (void)hipGraphExecDestroy(n->graph); n->graph = nullptr; }
@@ -1149,9 +1383,9 @@ int mc_replay_delivery(mc_net* n, int64_t b, int64_t e, int64_t* ring_out, int64
   int2* d_sp = nullptr;
   long long* d_first = nullptr;
   long long* d_ring = nullptr;
-  if ((rc = dev_alloc(&d_sp, std::max<size_t>(cnt, 1))) != MC_OK) return rc;
-  if ((rc = dev_alloc(&d_first, cnt + 1)) != MC_OK) { dev_free(d_sp); return rc; }
-  if ((rc = dev_alloc(&d_ring, (size_t)slots * n->ring_stride)) != MC_OK) { dev_free(d_sp); dev_free(d_first); return rc; }
+  if ((rc = dev_alloc(n->alloc, &d_sp, std::max<size_t>(cnt, 1))) != MC_OK) return rc;
+  if ((rc = dev_alloc(n->alloc, &d_first, cnt + 1)) != MC_OK) { dev_free(n->alloc, d_sp); return rc; }
+  if ((rc = dev_alloc(n->alloc, &d_ring, (size_t)slots * n->ring_stride)) != MC_OK) { dev_free(n->alloc, d_sp); dev_free(n->alloc, d_first); return rc; }
   hipError_t err = hipSuccess;
   if (cnt) err = hipMemcpy(d_sp, sp.data(), sizeof(int2) * cnt, hipMemcpyHostToDevice);
   if (err == hipSuccess) err = hipMemcpy(d_first, first.data(), sizeof(long long) * (cnt + 1), hipMemcpyHostToDevice);
@@ -1171,7 +1405,7 @@ int mc_replay_delivery(mc_net* n, int64_t b, int64_t e, int64_t* ring_out, int64
       for (int64_t i = 0; i < N; ++i) ring_out[k * N + i] = slot[n->pad_of(i)];
     }
   }
-  dev_free(d_sp); dev_free(d_first); dev_free(d_ring);
+  dev_free(n->alloc, d_sp); dev_free(n->alloc, d_first); dev_free(n->alloc, d_ring);
   if (err != hipSuccess) return set_error(MC_ERR_HIP, std::string("replay: ") + hipGetErrorString(err));
   if (ms_out) *ms_out = ms;
   if (events_out) *events_out = events;
@@ -1182,7 +1416,7 @@ int mc_atomic_rate(mc_net* n, int64_t entries, double* gops) {
   if (!device_ready(n) || !gops) return set_error(MC_ERR_INVALID_ARG, "bad handle or NULL");
   if (entries < 1 || entries > ((int64_t)1 << 32)) return set_error(MC_ERR_INVALID_ARG, "entries out of [1, 2^32]");
   unsigned long long* t = nullptr;
-  int rc = dev_alloc(&t, (size_t)entries);
+  int rc = dev_alloc(n->alloc, &t, (size_t)entries);
   if (rc != MC_OK) return rc;
   const int grid = n->n_cu * 8;
   const long long per_thread = 256;
@@ -1194,20 +1428,176 @@ int mc_atomic_rate(mc_net* n, int64_t entries, double* gops) {
   if (err == hipSuccess) err = hipEventSynchronize(n->ev1);
   float ms = 0;
   if (err == hipSuccess) err = hipEventElapsedTime(&ms, n->ev0, n->ev1);
-  dev_free(t);
+  dev_free(n->alloc, t);
   if (err != hipSuccess) return set_error(MC_ERR_HIP, std::string("atomic rate: ") + hipGetErrorString(err));
   *gops = (double)grid * 256.0 * per_thread / (ms * 1e-3) / 1e9;
   return MC_OK;
 }
 
-// Autotuner: times candidate launch shapes of both schemes from a saved copy
-// of the current state and keeps the fastest.  Every candidate computes the
-// same bits (integer input sums, fixed floating-point order), so the choice
-// only affects speed; state, counters and the recorded raster are restored.
+int mc_probe_stream(mc_net* n, int64_t bytes, double* gbs) {
+  if (!device_ready(n) || !gbs) return set_error(MC_ERR_INVALID_ARG, "bad handle or NULL");
+  if (bytes < (1 << 20) || bytes > ((int64_t)1 << 40)) return set_error(MC_ERR_INVALID_ARG, "bytes out of [1 MiB, 1 TiB]");
+  bytes &= ~(int64_t)15;
+  unsigned char* buf = nullptr;
+  unsigned long long* sink = nullptr;
+  int rc = dev_alloc(n->alloc, &buf, (size_t)bytes);
+  if (rc != MC_OK) return rc;
+  if ((rc = dev_alloc(n->alloc, &sink, 1)) != MC_OK) { dev_free(n->alloc, buf); return rc; }
+  const int grid = n->n_cu * 8;
+  hipError_t err = hipMemsetAsync(buf, 0x11, (size_t)bytes, n->stream);
+  if (err == hipSuccess) err = launch_stream_read(buf, bytes, sink, grid, n->stream);   // warm-up
+  if (err == hipSuccess) err = hipEventRecord(n->ev0, n->stream);
+  if (err == hipSuccess) err = launch_stream_read(buf, bytes, sink, grid, n->stream);
+  if (err == hipSuccess) err = hipEventRecord(n->ev1, n->stream);
+  if (err == hipSuccess) err = hipEventSynchronize(n->ev1);
+  float ms = 0;
+  if (err == hipSuccess) err = hipEventElapsedTime(&ms, n->ev0, n->ev1);
+  dev_free(n->alloc, buf);
+  dev_free(n->alloc, sink);
+  if (err != hipSuccess) return set_error(MC_ERR_HIP, std::string("stream probe: ") + hipGetErrorString(err));
+  *gbs = (double)bytes / (ms * 1e-3) / 1e9;
+  return MC_OK;
+}
+
+int mc_probe_atomics(mc_net* n, int64_t slots, int32_t pattern, double* gops) {
+  if (!device_ready(n) || !gops) return set_error(MC_ERR_INVALID_ARG, "bad handle or NULL");
+  if (slots < 1 || slots > 100000) return set_error(MC_ERR_INVALID_ARG, "slots out of [1, 1e5]");
+  if (pattern != 0 && pattern != 1) return set_error(MC_ERR_INVALID_ARG, "pattern must be 0 or 1");
+  // the store's delay histogram as a 32-bit cumulative table, and its mean out-degree
+  if (n->dcdf.empty()) {
+    std::vector<int64_t> hist(kRingSlots, 0);
+    for (uint8_t d : n->h.dly) hist[d]++;
+    n->dcdf.assign(kRingSlots, 0xFFFFFFFFu);
+    int64_t cum = 0;
+    const double M = (double)std::max<int64_t>(1, n->h.M);
+    for (int d = 0; d < kRingSlots; ++d) {
+      cum += hist[d];
+      const double c = std::floor((double)cum / M * 4294967296.0);
+      n->dcdf[d] = c >= 4294967295.0 ? 0xFFFFFFFFu : (unsigned)c;
+    }
+  }
+  const double deg = (double)n->h.M / (double)std::max<int64_t>(1, n->h.N);
+  const int gap = (int)std::max(1.0, std::min(1e6, std::round((double)n->h.N / std::max(1.0, deg))));
+  unsigned long long* t = nullptr;
+  unsigned* dcdf = nullptr;
+  int rc = dev_alloc(n->alloc, &t, (size_t)slots * n->ring_stride);
+  if (rc != MC_OK) return rc;
+  if ((rc = dev_alloc(n->alloc, &dcdf, kRingSlots)) != MC_OK) { dev_free(n->alloc, t); return rc; }
+  const int grid = n->n_cu * 8;
+  const long long items = 1 << 19;            // 2^27 events per launch
+  hipError_t err = hipMemcpy(dcdf, n->dcdf.data(), sizeof(unsigned) * kRingSlots, hipMemcpyHostToDevice);
+  if (err == hipSuccess) err = hipMemsetAsync(t, 0, sizeof(unsigned long long) * slots * n->ring_stride, n->stream);
+  if (err == hipSuccess)
+    err = launch_atomic_slots(t, slots, n->ring_stride, n->n_pad, items, pattern, gap, dcdf, grid, n->stream);
+  if (err == hipSuccess) err = hipEventRecord(n->ev0, n->stream);
+  if (err == hipSuccess)
+    err = launch_atomic_slots(t, slots, n->ring_stride, n->n_pad, items, pattern, gap, dcdf, grid, n->stream);
+  if (err == hipSuccess) err = hipEventRecord(n->ev1, n->stream);
+  if (err == hipSuccess) err = hipEventSynchronize(n->ev1);
+  float ms = 0;
+  if (err == hipSuccess) err = hipEventElapsedTime(&ms, n->ev0, n->ev1);
+  dev_free(n->alloc, t);
+  dev_free(n->alloc, dcdf);
+  if (err != hipSuccess) return set_error(MC_ERR_HIP, std::string("atomic probe: ") + hipGetErrorString(err));
+  *gops = (double)items * 256.0 / (ms * 1e-3) / 1e9;
+  return MC_OK;
+}
+
+int mc_probe_exchange(mc_net* n, int64_t steps, double* us) {
+  if (!device_ready(n) || !us) return set_error(MC_ERR_INVALID_ARG, "bad handle or NULL");
+  if (n->launch.scheme != MC_SCHEME_PERSISTENT_LDS) return set_error(MC_ERR_STATE, "the exchange probe takes the persistent scheme's shape");
+  if (steps < 1 || steps > 10000000) return set_error(MC_ERR_INVALID_ARG, "steps out of [1, 1e7]");
+  unsigned long long* flags = nullptr;
+  unsigned* err_word = nullptr;
+  int rc = dev_alloc(n->alloc, &flags, persist_flag_words(n->pG));
+  if (rc != MC_OK) return rc;
+  if ((rc = dev_alloc(n->alloc, &err_word, 1)) != MC_OK) { dev_free(n->alloc, flags); return rc; }
+  const long long wait = (long long)n->wall_khz * 1000 * kWaitSeconds;
+  hipError_t err = hipMemsetAsync(flags, 0, sizeof(unsigned long long) * persist_flag_words(n->pG), n->stream);
+  if (err == hipSuccess) err = hipMemsetAsync(err_word, 0, sizeof(unsigned), n->stream);
+  if (err == hipSuccess) err = launch_exchange_probe(flags, n->pG, n->launch.block, std::min<int64_t>(steps, 1000), wait, err_word, n->stream);
+  if (err == hipSuccess) err = hipEventRecord(n->ev0, n->stream);
+  if (err == hipSuccess) err = launch_exchange_probe(flags, n->pG, n->launch.block, steps, wait, err_word, n->stream);
+  if (err == hipSuccess) err = hipEventRecord(n->ev1, n->stream);
+  if (err == hipSuccess) err = hipEventSynchronize(n->ev1);
+  float ms = 0;
+  unsigned bad = 0;
+  if (err == hipSuccess) err = hipEventElapsedTime(&ms, n->ev0, n->ev1);
+  if (err == hipSuccess) err = hipMemcpy(&bad, err_word, sizeof(unsigned), hipMemcpyDeviceToHost);
+  dev_free(n->alloc, flags);
+  dev_free(n->alloc, err_word);
+  if (err != hipSuccess) return set_error(MC_ERR_HIP, std::string("exchange probe: ") + hipGetErrorString(err));
+  if (bad) return set_error(MC_ERR_TIMEOUT, "exchange probe: a workgroup's record never arrived");
+  *us = (double)ms * 1e3 / (double)steps;
+  return MC_OK;
+}
+
+// Key of the autotuner cache: the network's shape and the device.
+static std::string tune_key(mc_net* n) {
+  uint64_t h = 1469598103934665603ULL;   // FNV-1a over the shape's integers
+  auto mix = [&](uint64_t v) {
+    for (int k = 0; k < 8; ++k) { h ^= (v >> (8 * k)) & 0xFFu; h *= 1099511628211ULL; }
+  };
+  mix((uint64_t)n->h.N); mix((uint64_t)n->h.M); mix((uint64_t)n->h.n_inst); mix((uint64_t)n->h.n_pops);
+  for (int64_t v : n->h.pop_off) mix((uint64_t)v);
+  mix((uint64_t)n->h.max_delay); mix((uint64_t)n->h.max_row);
+  hipDeviceProp_t prop;
+  std::string dev = "unknown";
+  if (hipGetDeviceProperties(&prop, n->device) == hipSuccess) {
+    dev = prop.gcnArchName;
+    for (char& c : dev) if (c == ' ' || c == ':') c = '_';
+    dev += "_cu" + std::to_string(prop.multiProcessorCount);
+  }
+  char buf[32];
+  std::snprintf(buf, sizeof(buf), "%016llx", (unsigned long long)h);
+  return std::string(buf) + "_" + dev;
+}
+
+// The stored choice for `key` (the last line that names it), if any.
+static bool tune_cache_read(const char* path, const std::string& key, mc_launch* l) {
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char k[256];
+  int sc, b, npw, spg, rpw;
+  double ms;
+  bool found = false;
+  while (std::fscanf(f, "%255s %d %d %d %d %d %lf", k, &sc, &b, &npw, &spg, &rpw, &ms) == 7) {
+    if (key == k) {
+      *l = mc_launch{sizeof(mc_launch), sc, b, npw, spg, rpw};
+      found = true;
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+static void tune_cache_write(const char* path, const std::string& key, const mc_launch& l, double ms) {
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;   // an unwritable cache only costs the next run its tuning
+  std::fprintf(f, "%s %d %d %d %d %d %.6f\n", key.c_str(), l.scheme, l.block, l.neurons_per_wg, l.steps_per_graph,
+               l.rows_per_wave, ms);
+  std::fclose(f);
+}
+
+// Autotuner: times candidate launch shapes from a saved copy of the current
+// state and keeps the fastest.  Every candidate computes the same bits
+// (integer input sums, fixed floating-point order), so the choice only
+// affects speed; state, counters and the recorded raster are restored.  The
+// target-owner scheme is not a candidate: it lost to the step kernels or the
+// persistent kernel on every workload measured (a chain of dependent memory
+// round trips per step costs more than the atomics it saves).
 int mc_tune(mc_net* n, int64_t steps, mc_launch* best) {
   if (!device_ready(n)) return set_error(MC_ERR_STATE, "handle is host-only, failed or NULL");
   if (steps < 1 || steps > 100000) return set_error(MC_ERR_INVALID_ARG, "steps out of [1, 1e5]");
-  if (n->step + 2 * steps + 1000 > 2147483647LL) return set_error(MC_ERR_RANGE, "step counter too large to tune");
+  if (n->step + 2 * steps + 1000 > 2147483647LL) return set_error(MC_ERR_RANGE, "step count beyond int32 raster steps");
+  const char* cache = std::getenv("MC_TUNE_CACHE");
+  const std::string key = cache && *cache ? tune_key(n) : std::string();
+  mc_launch cached{};
+  if (!key.empty() && tune_cache_read(cache, key, &cached) && validate_launch(n, cached) == MC_OK &&
+      apply_launch(n, cached) == MC_OK) {
+    if (best) *best = cached;
+    return MC_OK;
+  }
   size_t need = 0;
   mc_save_state(n, nullptr, 0, &need);
   std::vector<char> blob;
@@ -1220,18 +1610,21 @@ int mc_tune(mc_net* n, int64_t steps, mc_launch* best) {
   // epilogue (LDS window in and out) amortise over 1 s of model time
   const int kPersistSteps = 10000;
   const mc_launch cands[] = {
-      {sizeof(mc_launch), MC_SCHEME_PERSISTENT_LDS, 512, 0, kPersistSteps},
-      {sizeof(mc_launch), MC_SCHEME_PERSISTENT_LDS, 256, 0, kPersistSteps},
-      {sizeof(mc_launch), MC_SCHEME_PERSISTENT_LDS, 512, 256, kPersistSteps},
-      {sizeof(mc_launch), MC_SCHEME_PERSISTENT_LDS, 512, 512, kPersistSteps},
-      {sizeof(mc_launch), MC_SCHEME_PERSISTENT_LDS, 256, 128, kPersistSteps},
-      {sizeof(mc_launch), MC_SCHEME_TARGET_OWNER, 256, 256, spg},
-      {sizeof(mc_launch), MC_SCHEME_TARGET_OWNER, 256, 128, spg},
-      {sizeof(mc_launch), MC_SCHEME_TARGET_OWNER, 256, 64, spg},
-      {sizeof(mc_launch), MC_SCHEME_STEP_KERNELS, 256, 256, spg},
-      {sizeof(mc_launch), MC_SCHEME_STEP_KERNELS, 256, 1024, spg},
-      {sizeof(mc_launch), MC_SCHEME_STEP_KERNELS, 512, 512, spg},
-      {sizeof(mc_launch), MC_SCHEME_STEP_KERNELS, 128, 128, spg},
+      {sizeof(mc_launch), MC_SCHEME_PERSISTENT_LDS, 512, 0, kPersistSteps, 0},
+      {sizeof(mc_launch), MC_SCHEME_PERSISTENT_LDS, 256, 0, kPersistSteps, 0},
+      {sizeof(mc_launch), MC_SCHEME_PERSISTENT_LDS, 512, 256, kPersistSteps, 0},
+      {sizeof(mc_launch), MC_SCHEME_PERSISTENT_LDS, 512, 512, kPersistSteps, 0},
+      {sizeof(mc_launch), MC_SCHEME_PERSISTENT_LDS, 256, 128, kPersistSteps, 0},
+      {sizeof(mc_launch), MC_SCHEME_PERSISTENT_BUCKETS, 256, 0, kPersistSteps, 0},
+      {sizeof(mc_launch), MC_SCHEME_PERSISTENT_BUCKETS, 512, 0, kPersistSteps, 0},
+      {sizeof(mc_launch), MC_SCHEME_PERSISTENT_BUCKETS, 128, 0, kPersistSteps, 0},
+      {sizeof(mc_launch), MC_SCHEME_STEP_KERNELS, 256, 256, spg, 0},
+      {sizeof(mc_launch), MC_SCHEME_STEP_KERNELS, 256, 256, spg, 1},
+      {sizeof(mc_launch), MC_SCHEME_STEP_KERNELS, 256, 1024, spg, 0},
+      {sizeof(mc_launch), MC_SCHEME_STEP_KERNELS, 512, 512, spg, 0},
+      {sizeof(mc_launch), MC_SCHEME_STEP_KERNELS, 512, 512, spg, 1},
+      {sizeof(mc_launch), MC_SCHEME_STEP_KERNELS, 128, 128, spg, 0},
+      {sizeof(mc_launch), MC_SCHEME_STEP_KERNELS, 128, 128, spg, 1},
   };
   double best_ms = 1e300;
   mc_launch chosen = original;
@@ -1251,6 +1644,7 @@ int mc_tune(mc_net* n, int64_t steps, mc_launch* best) {
   }
   if ((rc = apply_launch(n, chosen)) != MC_OK) return rc;
   if ((rc = mc_load_state(n, blob.data(), blob.size())) != MC_OK) return rc;
+  if (!key.empty() && best_ms < 1e300) tune_cache_write(cache, key, chosen, best_ms / (double)steps);
   if (best) *best = chosen;
   return MC_OK;
 }
@@ -1258,8 +1652,9 @@ int mc_tune(mc_net* n, int64_t steps, mc_launch* best) {
 int mc_get_persist_shape(mc_net* n, int32_t* G, int32_t* B, int32_t* DL) {
   if (!device_ready(n) || !G || !B || !DL) return set_error(MC_ERR_INVALID_ARG, "bad handle or NULL output");
   const bool on = n->launch.scheme == MC_SCHEME_PERSISTENT_LDS;
-  *G = on ? n->pG : 0;
-  *B = on ? n->pB : 0;
+  const bool bk = n->launch.scheme == MC_SCHEME_PERSISTENT_BUCKETS;
+  *G = on ? n->pG : bk ? n->own_blocks : 0;
+  *B = on ? n->pB : bk ? n->wg_neurons : 0;
   *DL = on ? n->pDL : 0;
   return MC_OK;
 }
@@ -1287,7 +1682,7 @@ int mc_adjoint(mc_net* n, const mc_adjoint_config* a, void* grad, double* loss) 
   int R = 1;
   while (R < Kc + 101) R <<= 1;
   int rc;
-  AdjBuffers B;
+  AdjBuffers B(n->alloc);
   double *ck_y = nullptr, *ck_I = nullptr;
   int32_t* ck_r = nullptr;
   long long* ck_ring = nullptr;

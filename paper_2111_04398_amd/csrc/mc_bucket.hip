@@ -1,0 +1,557 @@
+// mc_bucket.hip -- persistent multi-step kernel for many independent
+// instances (and any network too large for the LDS window of k_persist):
+// target-owner delivery into per-workgroup delay buckets.
+//
+// Every workgroup owns a block of at most B target neurons of one instance
+// (T consecutive targets per thread) and exchanges spike records only with
+// the workgroups of its own instance: instances never interact, so a batch
+// runs as independent groups inside one launch and a slow instance delays
+// only itself.
+//
+// Why buckets: at the batch's size (7.5e5 neurons) the LDS of a compute unit
+// holds only a few steps of pending input for its ~3000 targets, so most
+// events would be device-scope int64 atomics into the ring, and those are
+// performed at the memory side at ~2e10/s for the whole chip (~50 us per
+// step for the batch's ~1.1e6 events).  Instead, the events of a step are
+// appended to buckets of the owner workgroup, one bucket per arrival step
+// (step mod 128): an LDS counter gives the position, the entry (local
+// target, weight) is stored to global memory.  When the arrival step comes,
+// the owner reads its bucket back (one coalesced pass) and sums it in LDS
+// with LDS atomics.  The events' global traffic becomes a streaming write
+// and a streaming read of 8 bytes each.  The sums are integer sums, so the
+// order of the entries does not matter.  A bucket that is full sends further
+// events to the global ring with device atomics (the owner reads the ring
+// slot of that step too); at the end of a launch the buckets still pending
+// are summed into the ring, where the next launch (or another scheme)
+// finds them.
+//
+// Step order per iteration n (as k_persist: the spike decision of step m
+// needs I from before step m's input, so step n+1's decision and record go
+// out before the wait for step n's records):
+//   1. bucket of step n -> LDS sums; input of step n (+ ring, + drive) into I;
+//   2. spike decision of step n+1; compaction; record of step n+1;
+//   3. drive of step n+1; wait for the records of step n of the instance's
+//      workgroups, listing their spike ids;
+//   4. every event of step n's spikes that lands in this block goes into the
+//      bucket of its arrival step.
+// Spike records: four per workgroup (step mod 4).  Word 0 = tag16 << 48 |
+// count << 36 | the block-local indices (11 bits each) of the first three
+// spikes; words 1..3 = (step + 1) << 32 | id of spikes 4..6; later ids in a
+// side array written before word 0.  The last workgroup to finish a launch
+// clears every record, so a tag needs to carry only the step.
+#pragma clang fp contract(off)
+
+#include <algorithm>
+
+#include "mc_device.h"
+
+namespace mc {
+
+namespace {
+
+constexpr int kBW0Ids = 3;              // ids in word 0 (11-bit block-local indices)
+constexpr int kBInline = kBW0Ids + 3;   // ids carried by a record
+constexpr int kBListCap = 1024;         // spikes of one step listed in LDS (more: chunked, from the records)
+constexpr int kBBigCap = 64;            // producers with more than kBInline spikes listed per step
+constexpr int kBPollPerLane = kBucketMaxProducers / 64;
+constexpr int kBUnroll = 4;             // entries in flight per lane
+
+template <class T>
+__device__ __forceinline__ T bld(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ __forceinline__ void bst(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int bpoisson(const uint64_t* T, uint32_t u) {
+  int k = 0;
+  while ((uint64_t)u >= T[k]) ++k;
+  return k;
+}
+
+// Block-wide exclusive scan of one int per thread (s_tmp: one int per wave).
+__device__ __forceinline__ int bscan(int v, int* s_tmp, int* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) s_tmp[wave] = x;
+  __syncthreads();
+  int woff = 0, tot = 0;
+  for (int w = 0; w < nw; ++w) { const int t = s_tmp[w]; woff += (w < wave) ? t : 0; tot += t; }
+  *total = tot;
+  return woff + x - v;
+}
+
+}  // namespace
+
+// LDS (dynamic): s_x[B] i64 (input sums of the step being absorbed)
+template <int T>
+__global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs a, int steps) {
+  extern __shared__ __align__(16) unsigned char s_raw[];
+  __shared__ uint64_t s_table[kMaxPops * kTableLen];
+  __shared__ int s_bcnt[kRingSlots];           // entries in each bucket (arrival step mod 128)
+  __shared__ unsigned s_dirty[kRingSlots / 32];  // ring slots that received bucket overflow
+  __shared__ int s_tmp[2][16];
+  __shared__ int s_first[kBInline];             // ids of the step's first spikes (record)
+  __shared__ int s_cnt[kBucketMaxProducers];    // spike count of each producer of the instance this step
+  __shared__ int s_ids[kBListCap];
+  __shared__ int2 s_big[kBBigCap];
+  __shared__ int s_nids, s_nbig, s_abort, s_last;
+  __shared__ unsigned long long s_events;
+  __shared__ unsigned long long s_popcnt[kMaxPops];
+  long long* s_x = reinterpret_cast<long long*>(s_raw);
+
+  const int g = blockIdx.x, tid = threadIdx.x, nthr = blockDim.x;
+  const int lane = tid & 63, wave = tid >> 6, nw = nthr >> 6;
+  const int b = a.binst[g], lb = a.blb[g];
+  const int gi0 = a.ifb[b];                                        // the instance's first workgroup
+  const int Gi = ((b + 1 < p.n_inst) ? a.ifb[b + 1] : a.G) - gi0;   // its workgroups
+  const long long j0 = a.bt0[g];
+  const int Bg = a.bt0[g + 1] - a.bt0[g];
+  const long long n0 = *p.step_base;
+  unsigned long long* bk = a.bk + (size_t)g * kRingSlots * a.cap;
+
+  for (int k = tid; k < p.n_pops * kTableLen; k += nthr) s_table[k] = p.table[k];
+  for (int k = tid; k < a.B; k += nthr) s_x[k] = 0;
+  for (int k = tid; k < kRingSlots; k += nthr) s_bcnt[k] = 0;
+  if (tid < kRingSlots / 32) s_dirty[tid] = 0;
+  for (int k = tid; k < kBucketMaxProducers; k += nthr) s_cnt[k] = 0;
+  if (tid == 0) { s_abort = 0; s_events = 0; }
+  if (tid < kMaxPops) s_popcnt[tid] = 0;
+  __syncthreads();
+
+  // thread t owns targets j0 + t*T .. j0 + t*T + T-1 (those < Bg)
+  // population (0xFF: none) and Poisson count of target k in byte k & 3 of word k >> 2
+  constexpr int TW = (T + 3) / 4;
+  const int jt = tid * T;
+  double y[T], I[T];
+  int r[T];
+  unsigned popw[TW], kdw[TW];
+#pragma unroll
+  for (int w = 0; w < TW; ++w) { popw[w] = 0xFFFFFFFFu; kdw[w] = 0; }
+  auto pop_of = [&](int k) -> unsigned { return (popw[k >> 2] >> (8 * (k & 3))) & 0xFFu; };
+#pragma unroll
+  for (int k = 0; k < T; ++k) {
+    y[k] = 0.0; I[k] = 0.0; r[k] = 0;
+    if (jt + k < Bg) {
+      const long long j = j0 + jt + k;
+      const unsigned pk = (p.qpops[j >> 2] >> (8 * (j & 3))) & 0xFFu;
+      popw[k >> 2] = (popw[k >> 2] & ~(0xFFu << (8 * (k & 3)))) | (pk << (8 * (k & 3)));
+      y[k] = p.y[j]; I[k] = p.I[j]; r[k] = p.r[j];
+    }
+  }
+  // Poisson counts of my targets at step m (one Philox block per quad)
+  auto drive = [&](long long m) {
+    U64x4 v{0, 0, 0, 0};
+#pragma unroll
+    for (int w = 0; w < TW; ++w) kdw[w] = 0;
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+      if (jt + k >= Bg) continue;
+      const long long j = j0 + jt + k;
+      if (k == 0 || (j & 3) == 0) {              // one block per quad, shared by the quad's targets
+        const long long q = j >> 2;
+        v = philox4x64_10((uint64_t)m, (uint64_t)p.qlocal[q], 0, kTagDrive, p.qseed[q], 0);
+      }
+      const unsigned pk = pop_of(k);
+      if (pk != 0xFFu)
+        kdw[k >> 2] |= (unsigned)bpoisson(s_table + pk * kTableLen, hi32(pick(v, (unsigned)(j & 3)))) << (8 * (k & 3));
+    }
+  };
+  long long rcnt = p.raster_cnt[g];
+  long long ck_seg = -1, ck_phase = 1;
+  if (p.ck_y) {
+    const long long k = n0 - p.ck_step0;
+    ck_seg = (k >= 0) ? k / p.ck_every : -1;
+    ck_phase = (k >= 0) ? k % p.ck_every : 1;
+  }
+  if (steps > 0) drive(n0);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+
+  auto decide = [&](long long m) -> unsigned {   // spike decision of step m: bit k = target k spiked
+    if (p.ck_y) {
+      if (ck_phase == 0 && ck_seg >= 0 && ck_seg < p.ck_count) {
+#pragma unroll
+        for (int k = 0; k < T; ++k)
+          if (jt + k < Bg) {
+            const size_t at = (size_t)ck_seg * p.ring_stride + j0 + jt + k;
+            p.ck_y[at] = y[k]; p.ck_I[at] = I[k]; p.ck_r[at] = r[k];
+          }
+      }
+      if (++ck_phase == p.ck_every) { ck_phase = 0; ++ck_seg; }
+    }
+    unsigned mask = 0;
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+      const unsigned pk = pop_of(k);
+      if (pk == 0xFFu) continue;
+      const bool free_ = (r[k] == 0);
+      if (free_) {
+        double yn = p.P22 * y[k] + p.P21 * I[k];
+        if (p.i_e != 0.0) yn = yn + p.P20 * p.i_e;
+        y[k] = yn;
+      } else {
+        r[k] = r[k] - 1;
+      }
+      if (free_ && y[k] >= p.theta) {
+        y[k] = p.y_reset;
+        r[k] = p.ref_steps;
+        mask |= 1u << k;
+        atomicAdd(&s_popcnt[pk], 1ull);
+      }
+    }
+    return mask;
+  };
+  auto publish = [&](long long m, unsigned mask) {   // compaction (ascending ids), record of step m, raster
+    int nloc;
+    const int c = __popc(mask);
+    const int pre = bscan(c, s_tmp[0], &nloc);
+    const unsigned long long tag = (unsigned long long)(m + 1) << 32;
+    const unsigned long long tag16 = (unsigned long long)((m + 1) % 65535 + 1) << 48;
+    const size_t rec = (size_t)g * kRecSlots + (size_t)(m % kRecSlots);
+    unsigned long long* myrec = a.flags + rec * kPersistFlagStride;
+    const bool fits = rcnt + nloc <= p.raster_cap;
+    int pos = pre;
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+      if (!((mask >> k) & 1u)) continue;
+      const int id = (int)(j0 + jt + k);
+      if (pos < kBInline) s_first[pos] = id;
+      else bst(&a.pub[rec * a.B + pos], id);
+      if (fits) p.raster[(size_t)g * p.raster_cap + rcnt + pos] = make_int2((int)m, id);
+      ++pos;
+    }
+    if (nloc > kBInline) __builtin_amdgcn_s_waitcnt(0);   // side-array ids complete before word 0
+    __syncthreads();
+    if (tid >= kBW0Ids && tid < min(nloc, kBInline)) bst(&myrec[1 + tid - kBW0Ids], tag | (unsigned)s_first[tid]);
+    if (tid == 0) {
+      unsigned long long w = tag16 | (unsigned long long)min(nloc, 4095) << 36;
+      for (int k = 0; k < min(nloc, kBW0Ids); ++k) w |= (unsigned long long)(s_first[k] - j0) << (11 * k);
+      bst(&myrec[0], w);
+    }
+    if (fits) rcnt += nloc;
+    else if (tid == 0) atomicOr(p.overflow, 1u);
+  };
+  // id k of producer h's record of step n (after its record has been accepted)
+  auto rec_id = [&](int h, size_t rslot, int k) -> int {
+    const unsigned long long* rec = a.flags + ((size_t)h * kRecSlots + rslot) * kPersistFlagStride;
+    if (k < kBW0Ids) return a.bt0[h] + (int)((bld(&rec[0]) >> (11 * k)) & 0x7FFu);
+    if (k < kBInline) return (int)(bld(&rec[1 + k - kBW0Ids]) & 0xFFFFFFFFu);
+    return bld(&a.pub[((size_t)h * kRecSlots + rslot) * a.B + k]);
+  };
+  // one wavefront appends the events of spikes ids[k0..k1) of step ns that
+  // land in this block to the buckets of their arrival steps
+  auto deliver = [&](const int* ids, int k0, int k1, long long ns, unsigned long long* ev_out) {
+    unsigned long long ev = 0;
+    for (int base = k0; base < k1; base += 64) {
+      long long lo = 0;
+      int len = 0;
+      if (base + lane < k1) {
+        const int i = ids[base + lane];
+        const int64_t o = a.boff[i] + lb;
+        lo = p.row_ptr[i] + a.blk2[o];
+        len = a.blk2[o + 1] - a.blk2[o];
+        ev += (unsigned long long)len;
+      }
+      int x = len;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int yv = __shfl_up(x, o, 64);
+        if (lane >= o) x += yv;
+      }
+      const int total = __shfl(x, 63, 64);
+      const int excl = x - len;
+      for (int f0 = 0; f0 < total; f0 += 64 * kBUnroll) {
+        int tt[kBUnroll], ww[kBUnroll], dd[kBUnroll];
+#pragma unroll
+        for (int u = 0; u < kBUnroll; ++u) {
+          const int f = f0 + u * 64 + lane;
+          dd[u] = 0;
+          int lo_l = 0, hi_l = 64;
+#pragma unroll
+          for (int st = 0; st < 6; ++st) {
+            const int mid = (lo_l + hi_l) >> 1;
+            if (__shfl(excl, mid, 64) <= f) lo_l = mid; else hi_l = mid;
+          }
+          const long long lo_j = __shfl(lo, lo_l, 64);
+          const int ex_j = __shfl(excl, lo_l, 64);
+          if (f < total) {
+            const long long e = lo_j + (f - ex_j);
+            tt[u] = p.tgt[e];
+            ww[u] = p.wq[e];
+            dd[u] = p.dly[e];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kBUnroll; ++u) {
+          if (dd[u] == 0) continue;
+          const int slot = (int)((ns + dd[u]) & kRingMask);
+          const int at = atomicAdd(&s_bcnt[slot], 1);
+          if (at < a.cap) {
+            bst(&bk[(size_t)slot * a.cap + at],
+                (unsigned long long)(unsigned)(tt[u] - j0) << 32 | (unsigned)ww[u]);
+          } else {   // full bucket: the ring slot, read by the owner at that step
+            atomicAdd(reinterpret_cast<unsigned long long*>(p.ring + (size_t)slot * p.ring_stride + tt[u]),
+                      (unsigned long long)(long long)ww[u]);
+            atomicOr(&s_dirty[slot >> 5], 1u << (slot & 31));
+          }
+        }
+      }
+    }
+    *ev_out += ev;
+  };
+
+  unsigned mask = 0;
+  if (steps > 0) {
+    mask = decide(n0);
+    publish(n0, mask);
+  }
+  for (int it = 0; it < steps; ++it) {
+    const long long n = n0 + it;
+    const int slot = (int)(n & kRingMask);
+    const size_t rslot = (size_t)(n % kRecSlots);
+    // ---- 1. input of step n: its bucket summed in LDS, then into I --------
+    {
+      const int cnt = min(s_bcnt[slot], a.cap);
+      const unsigned long long* bq = bk + (size_t)slot * a.cap;
+      for (int e = tid; e < cnt; e += nthr) {
+        const unsigned long long v = bld(&bq[e]);
+        atomicAdd(reinterpret_cast<unsigned long long*>(&s_x[v >> 32]), (unsigned long long)(long long)(int)(v & 0xFFFFFFFFu));
+      }
+    }
+    const bool read_ring = (it < a.horizon) || ((s_dirty[slot >> 5] >> (slot & 31)) & 1u);
+    __syncthreads();
+    if (tid == 0) {
+      s_bcnt[slot] = 0;
+      s_dirty[slot >> 5] &= ~(1u << (slot & 31));
+      s_nids = 0;
+      s_nbig = 0;
+    }
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+      const int jl = jt + k;
+      if (jl >= Bg) continue;
+      long long x_int = s_x[jl];
+      s_x[jl] = 0;
+      if (read_ring) {
+        long long* e = p.ring + (size_t)slot * p.ring_stride + j0 + jl;
+        const long long v = bld(e);
+        if (v != 0) { bst(e, 0ll); x_int += v; }
+      }
+      const unsigned pk = pop_of(k);
+      if (pk != 0xFFu) x_int += (long long)((kdw[k >> 2] >> (8 * (k & 3))) & 0xFFu) * p.jext_q;
+      if (p.xrec && n - p.xrec_step0 >= 0 && n - p.xrec_step0 < p.xrec_steps)
+        p.xrec[(size_t)(n - p.xrec_step0) * p.ring_stride + j0 + jl] = x_int;
+      if (pk != 0xFFu) I[k] = p.P11 * I[k] + (double)x_int * 0x1p-16;
+    }
+    // ---- 2. spike decision and record of step n+1 ---------------------------
+    mask = 0;
+    if (it + 1 < steps) {
+      mask = decide(n + 1);
+      publish(n + 1, mask);
+    } else {
+      __syncthreads();
+    }
+    // ---- 3. drive of step n+1; wait for the instance's records of step n ---
+    //      (the polling wavefront draws its drive after the poll)
+    if (wave != nw - 1 && it + 1 < steps) drive(n + 1);
+    const unsigned long long tag = (unsigned long long)(n + 1) << 32;
+    const unsigned long long tag16 = (unsigned long long)((n + 1) % 65535 + 1) << 48;
+    if (wave == nw - 1) {
+      const long long t_poll = wall_clock64();
+      unsigned todo = 0;
+#pragma unroll
+      for (int rr = 0; rr < kBPollPerLane; ++rr)
+        if (lane + 64 * rr < Gi) todo |= 1u << rr;
+      while (todo) {
+        unsigned long long w0[kBPollPerLane];
+#pragma unroll
+        for (int rr = 0; rr < kBPollPerLane; ++rr)
+          w0[rr] = ((todo >> rr) & 1u)
+                       ? bld(&a.flags[((size_t)(gi0 + lane + 64 * rr) * kRecSlots + rslot) * kPersistFlagStride])
+                       : 0ull;
+#pragma unroll
+        for (int rr = 0; rr < kBPollPerLane; ++rr) {
+          if (!((todo >> rr) & 1u) || (w0[rr] & 0xFFFF000000000000ull) != tag16) continue;
+          const int hl = lane + 64 * rr, h = gi0 + hl;
+          const int c = (int)((w0[rr] >> 36) & 0xFFFu);
+          unsigned long long wk[kBInline - kBW0Ids];
+          bool ok = true;
+          if (c > kBW0Ids) {
+            const unsigned long long* rec = a.flags + ((size_t)h * kRecSlots + rslot) * kPersistFlagStride;
+#pragma unroll
+            for (int k = 0; k < kBInline - kBW0Ids; ++k) wk[k] = bld(&rec[1 + k]);
+#pragma unroll
+            for (int k = 0; k < kBInline - kBW0Ids; ++k)
+              if (kBW0Ids + k < c) ok &= ((wk[k] & 0xFFFFFFFF00000000ull) == tag);
+          }
+          if (!ok) continue;
+          s_cnt[hl] = c;
+          if (c > 0) {
+            const int o = atomicAdd(&s_nids, c);
+            const int hb = a.bt0[h];
+            for (int k = 0; k < min(c, kBInline); ++k) {
+              if (o + k >= kBListCap) break;
+              s_ids[o + k] = (k < kBW0Ids) ? hb + (int)((w0[rr] >> (11 * k)) & 0x7FFu)
+                                           : (int)(wk[k - kBW0Ids] & 0xFFFFFFFFu);
+            }
+            if (c > kBInline) {
+              const int bg = atomicAdd(&s_nbig, 1);
+              if (bg < kBBigCap) s_big[bg] = make_int2(h, o);
+            }
+          }
+          todo &= ~(1u << rr);
+        }
+        if (!todo) break;
+        __builtin_amdgcn_s_sleep(1);
+        if (wall_clock64() - t_poll > a.wait_ticks) {
+          atomicOr(p.overflow, 2u);
+          s_abort = 1;
+#pragma unroll
+          for (int rr = 0; rr < kBPollPerLane; ++rr)
+            if ((todo >> rr) & 1u) s_cnt[lane + 64 * rr] = 0;
+          break;
+        }
+      }
+      if (it + 1 < steps) drive(n + 1);
+    }
+    __syncthreads();
+    if (s_abort) break;
+    // ---- 4. events of step n's spikes into the buckets ----------------------
+    const int S = s_nids;
+    unsigned long long ev = 0;
+    if (S <= kBListCap && s_nbig <= kBBigCap) {
+      const int nbig = s_nbig;
+      if (nbig > 0) {
+        for (int e = 0; e < nbig; ++e) {
+          const int h = s_big[e].x, o = s_big[e].y, c = s_cnt[h - gi0];
+          for (int k = kBInline + tid; k < c; k += nthr) s_ids[o + k] = bld(&a.pub[((size_t)h * kRecSlots + rslot) * a.B + k]);
+        }
+        __syncthreads();
+      }
+      const int k0 = (int)((long long)S * wave / nw), k1 = (int)((long long)S * (wave + 1) / nw);
+      deliver(s_ids, k0, k1, n, &ev);
+    } else {
+      // more spikes than the list holds: in producer order, chunk by chunk,
+      // the ids read again from the records (thread t sums producers 2t, 2t+1)
+      const int c0 = (2 * tid < Gi) ? s_cnt[2 * tid] : 0;
+      const int c1 = (2 * tid + 1 < Gi) ? s_cnt[2 * tid + 1] : 0;
+      int Sall;
+      const int pre_h = bscan(c0 + c1, s_tmp[1], &Sall);
+      __syncthreads();
+      int* s_pre = reinterpret_cast<int*>(s_x);      // the sums are all zero here: borrow their LDS
+      if (2 * tid < Gi) s_pre[2 * tid] = pre_h;
+      if (2 * tid + 1 < Gi) s_pre[2 * tid + 1] = pre_h + c0;
+      if (tid == 0) s_pre[Gi] = Sall;
+      __syncthreads();
+      for (int base = 0; base < Sall; base += kBListCap) {
+        const int cnt = min(kBListCap, Sall - base);
+        for (int k = tid; k < cnt; k += nthr) {
+          const int gk = base + k;
+          int lo = 0, hi = Gi;
+          while (hi - lo > 1) { const int mid = (lo + hi) >> 1; if (s_pre[mid] <= gk) lo = mid; else hi = mid; }
+          s_ids[k] = rec_id(gi0 + lo, rslot, gk - s_pre[lo]);
+        }
+        __syncthreads();
+        const int k0 = (int)((long long)cnt * wave / nw), k1 = (int)((long long)cnt * (wave + 1) / nw);
+        deliver(s_ids, k0, k1, n, &ev);
+        __syncthreads();
+      }
+      for (int k = tid; k <= Gi; k += nthr) s_pre[k] = 0;
+    }
+    if (ev) atomicAdd(&s_events, ev);
+    __syncthreads();
+  }
+  // ---- epilogue: state, counters; pending buckets summed into the ring -----
+#pragma unroll
+  for (int k = 0; k < T; ++k)
+    if (jt + k < Bg) { const long long j = j0 + jt + k; p.y[j] = y[k]; p.I[j] = I[k]; p.r[j] = r[k]; }
+  if (tid < p.n_pops) p.wg_spikes[(size_t)g * p.n_pops + tid] += s_popcnt[tid];
+  if (tid == 0) {
+    p.raster_cnt[g] = rcnt;
+    p.wg_events[g] += s_events;
+  }
+  for (int sl = 0; sl < kRingSlots; ++sl) {
+    const int cnt = min(s_bcnt[sl], a.cap);
+    if (cnt == 0) continue;                      // uniform: every thread reads the same count
+    const unsigned long long* bq = bk + (size_t)sl * a.cap;
+    for (int e = tid; e < cnt; e += nthr) {
+      const unsigned long long v = bld(&bq[e]);
+      atomicAdd(reinterpret_cast<unsigned long long*>(&s_x[v >> 32]), (unsigned long long)(long long)(int)(v & 0xFFFFFFFFu));
+    }
+    __syncthreads();
+    for (int jl = tid; jl < Bg; jl += nthr) {
+      const long long v = s_x[jl];
+      if (v == 0) continue;
+      s_x[jl] = 0;
+      long long* e = p.ring + (size_t)sl * p.ring_stride + j0 + jl;
+      bst(e, bld(e) + v);                        // only this workgroup touches its targets' entries
+    }
+    __syncthreads();
+  }
+  // the last workgroup to finish clears the records and advances the step
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (tid == 0) {
+    unsigned long long* done = a.flags + persist_record_words(a.G);
+    s_last = (__hip_atomic_fetch_add(done, 1ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == (unsigned long long)(a.G - 1));
+  }
+  __syncthreads();
+  if (s_last) {
+    const int words = (int)persist_record_words(a.G);
+    for (int k = tid; k < words; k += nthr) bst(&a.flags[k], 0ull);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (tid == 0) {
+      bst(p.step_base, n0 + (long long)steps);
+      __hip_atomic_store(a.flags + persist_record_words(a.G), 0ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+// Dynamic LDS: the step's input sums (B int64), which the fallback listing
+// also borrows for its producer prefix ((kBucketMaxProducers + 1) ints).
+size_t bucket_lds_bytes(int B) {
+  return std::max((size_t)B * sizeof(long long), (size_t)(kBucketMaxProducers + 1) * sizeof(int));
+}
+
+template <int T>
+static hipError_t launch_bucket_t(const DevNet& p, const BucketArgs& a, int steps, int block, hipStream_t s) {
+  hipLaunchKernelGGL(k_bucket<T>, dim3(a.G), dim3(block), bucket_lds_bytes(a.B), s, p, a, steps);
+  return hipGetLastError();
+}
+
+int bucket_targets_per_thread(int B, int block) {
+  const int t = (B + block - 1) / block;
+  return t <= 1 ? 1 : t <= 2 ? 2 : t <= 4 ? 4 : t <= 6 ? 6 : 0;
+}
+
+hipError_t launch_bucket(const DevNet& p, const BucketArgs& a, int steps, int block, hipStream_t s) {
+  switch (bucket_targets_per_thread(a.B, block)) {
+    case 1: return launch_bucket_t<1>(p, a, steps, block, s);
+    case 2: return launch_bucket_t<2>(p, a, steps, block, s);
+    case 4: return launch_bucket_t<4>(p, a, steps, block, s);
+    case 6: return launch_bucket_t<6>(p, a, steps, block, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t bucket_occupancy(int B, int block, int* blocks_per_cu) {
+  const size_t lds = bucket_lds_bytes(B);
+  switch (bucket_targets_per_thread(B, block)) {
+    case 1: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_bucket<1>, block, lds);
+    case 2: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_bucket<2>, block, lds);
+    case 4: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_bucket<4>, block, lds);
+    case 6: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_bucket<6>, block, lds);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace mc

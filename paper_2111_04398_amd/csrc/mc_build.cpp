@@ -305,16 +305,29 @@ int build_host(const mc_config& c, HostNet& net, std::string& err, ConnBuilder* 
       for (int64_t j = 0; j < in.N; ++j) first[j + 1] = first[j] + kin[in.pop[j]];
       const int64_t Mb = first[in.N];
       std::vector<int32_t> src((size_t)Mb);
+      if (conn) {
+        FixedPlan plan;
+        plan.N = in.N;
+        plan.n_pops = n;
+        plan.off = in.off.data();
+        plan.pop = in.pop.data();
+        plan.K = K.data();
+        plan.first = first.data();
+        plan.seed = in.seed;
+        const int rc = conn->sources(plan, src.data(), err);
+        if (rc != MC_OK) return rc;
+      } else {
 #pragma omp parallel for schedule(dynamic, 64)
-      for (int64_t j = 0; j < in.N; ++j) {
-        const int a = in.pop[j];
-        int64_t m = 0;
-        for (int bb = 0; bb < n; ++bb) {
-          const uint64_t Nb = (uint64_t)(in.off[bb + 1] - in.off[bb]);
-          for (int64_t q = 0; q < K[a * n + bb]; ++q, ++m) {
-            const U64x4 v = philox4x64_10((uint64_t)j, (uint64_t)(m >> 2), 0, kTagSrc, in.seed, 0);
-            const uint64_t u = hi32(pick(v, (unsigned)(m & 3)));
-            src[first[j] + m] = (int32_t)(in.off[bb] + (int64_t)((u * Nb) >> 32));
+        for (int64_t j = 0; j < in.N; ++j) {
+          const int a = in.pop[j];
+          int64_t m = 0;
+          for (int bb = 0; bb < n; ++bb) {
+            const uint64_t Nb = (uint64_t)(in.off[bb + 1] - in.off[bb]);
+            for (int64_t q = 0; q < K[a * n + bb]; ++q, ++m) {
+              const U64x4 v = philox4x64_10((uint64_t)j, (uint64_t)(m >> 2), 0, kTagSrc, in.seed, 0);
+              const uint64_t u = hi32(pick(v, (unsigned)(m & 3)));
+              src[first[j] + m] = (int32_t)(in.off[bb] + (int64_t)((u * Nb) >> 32));
+            }
           }
         }
       }
@@ -351,6 +364,10 @@ int build_host(const mc_config& c, HostNet& net, std::string& err, ConnBuilder* 
   for (int64_t i = 0; i < net.N; ++i) mx = std::max(mx, net.row_ptr[i + 1] - net.row_ptr[i]);
   if (mx > (int64_t)1 << 30) return fail(err, MC_ERR_RANGE, "row longer than 2^30 synapses");
   net.max_row = (int)mx;
+  int dm = 0;
+#pragma omp parallel for reduction(max : dm)
+  for (int64_t e = 0; e < net.M; ++e) dm = std::max(dm, (int)net.dly[e]);
+  net.max_delay = dm;
   return MC_OK;
 }
 

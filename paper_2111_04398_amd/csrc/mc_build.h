@@ -25,6 +25,7 @@ struct HostNet {
   std::vector<int32_t> wq;               // [M], 2^-16 pA
   std::vector<uint8_t> dly;              // [M], steps
   int max_row = 0;
+  int max_delay = 0;                     // largest delay in the store (steps)
   // dynamics constants
   double P11 = 0, P21 = 0, P22 = 0, P20 = 0;
   double i_e = 0, theta = 0, y_reset = 0, e_l = 0;   // theta, y_reset relative to E_L
@@ -48,14 +49,32 @@ struct BernoulliPlan {
   int64_t goff = 0;            // global id of the instance's first neuron
 };
 
-// Draws the connections of a Bernoulli instance elsewhere (the HIP device):
-// count() gives every source's number of targets, fill() every source's
-// targets (global ids, ascending) at row_ptr_local[i] - row_ptr_local[0] of
-// tgt.  Both must equal the host's draws bit for bit.
+// One instance of the fixed in-degree rule: target j draws, for each
+// presynaptic population b in order, K[pop(j) * n_pops + b] sources of b
+// uniformly with replacement; its draw m (m counts all its draws) is
+// off[b] + ((u * N_b) >> 32) with u the upper 32 bits of word m&3 of the
+// Philox block keyed (j, m>>2, 0, SRC).
+struct FixedPlan {
+  int64_t N = 0;
+  int n_pops = 0;
+  const int64_t* off = nullptr;    // [n_pops+1] local population offsets
+  const uint8_t* pop = nullptr;    // [N]
+  const int64_t* K = nullptr;      // [n_pops*n_pops] draws, [post][pre]
+  const int64_t* first = nullptr;  // [N+1] offset of target j's draws
+  uint64_t seed = 0;
+};
+
+// Draws the connections of an instance elsewhere (the HIP device).  For the
+// Bernoulli rule count() gives every source's number of targets, fill() every
+// source's targets (global ids, ascending) at row_ptr_local[i] -
+// row_ptr_local[0] of tgt; for the fixed in-degree rule sources() gives
+// every draw's local source at first[j] + m.  All must equal the host's
+// draws bit for bit.
 struct ConnBuilder {
   virtual ~ConnBuilder() = default;
   virtual int count(const BernoulliPlan& plan, int64_t* counts, std::string& err) = 0;
   virtual int fill(const BernoulliPlan& plan, const int64_t* row_ptr_local, int32_t* tgt, std::string& err) = 0;
+  virtual int sources(const FixedPlan& plan, int32_t* src, std::string& err) = 0;
 };
 
 // Validates the configuration and builds the whole network.  With `conn`,

@@ -1,5 +1,5 @@
-// mc_construct.hip -- connections of the pairwise Bernoulli rule drawn on the
-// device.
+// mc_construct.hip -- connections of the pairwise Bernoulli rule and sources
+// of the fixed in-degree rule drawn on the device.
 //
 // Instantiation is untimed (Methods), and for the microcircuit most of it is
 // the pair test: every (source, target) pair of an instance is tested against
@@ -13,6 +13,12 @@
 // One wavefront per source row: lanes take consecutive quads of targets (one
 // Philox block each), so the row's targets come out in ascending order; a
 // count pass sizes the rows, a fill pass writes them.
+//
+// The fixed in-degree rule draws every target's sources with replacement:
+// draw m of target j takes the multiply-shift bounded integer (u * N_b) >> 32
+// of the upper 32 bits u of word m&3 of the block keyed (j, m>>2, 0, SRC).
+// Only these integer draws move to the device; the host sorts them by
+// source into rows and draws weights and delays.
 #include "mc_build.h"
 #include "mc_device.h"
 
@@ -95,6 +101,42 @@ __global__ __launch_bounds__(kConnBlock) void k_bern_fill(BernArgs a, const long
   }
 }
 
+// Fixed in-degree sources: one wavefront per target j, lanes on consecutive
+// Philox blocks (four draws each); draw m of target j comes from the
+// population whose cumulative count K[pop(j)][0..b] first exceeds m.
+struct FixedArgs {
+  long long N;
+  int n;
+  uint64_t seed;
+  const long long* off;             // [n+1]
+  const uint8_t* pop;               // [N]
+  const long long* K;               // [n*n], [post][pre]
+  const long long* first;           // [N+1]
+};
+
+__global__ __launch_bounds__(kConnBlock) void k_fixed_sources(FixedArgs a, int32_t* src) {
+  const int lane = threadIdx.x & 63;
+  const long long wave = (blockIdx.x * (long long)blockDim.x + threadIdx.x) >> 6;
+  const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
+  for (long long j = wave; j < a.N; j += nwaves) {
+    const int post = a.pop[j];
+    const long long kin = a.first[j + 1] - a.first[j];
+    for (long long q = lane; 4 * q < kin; q += 64) {
+      const U64x4 v = philox4x64_10((uint64_t)j, (uint64_t)q, 0, kTagSrc, a.seed, 0);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const long long m = 4 * q + k;
+        if (m >= kin) break;
+        int b = 0;
+        long long cum = a.K[post * a.n];
+        while (m >= cum) { ++b; cum += a.K[post * a.n + b]; }
+        const uint64_t Nb = (uint64_t)(a.off[b + 1] - a.off[b]);
+        src[a.first[j] + m] = (int32_t)(a.off[b] + (long long)(((uint64_t)hi32(pick(v, (unsigned)k)) * Nb) >> 32));
+      }
+    }
+  }
+}
+
 template <class T>
 hipError_t dalloc(T** p, size_t n) { return hipMalloc((void**)p, (n ? n : 1) * sizeof(T)); }
 
@@ -154,6 +196,32 @@ class DeviceConn : public ConnBuilder {
     if (e == hipSuccess) e = hipStreamSynchronize(s_);
     (void)hipFree(drp);
     (void)hipFree(dt);
+    return check(e, err);
+  }
+
+  int sources(const FixedPlan& f, int32_t* src, std::string& err) override {
+    const long long Mb = f.first[f.N];
+    long long *off = nullptr, *K = nullptr, *first = nullptr;
+    uint8_t* pop = nullptr;
+    int32_t* ds = nullptr;
+    hipError_t e = dalloc(&off, (size_t)f.n_pops + 1);
+    if (e == hipSuccess) e = dalloc(&K, (size_t)f.n_pops * f.n_pops);
+    if (e == hipSuccess) e = dalloc(&first, (size_t)f.N + 1);
+    if (e == hipSuccess) e = dalloc(&pop, (size_t)f.N);
+    if (e == hipSuccess) e = dalloc(&ds, (size_t)Mb);
+    if (e == hipSuccess) e = hipMemcpyAsync(off, f.off, sizeof(long long) * (f.n_pops + 1), hipMemcpyHostToDevice, s_);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(K, f.K, sizeof(long long) * f.n_pops * f.n_pops, hipMemcpyHostToDevice, s_);
+    if (e == hipSuccess) e = hipMemcpyAsync(first, f.first, sizeof(long long) * (f.N + 1), hipMemcpyHostToDevice, s_);
+    if (e == hipSuccess) e = hipMemcpyAsync(pop, f.pop, (size_t)f.N, hipMemcpyHostToDevice, s_);
+    if (e == hipSuccess) {
+      const FixedArgs a{(long long)f.N, f.n_pops, f.seed, off, pop, K, first};
+      hipLaunchKernelGGL(k_fixed_sources, dim3(grid_), dim3(kConnBlock), 0, s_, a, ds);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess && Mb > 0) e = hipMemcpyAsync(src, ds, sizeof(int32_t) * Mb, hipMemcpyDeviceToHost, s_);
+    if (e == hipSuccess) e = hipStreamSynchronize(s_);
+    (void)hipFree(off); (void)hipFree(K); (void)hipFree(first); (void)hipFree(pop); (void)hipFree(ds);
     return check(e, err);
   }
 

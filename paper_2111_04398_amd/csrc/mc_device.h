@@ -77,11 +77,13 @@ struct PersistArgs {
   int B;                       // most target neurons of one workgroup (multiple of 4, <= kPersistMaxB)
   const int* bstart;           // [G+1] workgroup g owns padded targets [bstart[g], bstart[g+1]) (multiples of 4)
   int DL;                      // near slots held in LDS (2..101)
+  int horizon;                 // ring slots ahead of the first step that may hold input at launch (<= 127)
   int BW;                      // 32-bit words per far-bitmap row: ceil(B/32)
   const long long* blk;        // [n_pad][G+1] first synapse of each row with target >= bstart[g]
-  unsigned long long* flags;   // [G][kRecSlots][8] spike records by step mod kRecSlots
+  unsigned long long* flags;   // [G][kRecSlots][8] spike records by step mod kRecSlots, then the
+                               // launch's finish counter (one word, zero between launches)
   int* pub;                    // [G][kRecSlots][B] published spike ids beyond the seventh
-  long long spin_limit;        // polls before giving up
+  long long wait_ticks;        // longest wait for one step's records, in wall_clock64 ticks (then: error bit 2)
   unsigned long long* phase;   // optional [G*8]: summed wall_clock64 ticks per phase (nullptr: off)
   // near table: the delay-1/2 synapses of row i into workgroup g's block are
   // ne[nb[i][p] .. nb[i][p+1]) with p the position of g when the workgroups
@@ -92,7 +94,8 @@ struct PersistArgs {
 };
 constexpr int kPersistFlagStride = 8;
 constexpr int kRecSlots = 4;            // spike records (and side arrays) per workgroup, by step mod 4
-inline size_t persist_flag_words(int G) { return (size_t)G * kRecSlots * kPersistFlagStride; }
+__host__ __device__ inline size_t persist_record_words(int G) { return (size_t)G * kRecSlots * kPersistFlagStride; }
+__host__ __device__ inline size_t persist_flag_words(int G) { return persist_record_words(G) + kPersistFlagStride; }
 constexpr int kPersistMaxB = 512;       // owned targets per workgroup (one per thread)
 constexpr int kPersistMaxBlock = 512;   // threads per workgroup: 256 VGPRs per lane, no scratch spills
 size_t persist_lds_bytes(int G, int B, int DL);
@@ -114,6 +117,15 @@ hipError_t launch_replay(const int2* spikes, const long long* first_item, int n_
                          const int64_t* row_ptr, const int32_t* tgt, const int32_t* wq, const uint8_t* dly,
                          long long* ring, long long stride, long long step0, int grid, hipStream_t s);
 hipError_t launch_atomic_rate(unsigned long long* table, long long n, long long per_thread, int grid, hipStream_t s);
+hipError_t launch_stream_read(const void* src, long long bytes, unsigned long long* sink, int grid, hipStream_t s);
+hipError_t launch_atomic_slots(unsigned long long* table, long long slots, long long stride, long long n_targets,
+                               long long n_items, int pattern, int gap, const unsigned* dcdf, int grid,
+                               hipStream_t s);
+// Empty persistent loop of G co-resident workgroups exchanging one spike
+// record per step (no neurons, no delivery): the exchange's latency floor.
+// flags: persist_flag_words(G) words, zero on entry and on exit.
+hipError_t launch_exchange_probe(unsigned long long* flags, int G, int block, long long steps, long long wait_ticks,
+                                 unsigned* err, hipStream_t s);
 
 // One segment of the adjoint's reverse pass (see mc_adjoint.hip).
 struct AdjSeg {
@@ -145,6 +157,35 @@ hipError_t launch_adj_gather(const int4* srcs, const long long* first, int nsrc,
                              const int64_t* row_ptr, const int32_t* tgt, const uint8_t* dly, const double* li_ring,
                              long long stride, int R, long long last_m, void* grad, bool fp32, int grid, hipStream_t s);
 
+// Persistent kernel with target-owner delivery into per-workgroup delay
+// buckets (mc_bucket.hip).  Workgroup g owns padded targets [bt0[g],
+// bt0[g+1]) of instance binst[g] (its blb[g]-th block; the instance's blocks
+// are ifb[b] .. ifb[b+1]-1, the last instance's end at G); sub-rows as in
+// OwnerArgs (boff, blk2).
+struct BucketArgs {
+  int G;                       // workgroups (all co-resident)
+  int B;                       // most targets of one workgroup (multiple of 4, <= kBucketMaxB, <= 6 * block)
+  const int* bt0;              // [G+1]
+  const int* binst;            // [G]
+  const int* blb;              // [G]
+  const int* ifb;              // [n_inst]
+  const int64_t* boff;         // [n_pad+1]
+  const int32_t* blk2;
+  unsigned long long* flags;   // persist_flag_words(G): spike records [G][kRecSlots][8], then the finish counter
+  int* pub;                    // [G][kRecSlots][B] published ids beyond the record's
+  unsigned long long* bk;      // [G][128][cap] bucket entries (local target << 32 | weight)
+  int cap;                     // entries per bucket (more: device atomics into the ring)
+  long long wait_ticks;        // longest wait for one step's records (wall_clock64 ticks)
+  int horizon;                 // ring slots ahead of the first step that may hold input at launch
+};
+constexpr int kBucketMaxProducers = 512;   // workgroups of one instance
+constexpr int kBucketMaxBlock = 512;       // threads per workgroup
+constexpr int kBucketMaxB = 2048;          // targets per workgroup (11-bit local indices in the records)
+hipError_t launch_bucket(const DevNet& p, const BucketArgs& a, int steps, int block, hipStream_t s);
+hipError_t bucket_occupancy(int B, int block, int* blocks_per_cu);
+int bucket_targets_per_thread(int B, int block);   // 1, 2, 4 or 6 (0: more than 6 needed)
+size_t bucket_lds_bytes(int B);
+
 // Target-owner delivery (one kernel per step after the update kernel):
 // block k owns padded targets [bt0[k], bt0[k+1]) of instance binst[k]; it is
 // the lb = blb[k]-th block of that instance.  Row i's sub-row for the
@@ -169,10 +210,15 @@ hipError_t launch_build_blk2(const int64_t* row_ptr, const int32_t* tgt, long lo
                              hipStream_t s);
 
 constexpr int kMaxQuadsPerWgHost = 256;   // must equal the kernel's per-workgroup quad limit
-hipError_t launch_step(const DevNet& p, int offset, int qpw, int n_wg, int block, hipStream_t s);
+// wave_rows: 0 = every thread of the workgroup walks each spiking row in
+// turn; 1 = each wavefront walks whole rows (spikes dealt round robin).
+hipError_t launch_step(const DevNet& p, int offset, int qpw, int n_wg, int block, int wave_rows, hipStream_t s);
 hipError_t launch_advance(long long* step_base, int steps, hipStream_t s);
 hipError_t launch_inject(long long* ring, long long idx, long long value, hipStream_t s);
-hipError_t launch_set_weights(int32_t* wq, const double* w, long long M, hipStream_t s);
+// New weights (mode 0: set from pA values; 1/2: one gradient step with a
+// double/float gradient and rate eta); check pass sets *bad, else writes.
+hipError_t launch_weights(int32_t* wq, const void* src, int mode, double eta, long long M, unsigned* bad, bool check,
+                          hipStream_t s);
 // Connections of the Bernoulli rule drawn on the device (the host builder's
 // ConnBuilder; grid: workgroups of 256 threads; s: the stream it uses).
 struct ConnBuilder;

@@ -54,7 +54,7 @@ __device__ __forceinline__ int wave_prefix_small(int c, int* total) {
 // walks their synapse rows with all of its threads.
 // ---------------------------------------------------------------------------
 template <bool kOwnerLists>
-__global__ __launch_bounds__(kMaxBlock) void k_step(DevNet p, int offset, int qpw) {
+__global__ __launch_bounds__(kMaxBlock) void k_step(DevNet p, int offset, int qpw, int wave_rows) {
   __shared__ uint64_t s_table[kMaxPops * kTableLen];
   __shared__ int s_wcnt[kMaxWaves];
   __shared__ int s_spk[4 * kMaxQuadsPerWg];
@@ -174,13 +174,15 @@ __global__ __launch_bounds__(kMaxBlock) void k_step(DevNet p, int offset, int qp
     return;
   }
 
-  // owner delivery: all threads walk each spiking row
+  // owner delivery: all threads walk each spiking row in turn, or (wave_rows)
+  // every wavefront walks whole rows, the spikes dealt round robin
   const long long nn = n;
-  for (int s = 0; s < total; ++s) {
+  const int rstep = wave_rows ? (int)(blockDim.x >> 6) : 1;
+  for (int s = wave_rows ? (tid >> 6) : 0; s < total; s += rstep) {
     const long long rs = s_rs[s];
     const long long re = p.row_ptr[s_spk[s] + 1];
-    long long e = rs + tid;
-    const int stride = blockDim.x;
+    long long e = rs + (wave_rows ? (tid & 63) : tid);
+    const int stride = wave_rows ? 64 : blockDim.x;
     for (; e + 3 * stride < re; e += 4 * stride) {
       int t[4], w[4], d[4];
 #pragma unroll
@@ -203,10 +205,30 @@ __global__ void k_advance(long long* step_base, int steps) { *step_base += steps
 // Adds a value to one ring entry (host-requested input injection).
 __global__ void k_inject(long long* ring, long long idx, long long value) { ring[idx] += value; }
 
-// Quantises real weights (pA) to 2^-16 pA, round to nearest even.
-__global__ void k_set_weights(int32_t* wq, const double* w, long long M) {
-  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < M; k += (long long)gridDim.x * blockDim.x)
-    wq[k] = (int32_t)__double2ll_rn(w[k] * 65536.0);
+// New weights of every synapse in units of 2^-16 pA, rounded to nearest
+// even.  kWeightsSet: the real weights w_pA[k]; kWeightsStepF64/F32: one
+// gradient step w_q[k] 2^-16 - eta g[k] (g double or float), evaluated as
+// fl(w_q 2^-16 - fl(eta g)) (the first product is exact).  check: only test
+// that every new weight is finite and fits int32 (*bad = 1 if not), so that a
+// rejected update leaves the store untouched; else write them.
+enum { kWeightsSet = 0, kWeightsStepF64 = 1, kWeightsStepF32 = 2 };
+__global__ void k_weights(int32_t* wq, const void* src, int mode, double eta, long long M, unsigned* bad, int check) {
+  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < M; k += (long long)gridDim.x * blockDim.x) {
+    double w;
+    if (mode == kWeightsSet) {
+      w = static_cast<const double*>(src)[k];
+    } else {
+      const double g = (mode == kWeightsStepF64) ? static_cast<const double*>(src)[k]
+                                                 : (double)static_cast<const float*>(src)[k];
+      w = (double)wq[k] * 0x1p-16 - eta * g;
+    }
+    const double ws = w * 65536.0;
+    if (check) {
+      if (!(fabs(ws) <= 2147483647.0)) atomicOr(bad, 1u);
+    } else {
+      wq[k] = (int32_t)__double2ll_rn(ws);
+    }
+  }
 }
 
 // Packs the used prefixes of the per-workgroup raster segments (capacity
@@ -226,13 +248,13 @@ __global__ void k_raster_pack(const int2* raster, long long cap, const long long
 // ---------------------------------------------------------------------------
 namespace mc {
 
-hipError_t launch_step(const DevNet& p, int offset, int qpw, int n_wg, int block, hipStream_t s) {
-  hipLaunchKernelGGL(k_step<false>, dim3(n_wg), dim3(block), 0, s, p, offset, qpw);
+hipError_t launch_step(const DevNet& p, int offset, int qpw, int n_wg, int block, int wave_rows, hipStream_t s) {
+  hipLaunchKernelGGL(k_step<false>, dim3(n_wg), dim3(block), 0, s, p, offset, qpw, wave_rows);
   return hipGetLastError();
 }
 
 hipError_t launch_step_lists(const DevNet& p, int offset, int qpw, int n_wg, int block, hipStream_t s) {
-  hipLaunchKernelGGL(k_step<true>, dim3(n_wg), dim3(block), 0, s, p, offset, qpw);
+  hipLaunchKernelGGL(k_step<true>, dim3(n_wg), dim3(block), 0, s, p, offset, qpw, 0);
   return hipGetLastError();
 }
 
@@ -253,11 +275,12 @@ hipError_t launch_raster_pack(const int2* raster, long long cap, const long long
   return hipGetLastError();
 }
 
-hipError_t launch_set_weights(int32_t* wq, const double* w, long long M, hipStream_t s) {
+hipError_t launch_weights(int32_t* wq, const void* src, int mode, double eta, long long M, unsigned* bad, bool check,
+                          hipStream_t s) {
   if (M == 0) return hipSuccess;
   long long blocks = (M + 255) / 256;
   if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(k_set_weights, dim3((unsigned)blocks), dim3(256), 0, s, wq, w, M);
+  hipLaunchKernelGGL(k_weights, dim3((unsigned)blocks), dim3(256), 0, s, wq, src, mode, eta, M, bad, check ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -36,12 +36,15 @@
 // five workgroups publish no spike in a step and nearly all others at most
 // four, so one load of word 0 usually completes a record.  Every word carries
 // a tag, so a consumer accepts a record when all the words it needs show the
-// current step, whatever order the stores became visible in.  Spikes beyond
+// current step, whatever order the stores became visible in; a tag is the
+// step alone, which suffices because the last workgroup to finish a launch
+// clears every record, so that no record outlives the launch that wrote it
+// (also across rewinds of the state to earlier steps).  Spikes beyond
 // the seventh are written to a side array before word 0 (with a wait for
 // their completion), so they are visible once word 0 is.  All of these are
 // device-scope atomic accesses (coherent at the memory side), so the step
-// needs no L2 writeback or invalidate.  Every wait is bounded; on timeout the kernel sets an error bit
-// and every workgroup leaves the loop.
+// needs no L2 writeback or invalidate.  Every wait is bounded in time (wall clock); on timeout the
+// kernel sets error bit 2 and every workgroup leaves the loop.
 #pragma clang fp contract(off)
 
 #include "mc_device.h"
@@ -261,7 +264,7 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
   __shared__ int s_tmp[2][16];
   __shared__ int s_local[kPersistMaxB];
   __shared__ int s_cnt[kPersistMaxBlock];   // spike count of every producer in the current step
-  __shared__ int s_abort;
+  __shared__ int s_abort, s_last;
   __shared__ int s_nids, s_nbig;                 // ids listed by the poller this step; producers with more
   __shared__ int2 s_big[kBigCap];                // (producer, list offset) of those producers
   __shared__ unsigned long long s_events;
@@ -298,16 +301,22 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
   if (tid == 0) { s_abort = 0; s_events = 0; }
   if (tid < kMaxPops) s_popcnt[tid] = 0;
   __syncthreads();
-  // take the next DL steps of pending input of my targets into LDS; mark far entries
-  for (int k = tid; k < 128 * Bg; k += nthr) {
+  // take the next DL steps of pending input of my targets into LDS; mark far
+  // entries.  Only the first `horizon` slots can hold input (the largest
+  // delay, or further after an injection or a loaded state).  Inside a launch
+  // only the owner workgroup touches its targets' ring entries, so device-
+  // scope loads and stores suffice (no read-modify-write).
+  const int take = min(DL, a.horizon), scan = min(127, a.horizon);
+  for (int k = tid; k < scan * Bg; k += nthr) {
     const int m = k / Bg, jl = k - m * Bg;
     const long long step = n0 + m;
     long long* e = p.ring + (size_t)(step & kRingMask) * p.ring_stride + j0 + jl;
-    if (m < DL) {
-      acc[(size_t)(step % DL) * a.B + jl] =
-          (long long)__hip_atomic_exchange(reinterpret_cast<unsigned long long*>(e), 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else if (m < 127) {
-      if (ld_dev(e) != 0) atomicOr(&fbits[(step & kRingMask) * a.BW + (jl >> 5)], 1u << (jl & 31));
+    const long long v = ld_dev(e);
+    if (m < take) {
+      acc[(size_t)(step % DL) * a.B + jl] = v;
+      if (v != 0) st_dev(e, 0ll);
+    } else if (m >= DL && v != 0) {
+      atomicOr(&fbits[(step & kRingMask) * a.BW + (jl >> 5)], 1u << (jl & 31));
     }
   }
   // neuron state into registers: thread t < Bg owns neuron j0+t; the four
@@ -467,7 +476,7 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
     const bool work_now = overlap && !pollw;
     if (pollw) {
       const int lane = tid & 63;
-      long long spins = 0;
+      const long long t_poll = wall_clock64();
       unsigned todo = 0;
 #pragma unroll
       for (int r = 0; r < kPollPerLane; ++r)
@@ -519,7 +528,7 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
         }
         if (!todo) break;
         __builtin_amdgcn_s_sleep(1);
-        if (++spins > a.spin_limit) {
+        if (wall_clock64() - t_poll > a.wait_ticks) {
           atomicOr(p.overflow, 2u);
           s_abort = 1;
 #pragma unroll
@@ -678,18 +687,107 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
     p.raster_cnt[g] = rcnt;
     p.wg_events[g] += s_events;
   }
+  // the global entry of a window slot is zero unless far events were added
+  // to it (its far bit): a store, else an add
   for (int k = tid; k < DL * Bg; k += nthr) {
     const int m = k / Bg, jl = k - m * Bg;
     const long long step = n_end + m;
     const long long v = acc[(size_t)(step % DL) * a.B + jl];
-    if (v != 0)
-      atomicAdd(reinterpret_cast<unsigned long long*>(p.ring + (size_t)(step & kRingMask) * p.ring_stride + j0 + jl),
-                (unsigned long long)v);
+    if (v == 0) continue;
+    long long* e = p.ring + (size_t)(step & kRingMask) * p.ring_stride + j0 + jl;
+    if (fbits[(step & kRingMask) * a.BW + (jl >> 5)] & (1u << (jl & 31)))
+      atomicAdd(reinterpret_cast<unsigned long long*>(e), (unsigned long long)v);
+    else
+      st_dev(e, v);
+  }
+  // The last workgroup to finish (every other one has read all the records it
+  // will read) clears the spike records for the next launch and advances the
+  // step counter (every workgroup read it before its first record).
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (tid == 0) {
+    unsigned long long* done = a.flags + persist_record_words(a.G);
+    s_last = (__hip_atomic_fetch_add(done, 1ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == (unsigned long long)(a.G - 1));
+  }
+  __syncthreads();
+  if (s_last) {
+    const int words = (int)persist_record_words(a.G);
+    for (int k = tid; k < words; k += nthr) st_dev(&a.flags[k], 0ull);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (tid == 0) {
+      st_dev(p.step_base, n_end);
+      __hip_atomic_store(a.flags + persist_record_words(a.G), 0ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
   }
 }
 
-__global__ void k_zero_flags(unsigned long long* flags, int n) {
-  for (int k = threadIdx.x; k < n; k += blockDim.x) flags[k] = 0;
+// The exchange of k_persist with nothing else: every step, each of the G
+// workgroups publishes a step-tagged record (word 0 as in k_persist, no
+// spikes) and its last wavefront polls all G records of the step the same
+// way (eight producers per lane, device-scope loads, a short sleep between
+// rounds); then a barrier and the next step.  The time per step is the floor
+// the persistent kernel's step cannot go below.  Records are cleared by the
+// last workgroup to finish, as in k_persist.
+__global__ __launch_bounds__(kPersistMaxBlock) void k_exchange_probe(unsigned long long* flags, int G, long long steps,
+                                                                     long long wait_ticks, unsigned* err) {
+  __shared__ int s_abort, s_last;
+  const int g = blockIdx.x, tid = threadIdx.x, nthr = blockDim.x;
+  const int nw = nthr >> 6, wave = tid >> 6, lane = tid & 63;
+  if (tid == 0) s_abort = 0;
+  __syncthreads();
+  for (long long n = 0; n < steps; ++n) {
+    const unsigned long long tag16 = (unsigned long long)((n + 1) % 65535 + 1) << 48;
+    const size_t rslot = (size_t)(n % kRecSlots);
+    if (tid == 0) st_dev(&flags[((size_t)g * kRecSlots + rslot) * kPersistFlagStride], tag16);
+    if (wave == nw - 1) {
+      const long long t_poll = wall_clock64();
+      unsigned todo = 0;
+#pragma unroll
+      for (int r = 0; r < kPollPerLane; ++r)
+        if (lane + 64 * r < G) todo |= 1u << r;
+      while (todo) {
+        unsigned long long w0[kPollPerLane];
+#pragma unroll
+        for (int r = 0; r < kPollPerLane; ++r)
+          w0[r] = ((todo >> r) & 1u) ? ld_dev(&flags[((size_t)(lane + 64 * r) * kRecSlots + rslot) * kPersistFlagStride])
+                                     : 0ull;
+#pragma unroll
+        for (int r = 0; r < kPollPerLane; ++r)
+          if (((todo >> r) & 1u) && (w0[r] & 0xFFFF000000000000ull) == tag16) todo &= ~(1u << r);
+        if (!todo) break;
+        __builtin_amdgcn_s_sleep(1);
+        if (wall_clock64() - t_poll > wait_ticks) {
+          atomicOr(err, 2u);
+          s_abort = 1;
+          break;
+        }
+      }
+    }
+    __syncthreads();
+    if (s_abort) break;
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (tid == 0) {
+    unsigned long long* done = flags + persist_record_words(G);
+    s_last = (__hip_atomic_fetch_add(done, 1ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == (unsigned long long)(G - 1));
+  }
+  __syncthreads();
+  if (s_last) {
+    const int words = (int)persist_record_words(G);
+    for (int k = tid; k < words; k += nthr) st_dev(&flags[k], 0ull);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (tid == 0) __hip_atomic_store(flags + persist_record_words(G), 0ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+hipError_t launch_exchange_probe(unsigned long long* flags, int G, int block, long long steps, long long wait_ticks,
+                                 unsigned* err, hipStream_t s) {
+  if (G < 1 || G > kPersistMaxBlock || block < 64 || block > kPersistMaxBlock || block % 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_exchange_probe, dim3(G), dim3(block), 0, s, flags, G, steps, wait_ticks, err);
+  return hipGetLastError();
 }
 
 // blk[i][g] = first synapse of row i whose target is >= bstart[g] (rows sorted by target).
@@ -772,7 +870,6 @@ hipError_t persist_occupancy(int block, size_t lds, int* blocks_per_cu) {
 
 hipError_t launch_persist(const DevNet& p, const PersistArgs& a, int steps, int block, hipStream_t s) {
   const size_t lds = persist_lds_bytes(a.G, a.B, a.DL);
-  hipLaunchKernelGGL(k_zero_flags, dim3(1), dim3(256), 0, s, a.flags, (int)persist_flag_words(a.G));
   hipLaunchKernelGGL(k_persist, dim3(a.G), dim3(block), lds, s, p, a, steps);
   return hipGetLastError();
 }

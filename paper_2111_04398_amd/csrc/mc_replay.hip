@@ -1,5 +1,7 @@
 // mc_replay.hip -- throughput form of the delivery: the recorded spikes of
-// many steps delivered in one launch, and the chip's random int64 atomic rate.
+// many steps delivered in one launch; and the microbenchmarks of what the
+// memory system achieves for the delivery's two costs: a streaming read
+// (the synapse records) and int64 atomic adds into a slot-major ring.
 //
 // In the simulation loop a step of the full microcircuit delivers only
 // ~2.5e5 events, so the loop is bound by latency, not by bandwidth.  To see
@@ -55,6 +57,92 @@ __global__ __launch_bounds__(256) void k_atomic_rate(unsigned long long* table, 
     x ^= x << 13; x ^= x >> 7; x ^= x << 17;
     atomicAdd(&table[(x >> 11) % (unsigned long long)n], 1ull);
   }
+}
+
+// Streaming read of `n16` 16-byte words (grid-stride, four loads in flight
+// per lane): the achievable HBM read bandwidth.  The XOR of what a thread
+// read is stored only if it equals a value the data never produce, so the
+// loads cannot be dropped.
+__global__ __launch_bounds__(256) void k_stream_read(const ulonglong2* src, long long n16, unsigned long long* sink) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  unsigned long long x = 0;
+  long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  for (; k + 3 * stride < n16; k += 4 * stride) {
+    const ulonglong2 a = src[k], b = src[k + stride], c = src[k + 2 * stride], d = src[k + 3 * stride];
+    x ^= a.x ^ a.y ^ b.x ^ b.y ^ c.x ^ c.y ^ d.x ^ d.y;
+  }
+  for (; k < n16; k += stride) { const ulonglong2 a = src[k]; x ^= a.x ^ a.y; }
+  if (x == 0x5A5A5A5A5A5A5A5Aull) sink[0] = x;
+}
+
+// Slot-major int64 atomic adds into table[slot][target] (slots x stride
+// entries), in work items of 256 events (4 per lane, one wavefront).
+// pattern 0: every event at a uniformly random (slot, target);
+// pattern 1: the delivery's own pattern -- an item is a chunk of one source
+// row at spike step t (t advancing with the item index over the first
+// slots - 101 slots): targets ascending with gaps uniform in [1, 2 gap - 1],
+// each event's delay drawn from the network's delay histogram (dcdf: 32-bit
+// cumulative, dcdf[d] = P(delay <= d) 2^32), landing in slot t + delay.
+__device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__global__ __launch_bounds__(256) void k_atomic_slots(unsigned long long* table, long long slots, long long stride,
+                                                      long long n_targets, long long n_items, int pattern, int gap,
+                                                      const unsigned* dcdf) {
+  __shared__ unsigned s_cdf[128];
+  for (int k = threadIdx.x; k < 128; k += blockDim.x) s_cdf[k] = dcdf[k];
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const long long wave = (blockIdx.x * (long long)blockDim.x + threadIdx.x) >> 6;
+  const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
+  const long long tspan = slots > 101 ? slots - 101 : 1;
+  for (long long item = wave; item < n_items; item += nwaves) {
+    const unsigned long long h0 = mix64((unsigned long long)item);
+    const long long t = item * tspan / n_items;
+    // row chunk: lane l of round u takes event 64u + l; its target is the
+    // chunk start plus the prefix of the gaps up to it
+    long long tg = (long long)(h0 % (unsigned long long)n_targets);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const unsigned long long h = mix64(h0 ^ (unsigned long long)(u * 64 + lane + 1));
+      long long slot, target;
+      if (pattern == 0) {
+        slot = (long long)((h >> 40) % (unsigned long long)slots);
+        target = (long long)((h & 0xFFFFFFFFFFull) % (unsigned long long)n_targets);
+      } else {
+        int g = 1 + (int)((h >> 8) % (unsigned long long)(2 * gap - 1));
+        int x = g;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+          const int y = __shfl_up(x, o, 64);
+          if (lane >= o) x += y;
+        }
+        target = (tg + x) % n_targets;
+        tg += __shfl(x, 63, 64);
+        const unsigned r = (unsigned)(h >> 32);
+        int d = 1;
+        while (d < 127 && r >= s_cdf[d]) ++d;
+        slot = (t + d) % slots;
+      }
+      atomicAdd(&table[(size_t)slot * stride + target], 1ull);
+    }
+  }
+}
+
+hipError_t launch_stream_read(const void* src, long long bytes, unsigned long long* sink, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_stream_read, dim3(grid), dim3(256), 0, s, (const ulonglong2*)src, bytes / 16, sink);
+  return hipGetLastError();
+}
+
+hipError_t launch_atomic_slots(unsigned long long* table, long long slots, long long stride, long long n_targets,
+                               long long n_items, int pattern, int gap, const unsigned* dcdf, int grid,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_atomic_slots, dim3(grid), dim3(256), 0, s, table, slots, stride, n_targets, n_items, pattern,
+                     gap, dcdf);
+  return hipGetLastError();
 }
 
 hipError_t launch_replay(const int2* spikes, const long long* first_item, int n_spikes, long long n_items,

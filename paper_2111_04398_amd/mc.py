@@ -24,6 +24,8 @@ MC_OK = 0
 MC_ERR_INVALID_ARG = -1
 MC_ERR_BUFFER_TOO_SMALL = -6
 MC_ERR_MISMATCH = -8
+MC_ERR_RANGE = -2
+MC_ERR_TIMEOUT = -9
 MC_MAX_POPS = 16
 RING_SLOTS = 128
 RULE_FIXED_INDEGREE, RULE_BERNOULLI = 0, 1
@@ -31,10 +33,11 @@ GRAD_F64, GRAD_F32 = 0, 1
 ADJ_INPUT_AUTO, ADJ_INPUT_RECORD, ADJ_INPUT_REPLAY = 0, 1, 2
 FLAG_HOST_ONLY = 1
 FLAG_DEVICE_CONNECT = 2
-SCHEME_STEP_KERNELS, SCHEME_PERSISTENT_LDS, SCHEME_TARGET_OWNER = 0, 1, 2
+SCHEME_STEP_KERNELS, SCHEME_PERSISTENT_LDS, SCHEME_TARGET_OWNER, SCHEME_PERSISTENT_BUCKETS = 0, 1, 2, 3
 
 ERROR_NAMES = {0: "MC_OK", -1: "MC_ERR_INVALID_ARG", -2: "MC_ERR_RANGE", -3: "MC_ERR_OOM", -4: "MC_ERR_HIP",
-               -5: "MC_ERR_STATE", -6: "MC_ERR_BUFFER_TOO_SMALL", -7: "MC_ERR_NO_DEVICE", -8: "MC_ERR_MISMATCH"}
+               -5: "MC_ERR_STATE", -6: "MC_ERR_BUFFER_TOO_SMALL", -7: "MC_ERR_NO_DEVICE", -8: "MC_ERR_MISMATCH",
+               -9: "MC_ERR_TIMEOUT"}
 
 
 class MCError(RuntimeError):
@@ -55,12 +58,18 @@ class mc_config(C.Structure):
         ("h_ms", C.c_double), ("v0_lo_mV", C.c_double), ("v0_hi_mV", C.c_double),
         ("n_instances", C.c_int32), ("inst_scale", C.POINTER(C.c_double)), ("inst_seed", C.POINTER(C.c_uint64)),
         ("hip_stream", C.c_void_p), ("flags", C.c_uint32),
+        ("dev_alloc", C.c_void_p), ("dev_free", C.c_void_p), ("alloc_ctx", C.c_void_p),
     ]
+
+
+#: allocator hook types of mc_config
+DEV_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+DEV_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
 
 class mc_launch(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("scheme", C.c_int32), ("block", C.c_int32),
-                ("neurons_per_wg", C.c_int32), ("steps_per_graph", C.c_int32)]
+                ("neurons_per_wg", C.c_int32), ("steps_per_graph", C.c_int32), ("rows_per_wave", C.c_int32)]
 
 
 class mc_counters(C.Structure):
@@ -80,7 +89,8 @@ EXPORTS = [
     "mc_get_state", "mc_set_state", "mc_get_ring", "mc_inject", "mc_get_propagators", "mc_get_drive_tables",
     "mc_get_counters", "mc_set_launch", "mc_get_launch", "mc_tune", "mc_last_simulate_ms", "mc_reserve",
     "mc_save_state", "mc_load_state", "mc_set_weights", "mc_stream", "mc_profile_phases", "mc_replay_delivery",
-    "mc_atomic_rate", "mc_last_adjoint_ms", "mc_get_persist_shape", "mc_get_phase_table",
+    "mc_atomic_rate", "mc_last_adjoint_ms", "mc_get_persist_shape", "mc_get_phase_table", "mc_apply_gradient",
+    "mc_last_kernel_ms", "mc_probe_stream", "mc_probe_atomics", "mc_probe_exchange",
 ]
 
 _lib = None
@@ -129,10 +139,15 @@ def lib() -> C.CDLL:
     L.mc_get_launch.argtypes = [vp, C.POINTER(mc_launch)]
     L.mc_tune.argtypes = [vp, i64, C.POINTER(mc_launch)]
     L.mc_last_simulate_ms.argtypes = [vp, C.POINTER(f64)]
+    L.mc_last_kernel_ms.argtypes = [vp, C.POINTER(f64), C.POINTER(i64), C.POINTER(i64)]
+    L.mc_probe_stream.argtypes = [vp, i64, C.POINTER(f64)]
+    L.mc_probe_atomics.argtypes = [vp, i64, i32, C.POINTER(f64)]
+    L.mc_probe_exchange.argtypes = [vp, i64, C.POINTER(f64)]
     L.mc_reserve.argtypes = [vp, i64]
     L.mc_save_state.argtypes = [vp, vp, C.c_size_t, C.POINTER(C.c_size_t)]
     L.mc_load_state.argtypes = [vp, vp, C.c_size_t]
     L.mc_set_weights.argtypes = [vp, vp]
+    L.mc_apply_gradient.argtypes = [vp, vp, i32, f64]
     L.mc_stream.argtypes = [vp, C.POINTER(vp)]
     L.mc_profile_phases.argtypes = [vp, i64, P(np.float64)]
     L.mc_replay_delivery.argtypes = [vp, i64, i64, vp, i64, C.POINTER(f64), C.POINTER(i64)]
@@ -157,7 +172,9 @@ class Network:
     """An ``mc_net`` handle: build, simulate, observe, differentiate."""
 
     def __init__(self, w: Workload, host_only: bool = False, stream: Optional[int] = None,
-                 device_connect: bool = False):
+                 device_connect: bool = False, allocator=None):
+        """allocator: optional (dev_alloc(bytes) -> device pointer int, dev_free(ptr))
+        pair of Python callables; every device buffer of the network comes from it."""
         self.workload = w
         n = w.n_pops
         self._keep = [
@@ -191,6 +208,13 @@ class Network:
         c.inst_seed = seeds.ctypes.data_as(C.POINTER(C.c_uint64))
         c.hip_stream = stream
         c.flags = (FLAG_HOST_ONLY if host_only else 0) | (FLAG_DEVICE_CONNECT if device_connect else 0)
+        if allocator is not None:
+            fa, ff = allocator
+            # the callbacks must outlive the network: kept on the object
+            self._hooks = (DEV_ALLOC_FN(lambda nbytes, ctx: fa(nbytes) or None),
+                           DEV_FREE_FN(lambda ptr, ctx: ff(ptr)))
+            c.dev_alloc = C.cast(self._hooks[0], C.c_void_p)
+            c.dev_free = C.cast(self._hooks[1], C.c_void_p)
         h = C.c_void_p()
         _check(lib().mc_build_network(C.byref(c), C.byref(h)), "mc_build_network")
         self.h = h
@@ -292,22 +316,27 @@ class Network:
         _check(lib().mc_get_pop_offsets(self.h, instance, o), "mc_get_pop_offsets")
         return o
 
-    def set_launch(self, scheme=SCHEME_STEP_KERNELS, block=256, neurons_per_wg=256, steps_per_graph=1000):
-        l = mc_launch(C.sizeof(mc_launch), scheme, block, neurons_per_wg, steps_per_graph)
+    def set_launch(self, scheme=SCHEME_STEP_KERNELS, block=256, neurons_per_wg=256, steps_per_graph=1000,
+                   rows_per_wave=0):
+        l = mc_launch(C.sizeof(mc_launch), scheme, block, neurons_per_wg, steps_per_graph, rows_per_wave)
         _check(lib().mc_set_launch(self.h, C.byref(l)), "mc_set_launch")
+
+    @staticmethod
+    def _launch_dict(l) -> dict:
+        return {"scheme": l.scheme, "block": l.block, "neurons_per_wg": l.neurons_per_wg,
+                "steps_per_graph": l.steps_per_graph, "rows_per_wave": l.rows_per_wave}
 
     def get_launch(self) -> dict:
         l = mc_launch()
         _check(lib().mc_get_launch(self.h, C.byref(l)), "mc_get_launch")
-        return {"scheme": l.scheme, "block": l.block, "neurons_per_wg": l.neurons_per_wg,
-                "steps_per_graph": l.steps_per_graph}
+        return self._launch_dict(l)
 
     def tune(self, steps: int) -> dict:
-        """Times the candidate launch shapes and keeps the fastest (state restored)."""
+        """Times the candidate launch shapes and keeps the fastest (state
+        restored); with MC_TUNE_CACHE set, a stored choice is applied untimed."""
         l = mc_launch()
         _check(lib().mc_tune(self.h, steps, C.byref(l)), "mc_tune")
-        return {"scheme": l.scheme, "block": l.block, "neurons_per_wg": l.neurons_per_wg,
-                "steps_per_graph": l.steps_per_graph}
+        return self._launch_dict(l)
 
     def profile_phases(self, steps: int) -> dict:
         us = np.zeros(8, np.float64)
@@ -342,10 +371,36 @@ class Network:
         _check(lib().mc_atomic_rate(self.h, entries, C.byref(g)), "mc_atomic_rate")
         return g.value
 
+    def probe_stream(self, nbytes: int) -> float:
+        """Streaming-read bandwidth (GB/s) over nbytes of device memory."""
+        g = C.c_double()
+        _check(lib().mc_probe_stream(self.h, int(nbytes), C.byref(g)), "mc_probe_stream")
+        return g.value
+
+    def probe_atomics(self, slots: int, pattern: int) -> float:
+        """int64 atomic adds (1e9/s) into a slots x ring-stride table; pattern
+        0 uniform, 1 the delivery's row and delay pattern."""
+        g = C.c_double()
+        _check(lib().mc_probe_atomics(self.h, int(slots), int(pattern), C.byref(g)), "mc_probe_atomics")
+        return g.value
+
+    def probe_exchange(self, steps: int) -> float:
+        """us per step of the persistent scheme's exchange alone."""
+        g = C.c_double()
+        _check(lib().mc_probe_exchange(self.h, int(steps), C.byref(g)), "mc_probe_exchange")
+        return g.value
+
     def last_simulate_ms(self) -> float:
         ms = C.c_double()
         _check(lib().mc_last_simulate_ms(self.h, C.byref(ms)), "mc_last_simulate_ms")
         return ms.value
+
+    def last_kernel_ms(self) -> dict:
+        """Persistent kernel launches of the most recent simulate: summed HIP-event
+        durations (ms), launches timed and the steps they covered."""
+        ms, k, st = C.c_double(), C.c_int64(), C.c_int64()
+        _check(lib().mc_last_kernel_ms(self.h, C.byref(ms), C.byref(k), C.byref(st)), "mc_last_kernel_ms")
+        return {"ms": ms.value, "launches": k.value, "steps": st.value}
 
     def persist_shape(self) -> dict:
         """Persistent-scheme shape in use (zeros under the step kernels)."""
@@ -374,6 +429,11 @@ class Network:
 
     def set_weights(self, w_dev_ptr: int):
         _check(lib().mc_set_weights(self.h, C.c_void_p(w_dev_ptr)), "mc_set_weights")
+
+    def apply_gradient(self, grad_dev_ptr: int, fp32: bool, eta: float):
+        """mc_apply_gradient: w <- rint((w - eta g) 2^16) 2^-16 pA on the device store."""
+        _check(lib().mc_apply_gradient(self.h, C.c_void_p(grad_dev_ptr), GRAD_F32 if fp32 else GRAD_F64, float(eta)),
+               "mc_apply_gradient")
 
     def stream(self) -> int:
         s = C.c_void_p()

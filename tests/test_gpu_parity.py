@@ -97,9 +97,9 @@ def test_launch_configuration_invariance(scheme, block, npw, spg):
 
 
 # the launch shapes mc_tune times (same list and steps per graph)
-TUNER_CANDIDATES = [(1, 512, 0, 10000), (1, 256, 0, 10000), (1, 512, 256, 10000), (1, 512, 512, 10000),
-                    (1, 256, 128, 10000), (2, 256, 256, 1000), (2, 256, 128, 1000), (2, 256, 64, 1000),
-                    (0, 256, 256, 1000), (0, 256, 1024, 1000), (0, 512, 512, 1000), (0, 128, 128, 1000)]
+TUNER_CANDIDATES = [(1, 512, 0, 10000, 0), (1, 256, 0, 10000, 0), (1, 512, 256, 10000, 0), (1, 512, 512, 10000, 0),
+                    (1, 256, 128, 10000, 0), (0, 256, 256, 1000, 0), (0, 256, 256, 1000, 1), (0, 256, 1024, 1000, 0),
+                    (0, 512, 512, 1000, 0), (0, 512, 512, 1000, 1), (0, 128, 128, 1000, 0), (0, 128, 128, 1000, 1)]
 
 
 def test_every_autotuner_candidate_gives_the_same_bits():
@@ -110,7 +110,7 @@ def test_every_autotuner_candidate_gives_the_same_bits():
     o.run(900)
     for c in TUNER_CANDIDATES:
         net = mc.Network(w)
-        net.set_launch(scheme=c[0], block=c[1], neurons_per_wg=c[2], steps_per_graph=c[3])
+        net.set_launch(scheme=c[0], block=c[1], neurons_per_wg=c[2], steps_per_graph=c[3], rows_per_wave=c[4])
         net.simulate(900)
         assert_same(net, o, ring_depth=128, what=f"candidate {c}")
         net.close()
@@ -184,28 +184,35 @@ def test_persistent_scheme_at_its_largest_shape():
     assert_same(net, o, ring_depth=16, what="max persistent")
 
 
-@pytest.mark.parametrize("name", ["tiny_bernoulli", "adjoint_small", "batched_4", "balanced", "microcircuit"])
-def test_device_connection_drawing_builds_the_same_network(name):
-    """MC_FLAG_DEVICE_CONNECT draws the Bernoulli pair tests on the device;
-    the synapse store (rows, targets, weights, delays) equals the host
-    build's bit for bit, and so does the trajectory.  The fixed in-degree
-    rule (balanced) ignores the flag."""
-    w = {"tiny_bernoulli": tiny_bernoulli, "adjoint_small": workloads.adjoint_small,
+@pytest.mark.parametrize("name", ["tiny_fixed", "tiny_bernoulli", "adjoint_small", "batched_4", "balanced",
+                                  "microcircuit"])
+def test_device_connection_drawing_builds_the_oracles_network(name):
+    """MC_FLAG_DEVICE_CONNECT draws the connections on the device (the pair
+    tests of the Bernoulli rule, the source draws of the fixed in-degree
+    rule); the synapse store (rows, targets, weights, delays) equals the
+    oracle's bit for bit, instance by instance for the batch, and so does
+    the trajectory."""
+    w = {"tiny_fixed": tiny_fixed, "tiny_bernoulli": tiny_bernoulli, "adjoint_small": workloads.adjoint_small,
          "batched_4": lambda: workloads.batched(n_instances=4, sim_steps=300),
          "balanced": workloads.balanced, "microcircuit": workloads.microcircuit}[name]()
-    a = mc.Network(w)
-    b = mc.Network(w, device_connect=True)
-    sa, sb = a.synapses(), b.synapses()
-    for x, y in zip(sa, sb):
-        assert x.dtype == y.dtype and np.array_equal(x, y), name
-    del sa, sb
-    for net in (a, b):
+    net = mc.Network(w, device_connect=True)
+    rp, tg, wq, d = net.synapses()
+    off = net.instance_offsets()
+    for b in range(net.n_instances):
+        o = oracle.Oracle(w.instance(b).to_dict())
+        orp, otg, owq, od = o.synapses()
+        m0, m1 = rp[off[b]], rp[off[b + 1]]
+        assert np.array_equal(rp[off[b]:off[b + 1] + 1] - m0, orp), (name, b)
+        assert np.array_equal(tg[m0:m1] - off[b], otg), (name, b)
+        assert np.array_equal(wq[m0:m1], owq) and np.array_equal(d[m0:m1], od), (name, b)
+        del o, orp, otg, owq, od
+    del rp, tg, wq, d
+    if net.n_instances == 1 and net.M < 10_000_000:
+        o = oracle.Oracle(w.to_dict())
         net.set_launch(scheme=0, block=256, neurons_per_wg=256, steps_per_graph=100)
         net.simulate(200)
-    s0, i0 = a.spikes()
-    s1, i1 = b.spikes()
-    assert np.array_equal(s0, s1) and np.array_equal(i0, i1)
-    assert np.array_equal(a.state()[0].view(np.uint64), b.state()[0].view(np.uint64))
+        o.run(200)
+        assert_same(net, o, what=name)
 
 
 def test_recording_allocation_failure_keeps_the_handle_usable():
@@ -348,6 +355,49 @@ def test_batched_instances_match_standalone(scheme):
     assert net.counters()["events"] == total_events
 
 
+@pytest.mark.slow
+def test_batched_c2_full_shape_matches_per_instance_oracles():
+    """The 64-instance batch at its benchmark shape (seeds 1001-1064, scales
+    0.05-0.25, 750,775 neurons, ~5e8 synapses) under the launch the
+    autotuner picks for it, 1000 presim steps and 300 more: every
+    instance's raster, y/I/r bits, first 8 logical ring slots and event and
+    spike counters equal its standalone oracle's, run one instance after
+    another on the host."""
+    w = workloads.batched()
+    net = mc.Network(w, device_connect=True)
+    assert net.n_instances == 64 and net.N == 750_775
+    net.simulate(100)
+    best = net.tune(200)
+    print("c2 launch:", best, flush=True)
+    net.simulate(w.presim_steps - 100)
+    net.simulate(300)
+    s, i = net.spikes()
+    y, I, r = net.state()
+    ring = net.ring(8)
+    off = net.instance_offsets()
+    c = net.counters()
+    ev_total, sp_total = 0, np.zeros(w.n_pops, np.int64)
+    for b in range(64):
+        o = oracle.Oracle(w.instance(b).to_dict())
+        o.run(w.presim_steps + 300)
+        os_, oi = o.raster()
+        m = (i >= off[b]) & (i < off[b + 1])
+        assert np.array_equal(s[m], os_) and np.array_equal(i[m] - off[b], oi), (b, best)
+        oy, oI, orr = o.state()
+        sl = slice(off[b], off[b + 1])
+        assert np.array_equal(y[sl].view(np.uint64), oy.view(np.uint64)), b
+        assert np.array_equal(I[sl].view(np.uint64), oI.view(np.uint64)), b
+        assert np.array_equal(r[sl], orr), b
+        assert np.array_equal(ring[:, sl], o.ring(8)), b
+        sp, ev = o.counters()
+        ev_total += ev
+        sp_total += sp
+        del o
+        print(f"c2 instance {b}: {m.sum()} spikes equal", flush=True)
+    assert c["events"] == ev_total and np.array_equal(c["spikes_per_pop"], sp_total)
+    assert c["step"] == w.presim_steps + 300 and len(s) > 100_000
+
+
 @pytest.fixture(scope="module")
 def micro_oracle_runs():
     """Oracle trajectory of the full microcircuit: after 1000 and 1300 steps."""
@@ -429,3 +479,67 @@ def test_autotuner_and_phase_profile_keep_the_trajectory():
     net.simulate(200)
     o.run(1200)
     assert_same(net, o, what=f"tuned {best}")
+
+
+def test_network_lives_in_torch_allocator_memory():
+    """With the allocator hooks of mc_config every device buffer of the
+    network (synapse store, state, ring, raster, the persistent scheme's
+    tables) comes from torch's caching allocator and goes back to it; the
+    trajectory is the oracle's."""
+    import torch
+    allocs, frees = {}, []
+
+    def fa(nbytes):
+        p = torch.cuda.caching_allocator_alloc(nbytes)
+        allocs[p] = nbytes
+        return p
+
+    def ff(ptr):
+        torch.cuda.caching_allocator_delete(ptr)
+        frees.append(ptr)
+
+    w = workloads.balanced()
+    net = mc.Network(w, allocator=(fa, ff))
+    o = oracle.Oracle(w.to_dict())
+    assert sum(allocs.values()) >= 9 * net.M          # the synapse store came from torch
+    net.set_launch(scheme=1, block=512, neurons_per_wg=0, steps_per_graph=200)
+    net.simulate(500)
+    o.run(500)
+    assert_same(net, o, what="torch allocator")
+    net.close()
+    assert sorted(frees) == sorted(allocs) and len(frees) > 10
+
+
+@pytest.mark.parametrize("block,npw,spg", [(256, 256, 1000), (64, 64, 1), (1024, 512, 333)])
+def test_rows_per_wavefront_delivery(block, npw, spg):
+    """The step kernels' delivery with each wavefront walking whole rows
+    gives the oracle's bits."""
+    w = workloads.balanced()
+    net, o = mc.Network(w), oracle.Oracle(w.to_dict())
+    net.set_launch(scheme=0, block=block, neurons_per_wg=npw, steps_per_graph=spg, rows_per_wave=1)
+    net.simulate(800)
+    o.run(800)
+    assert_same(net, o, what=f"rows per wave {block},{npw},{spg}")
+
+
+def test_tune_cache_skips_the_second_tuning(tmp_path, monkeypatch):
+    """With MC_TUNE_CACHE set, the first mc_tune times the candidates and
+    stores its choice under the network's shape and device; a second network
+    of the same shape gets the stored launch without any timing (the cache
+    file gains no line), and its trajectory is the oracle's."""
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("MC_TUNE_CACHE", str(cache))
+    w = workloads.balanced()
+    a = mc.Network(w)
+    first = a.tune(100)
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1 and lines[0].split()[1:6] == [str(first[k]) for k in
+                                                         ("scheme", "block", "neurons_per_wg", "steps_per_graph",
+                                                          "rows_per_wave")]
+    b = mc.Network(w.replace(seed=9))
+    second = b.tune(100)
+    assert second == first and cache.read_text().splitlines() == lines
+    o = oracle.Oracle(w.replace(seed=9).to_dict())
+    b.simulate(500)
+    o.run(500)
+    assert_same(b, o, what="cached launch")
