@@ -460,7 +460,7 @@ def run_batched(args, mc, w) -> dict:
     the same instances simulated one after another as plain networks."""
     steps = args.steps or w.sim_steps
     t0 = time.perf_counter()
-    net = mc.Network(w)
+    net = mc.Network(w, device_connect=True)
     build_s = time.perf_counter() - t0
     gpu_ms, events, spikes, host_s, tuned = timed_run(net, steps, args.warmup, args.launch, args.tune_steps)
     launch = net.get_launch()
@@ -470,7 +470,7 @@ def run_batched(args, mc, w) -> dict:
     seq_ms, seq_events, seq_launch = 0.0, 0, {}
     n_seq = n_inst if args.seq_instances <= 0 else min(args.seq_instances, n_inst)
     for b in range(n_seq):
-        one = mc.Network(w.instance(b))
+        one = mc.Network(w.instance(b), device_connect=True)
         ms, ev, _, _, _ = timed_run(one, steps, args.warmup, args.seq_launch, args.tune_steps)
         seq_ms += ms
         seq_events += ev

@@ -145,8 +145,8 @@ typedef struct mc_launch {
   int32_t block;                 /* threads per workgroup: 64..1024, multiple of 64 */
   int32_t neurons_per_wg;        /* neurons updated by one workgroup: multiple of 4, <= 4*block, <= 1024
                                     (persistent: <= block; target owner: the targets of one delivery block,
-                                    its update kernel takes one quad per thread; buckets: <= min(2048,
-                                    6*block)); 0: automatic */
+                                    its update kernel takes one quad per thread; buckets: <= min(4092,
+                                    64*block)); 0: automatic */
   int32_t steps_per_graph;       /* steps captured per graph replay / per persistent launch (>= 1) */
   int32_t rows_per_wave;         /* step kernels' delivery: 0 = all threads of a workgroup walk each
                                     spiking row in turn; 1 = each wavefront walks whole rows (short rows);
@@ -186,14 +186,16 @@ enum { MC_ADJ_INPUT_AUTO = 0, MC_ADJ_INPUT_RECORD = 1, MC_ADJ_INPUT_REPLAY = 2 }
 int mc_build_network(const mc_config* cfg, mc_net** out);
 
 /* Advances the network by `steps` grid steps (update, then deliver, per
- * step), recording every spike.  Asynchronous on the network's stream;
+ * step: the simulation cycle of the Fig. 1 caption; the Methods time such a
+ * call over T_model after a presimulation), recording every spike.  Asynchronous on the network's stream;
  * getters synchronize.  Resumable: consecutive calls continue the same
  * trajectory bit for bit.  Errors: STATE (host-only or failed handle), HIP,
  * OOM (raster growth). */
 int mc_simulate(mc_net* net, int64_t steps);
 
-/* Copies the recorded spikes with step in [step_begin, step_end) into
- * caller-owned host arrays, sorted by step, then neuron id.  If more than
+/* Copies the recorded spikes (the raster of Supplementary Fig. 1) with step
+ * in [step_begin, step_end) into caller-owned host arrays, sorted by step,
+ * then neuron id.  If more than
  * `capacity` spikes fall in the range, writes nothing, sets *count_out to the
  * number required and returns BUFFER_TOO_SMALL. */
 int mc_get_spikes(mc_net* net, int64_t step_begin, int64_t step_end,
@@ -235,10 +237,13 @@ int mc_get_sizes(mc_net* net, int64_t* n_neurons, int64_t* n_synapses, int32_t* 
 int mc_get_instance_offsets(mc_net* net, int64_t* off_host /* [n_instances+1] */);
 /* Population offsets of instance b in global ids: [n_pops+1]. */
 int mc_get_pop_offsets(mc_net* net, int32_t instance, int64_t* off_host);
-/* The synapse store in canonical order: rows by source id, ascending target
- * inside a row (multapses in draw order).  row_ptr [N+1], tgt/w_q/dly [M]. */
+/* The explicit synapse store (Discussion: every synapse's weight stored) in
+ * canonical order: rows by source id, ascending target inside a row
+ * (multapses in draw order).  row_ptr [N+1], tgt/w_q/dly [M]. */
 int mc_get_synapses(mc_net* net, int64_t* row_ptr_host, int32_t* tgt_host, int32_t* w_q_host, uint8_t* dly_host);
-/* State after the last simulated step: y = V - E_L (mV), I (pA), refractory steps left. */
+/* State of the leaky integrate-and-fire neurons with exponential currents
+ * (Supplementary Fig. 1 caption) after the last simulated step: y = V - E_L
+ * (mV), I (pA), refractory steps left.  set: replaces it (r in [0, 255]). */
 int mc_get_state(mc_net* net, double* y_host, double* i_host, int32_t* r_host);
 int mc_set_state(mc_net* net, const double* y_host, const double* i_host, const int32_t* r_host);
 /* Logical input ring: pending[k*N + i] = integer input (2^-16 pA) neuron i
@@ -246,12 +251,18 @@ int mc_set_state(mc_net* net, const double* y_host, const double* i_host, const 
 int mc_get_ring(mc_net* net, int64_t depth, int64_t* pending_host);
 /* Adds `value` (2^-16 pA) to the input neuron i reads at step current+k. */
 int mc_inject(mc_net* net, int64_t k, int64_t neuron, int64_t value);
-/* Propagators P11, P21, P22, P20 of the exact integration step. */
+/* Propagators P11, P21, P22, P20 of the exact integration step of h
+ * (Supplementary Fig. 1 caption: h = 0.1 ms, tau_m, tau_syn). */
 int mc_get_propagators(mc_net* net, double* p_host /* [4] */);
-/* Poisson inverse-CDF tables [n_pops][64] of instance 0 (tables are the same for every instance). */
+/* Poisson inverse-CDF tables [n_pops][64] of the external drive, instance 0
+ * (the tables are the same for every instance). */
 int mc_get_drive_tables(mc_net* net, uint64_t* t_host);
+/* Step, spikes and synaptic events (Methods: transmitted spikes, the
+ * denominator of the energy per synaptic event) since the build. */
 int mc_get_counters(mc_net* net, mc_counters* out);
-/* Launch configuration; a change never changes results (integer sums).  A
+/* Launch configuration of the cycle (how its update and delivery map onto
+ * the GPU; the paper's counterpart is the thread placement of its Results);
+ * a change never changes results (integer sums).  A
  * shape the device cannot run (RANGE, INVALID_ARG) leaves the current one;
  * a failure while the new shape's tables are built (OOM, HIP) marks the
  * handle failed. */
@@ -260,8 +271,9 @@ int mc_get_launch(mc_net* net, mc_launch* l);
 /* Times candidate launch configurations on copies of the current state for
  * `steps` steps each, keeps the fastest (state and raster are restored).
  * If the environment variable MC_TUNE_CACHE names a file, the choice is
- * kept there keyed by the network's shape (neurons, synapses, instance and
- * population sizes, largest delay and row) and the device (name and compute
+ * kept there keyed by the network's shape (neurons, instance and population
+ * sizes, and the synapse count to an eighth of an octave, so that networks
+ * drawn with other seeds share the key) and the device (name and compute
  * units); a later call for the same key applies the stored choice without
  * timing anything.  *best_out: the launch chosen. */
 int mc_tune(mc_net* net, int64_t steps, mc_launch* best_out);
@@ -269,8 +281,10 @@ int mc_tune(mc_net* net, int64_t steps, mc_launch* best_out);
  * workgroup and steps of pending input held in LDS (the bucket scheme: 0
  * steps; all 0 under the step kernels). */
 int mc_get_persist_shape(mc_net* net, int32_t* workgroups_out, int32_t* targets_per_wg_out, int32_t* lds_steps_out);
-/* Simulates `steps` steps with per-phase device timestamps (persistent
- * scheme only) and returns the mean time per step in microseconds, averaged
+/* The time per phase of the cycle (Fig. 1b splits the run time into update,
+ * deliver, communicate and other): simulates `steps` steps with per-phase
+ * device timestamps (persistent scheme only) and returns the mean time per
+ * step in microseconds, averaged
  * over workgroups: us_out[0] update, [1] compaction+publication, [2] wait
  * for every workgroup's spikes, [3] spike-list gather, [4] delay-1
  * delivery, [5] the sum of [0..4]; overlapping parts of [2]: [6] drive of
@@ -283,7 +297,7 @@ int mc_profile_phases(mc_net* net, int64_t steps, double* us_out_host);
  * wavefront 0, 6: polling of the first poller, 7: unused); *workgroups_out =
  * G (0 before any profile).  BUFFER_TOO_SMALL if capacity < 8*G. */
 int mc_get_phase_table(mc_net* net, double* out_host, int64_t capacity, int32_t* workgroups_out);
-/* Throughput form of the delivery: every synapse of every recorded spike
+/* Throughput form of the deliver phase (Fig. 1 caption): every synapse of every recorded spike
  * with step in [step_begin, step_end) (< current step) is delivered in ONE
  * launch into a scratch ring of S = step_end - step_begin + 101 slots with
  * device int64 atomics (slot k = input read at step step_begin + k).
@@ -336,7 +350,9 @@ int mc_last_adjoint_ms(mc_net* net, double* forward_ms_out, double* reverse_ms_o
  * (one spike per refractory period per neuron).  OOM leaves the room there
  * was, and the handle usable. */
 int mc_reserve(mc_net* net, int64_t steps);
-/* Full dynamic state (step, y, I, r, ring, counters) to/from a host blob. */
+/* Full dynamic state (step, y, I, r, ring, counters) to/from a host blob,
+ * so that a run can resume or restart from any step (a simulation resumes
+ * bit for bit; the Methods' presimulation is such a prefix). */
 int mc_save_state(mc_net* net, void* blob_host, size_t capacity, size_t* used_out);
 int mc_load_state(mc_net* net, const void* blob_host, size_t size);
 /* Replaces every weight by rint(w_pA_dev[k] * 2^16) (device array of

@@ -206,7 +206,7 @@ struct mc_net {
   // HIP events around every persistent-kernel launch of the latest
   // mc_simulate (pairs k, k+1; at most kLaunchEvents / 2 launches timed)
   std::vector<hipEvent_t> ev_launch;
-  std::vector<unsigned> dcdf;          // delay histogram of the store, cumulative, 32-bit (atomic probe)
+  std::vector<unsigned char> dq;       // 1024 quantiles of the store's delay histogram (atomic probe)
   int launches_timed = 0;
   int64_t steps_timed = 0;
   hipStream_t aux = nullptr;           // read-back of the raster beside the simulation stream
@@ -240,6 +240,7 @@ struct mc_net {
   BucketArgs bucket() const {
     BucketArgs a{};
     a.G = own_blocks; a.B = wg_neurons;
+    a.Q = (wg_neurons + 4 * launch.block - 1) / (4 * launch.block);
     a.bt0 = d_bt0; a.binst = d_binst; a.blb = d_blb; a.ifb = d_ifb; a.boff = d_boff; a.blk2 = d_blk2;
     a.flags = d_flags; a.pub = d_pub; a.bk = d_bk; a.cap = bk_cap;
     a.wait_ticks = (long long)wall_khz * 1000 * kWaitSeconds;
@@ -298,8 +299,8 @@ int release_recording(mc_net* n) {
 void release_all(mc_net* n) {
   if (n->graph) { (void)hipGraphExecDestroy(n->graph); n->graph = nullptr; }
   release_recording(n);
-  dev_free(n->alloc, n->d_blk); dev_free(n->alloc, n->d_flags); dev_free(n->alloc, n->d_pub); dev_free(n->alloc, n->d_phase); dev_free(n->alloc, n->d_nb);
-  dev_free(n->alloc, n->d_bk);
+  dev_free(n->alloc, n->d_blk); dev_free(n->alloc, n->d_flags); dev_free(n->alloc, n->d_pub); dev_free(n->alloc, n->d_phase);
+  dev_free(n->alloc, n->d_nb); dev_free(n->alloc, n->d_bk);
   dev_free(n->alloc, n->d_ne);
   dev_free(n->alloc, n->d_bstart);
   dev_free(n->alloc, n->d_qinst); dev_free(n->alloc, n->d_inst_base); dev_free(n->alloc, n->d_ilist); dev_free(n->alloc, n->d_icnt);
@@ -347,7 +348,10 @@ int drain(mc_net* n, hipEvent_t upto = nullptr) {
     return set_error(MC_ERR_TIMEOUT, "persistent kernel: a workgroup waited more than " + std::to_string(kWaitSeconds) +
                                          " s for the spike records of a step and the launch was abandoned");
   }
-  if (ovf) { n->failed = true; return set_error(MC_ERR_STATE, "raster segment overflow (internal capacity error)"); }
+  if (ovf & kErrRasterOverflow) {
+    n->failed = true;
+    return set_error(MC_ERR_STATE, "raster segment overflow (internal capacity error)");
+  }
   std::vector<long long> seg_off((size_t)n->n_wg + 1, 0);
   for (int g = 0; g < n->n_wg; ++g) seg_off[g + 1] = seg_off[g] + cnt[g];
   const long long total = seg_off[n->n_wg];
@@ -458,8 +462,8 @@ int validate_launch(const mc_net* n, const mc_launch& l) {
   if (l.scheme == MC_SCHEME_PERSISTENT_BUCKETS) {
     if (l.block < 64 || l.block > kBucketMaxBlock || l.block % 64)
       return set_error(MC_ERR_INVALID_ARG, "the bucket scheme runs 64..512 threads per workgroup");
-    if (l.neurons_per_wg < 0 || l.neurons_per_wg % 4 || l.neurons_per_wg > std::min(kBucketMaxB, 6 * l.block))
-      return set_error(MC_ERR_INVALID_ARG, "bucket scheme: neurons_per_wg must be a multiple of 4, <= min(2048, 6 x block)");
+    if (l.neurons_per_wg < 0 || l.neurons_per_wg % 4 || l.neurons_per_wg > std::min(kBucketMaxB, 64 * l.block))
+      return set_error(MC_ERR_INVALID_ARG, "bucket scheme: neurons_per_wg must be a multiple of 4, <= min(4092, 64 x block)");
     if (l.steps_per_graph < 0 || l.steps_per_graph > 100000) return set_error(MC_ERR_INVALID_ARG, "steps_per_graph out of [0, 100000]");
     if (l.rows_per_wave != 0 && l.rows_per_wave != 1) return set_error(MC_ERR_INVALID_ARG, "rows_per_wave must be 0 or 1");
     return MC_OK;
@@ -520,6 +524,7 @@ int persist_shape(mc_net* n, const mc_launch& l, int* G, int* B, int* DL, std::v
 // Blocks of at most `targets` targets (a multiple of 4) that every
 // instance's padded range is split into (no block spans two instances).
 int64_t owner_block_count(const mc_net* n, int targets) {
+  if (targets <= 0) return 0;
   int64_t G = 0;
   for (int b = 0; b < n->h.n_inst; ++b)
     G += std::max<int64_t>(1, (n->inst_off_pad[b + 1] - n->inst_off_pad[b] + targets - 1) / targets);
@@ -532,10 +537,14 @@ int64_t owner_block_count(const mc_net* n, int targets) {
 // per thread (the listing of a step with more spikes than the LDS list
 // holds sums two producers per thread).
 int bucket_shape(mc_net* n, const mc_launch& l, int* B_out) {
-  const int bmax = std::min(kBucketMaxB, 6 * l.block);
+  const int bmax = std::min(kBucketMaxB, 64 * l.block);   // at most 16 quads per thread
+  if (bucket_lds_bytes(bmax) > (size_t)n->lds_max && bucket_lds_bytes(4) > (size_t)n->lds_max)
+    return set_error(MC_ERR_RANGE, "bucket scheme: LDS too small");
+  HIP_TRY(bucket_set_lds_limit(std::min<size_t>((size_t)n->lds_max, bucket_lds_bytes(bmax))));
   auto fits = [&](int B, std::string* why) -> bool {
     int occ = 0;
-    if (bucket_occupancy(B, l.block, &occ) != hipSuccess) { (void)hipGetLastError(); occ = 0; }
+    if (bucket_lds_bytes(B) > (size_t)n->lds_max) occ = 0;
+    else if (bucket_occupancy(B, l.block, &occ) != hipSuccess) { (void)hipGetLastError(); occ = 0; }
     const int64_t G = owner_block_count(n, B);
     int64_t gmax = 0;
     for (int b = 0; b < n->h.n_inst; ++b)
@@ -552,7 +561,7 @@ int bucket_shape(mc_net* n, const mc_launch& l, int* B_out) {
   };
   std::string why;
   if (l.neurons_per_wg) {
-    if (l.neurons_per_wg > bmax) return set_error(MC_ERR_RANGE, "bucket scheme: at most min(2048, 6 x threads) targets per workgroup");
+    if (l.neurons_per_wg > bmax) return set_error(MC_ERR_RANGE, "bucket scheme: at most min(4092, 64 x threads) targets per workgroup");
     if (!fits(l.neurons_per_wg, &why)) return set_error(MC_ERR_RANGE, "bucket scheme: " + why);
     *B_out = l.neurons_per_wg;
     return MC_OK;
@@ -571,6 +580,7 @@ int bucket_shape(mc_net* n, const mc_launch& l, int* B_out) {
 // of at most `targets` targets, and each row's sub-row bounds for the blocks
 // of its own instance.
 int setup_owner(mc_net* n, int targets, int max_targets) {
+  if (targets < 4 || targets % 4) return set_error(MC_ERR_INVALID_ARG, "target blocks need a positive multiple of 4 targets");
   const int ni = n->h.n_inst;
   std::vector<int> bt0, binst, blb, ifb((size_t)ni);
   for (int b = 0; b < ni; ++b) {
@@ -621,7 +631,7 @@ int apply_launch(mc_net* n, const mc_launch& l) {
   if (rc != MC_OK) return rc;
   int qpw = 0, n_wg = 0, wg_neurons = 0, G = 0, B = 0, DL = 0;
   std::vector<int> bs;
-  if (l.scheme != MC_SCHEME_PERSISTENT_LDS) {
+  if (l.scheme == MC_SCHEME_STEP_KERNELS || l.scheme == MC_SCHEME_TARGET_OWNER) {
     // step kernels: neurons_per_wg / 4 quads per workgroup; target owner: one
     // quad per thread in the update kernel, neurons_per_wg sizes the delivery blocks
     qpw = l.scheme == MC_SCHEME_TARGET_OWNER ? std::min(l.block, kMaxQuadsPerWgHost) : l.neurons_per_wg / 4;
@@ -703,7 +713,9 @@ int apply_launch(mc_net* n, const mc_launch& l) {
     n->qpw = qpw;
     n->n_wg = n_wg;
     n->wg_neurons = wg_neurons;
-    n->pG = G; n->pB = B; n->pDL = DL;
+    // the LDS-window scheme's shape (its tables are rebuilt whenever it is set again)
+    const bool lds_scheme = l.scheme == MC_SCHEME_PERSISTENT_LDS;
+    n->pG = lds_scheme ? G : 0; n->pB = lds_scheme ? B : 0; n->pDL = lds_scheme ? DL : 0;
     n->launch = l;
     guard.armed = false;   // setup_recording keeps the handle usable on its own failures where it can
     if ((rc = setup_recording(n, std::max<int64_t>(n->cap_steps, 4096))) != MC_OK) return rc;
@@ -1230,7 +1242,8 @@ static int update_weights(mc_net* n, const void* src, int mode, double eta) {
   if (bad) return set_error(MC_ERR_RANGE, "a new weight is not finite or does not fit int32 in units of 2^-16 pA "
                                           "(|w| < 32768 pA); the store is unchanged");
   HIP_TRY(launch_weights(n->d_wq, src, mode, eta, n->h.M, n->d_wbad, false, n->stream));
-  if (n->d_ne)
+  if (n->launch.scheme == MC_SCHEME_PERSISTENT_LDS && n->pG > 0 && n->d_ne)
+    // the near table holds copies of the delay-1/2 weights
     HIP_TRY(launch_near_fill(n->d_tgt, n->d_wq, n->d_dly, n->d_blk, n->d_bstart, n->n_pad, n->pG, n->d_nb, n->d_ne,
                              n->stream));
   HIP_TRY(hipStreamSynchronize(n->stream));
@@ -1295,7 +1308,17 @@ int mc_load_state(mc_net* n, const void* blob, size_t size) {
   HIP_TRY(hipMemcpy(n->d_I, o, sizeof(double) * P, hipMemcpyHostToDevice)); o += sizeof(double) * P;
   HIP_TRY(hipMemcpy(n->d_r, o, sizeof(int32_t) * P, hipMemcpyHostToDevice)); o += sizeof(int32_t) * P;
   HIP_TRY(hipMemcpy(n->d_ring, o, sizeof(long long) * kRingSlots * n->ring_stride, hipMemcpyHostToDevice));
-  n->horizon = kRingSlots - 1;         // a loaded ring may hold input anywhere
+  // horizon: one past the last slot ahead of the restored step that holds input
+  {
+    const long long* ring = reinterpret_cast<const long long*>(o);
+    int hz = 1;
+    for (int m = kRingSlots - 2; m >= 1 && hz == 1; --m) {
+      const long long* slot = ring + (size_t)((hd.step + m) & kRingMask) * n->ring_stride;
+      for (int64_t k = 0; k < n->ring_stride; ++k)
+        if (slot[k] != 0) { hz = m + 1; break; }
+    }
+    n->horizon = std::max(hz, std::max(1, n->h.max_delay));
+  }
   long long st = hd.step;
   HIP_TRY(hipMemcpy(n->d_step, &st, sizeof(long long), hipMemcpyHostToDevice));
   n->step = hd.step;
@@ -1463,41 +1486,42 @@ int mc_probe_atomics(mc_net* n, int64_t slots, int32_t pattern, double* gops) {
   if (!device_ready(n) || !gops) return set_error(MC_ERR_INVALID_ARG, "bad handle or NULL");
   if (slots < 1 || slots > 100000) return set_error(MC_ERR_INVALID_ARG, "slots out of [1, 1e5]");
   if (pattern != 0 && pattern != 1) return set_error(MC_ERR_INVALID_ARG, "pattern must be 0 or 1");
-  // the store's delay histogram as a 32-bit cumulative table, and its mean out-degree
-  if (n->dcdf.empty()) {
+  // 1024 quantiles of the store's delay histogram, and its mean out-degree
+  if (n->dq.empty()) {
     std::vector<int64_t> hist(kRingSlots, 0);
     for (uint8_t d : n->h.dly) hist[d]++;
-    n->dcdf.assign(kRingSlots, 0xFFFFFFFFu);
-    int64_t cum = 0;
+    n->dq.assign(1024, 1);
     const double M = (double)std::max<int64_t>(1, n->h.M);
-    for (int d = 0; d < kRingSlots; ++d) {
-      cum += hist[d];
-      const double c = std::floor((double)cum / M * 4294967296.0);
-      n->dcdf[d] = c >= 4294967295.0 ? 0xFFFFFFFFu : (unsigned)c;
+    int64_t cum = 0;
+    int d = 0;
+    for (int k = 0; k < 1024; ++k) {
+      const double q = (k + 0.5) / 1024.0 * M;
+      while (d < kRingSlots - 1 && (double)(cum + hist[d]) <= q) cum += hist[d++];
+      n->dq[k] = (unsigned char)std::max(1, d);
     }
   }
   const double deg = (double)n->h.M / (double)std::max<int64_t>(1, n->h.N);
   const int gap = (int)std::max(1.0, std::min(1e6, std::round((double)n->h.N / std::max(1.0, deg))));
   unsigned long long* t = nullptr;
-  unsigned* dcdf = nullptr;
+  unsigned char* dq = nullptr;
   int rc = dev_alloc(n->alloc, &t, (size_t)slots * n->ring_stride);
   if (rc != MC_OK) return rc;
-  if ((rc = dev_alloc(n->alloc, &dcdf, kRingSlots)) != MC_OK) { dev_free(n->alloc, t); return rc; }
+  if ((rc = dev_alloc(n->alloc, &dq, 1024)) != MC_OK) { dev_free(n->alloc, t); return rc; }
   const int grid = n->n_cu * 8;
   const long long items = 1 << 19;            // 2^27 events per launch
-  hipError_t err = hipMemcpy(dcdf, n->dcdf.data(), sizeof(unsigned) * kRingSlots, hipMemcpyHostToDevice);
+  hipError_t err = hipMemcpy(dq, n->dq.data(), 1024, hipMemcpyHostToDevice);
   if (err == hipSuccess) err = hipMemsetAsync(t, 0, sizeof(unsigned long long) * slots * n->ring_stride, n->stream);
   if (err == hipSuccess)
-    err = launch_atomic_slots(t, slots, n->ring_stride, n->n_pad, items, pattern, gap, dcdf, grid, n->stream);
+    err = launch_atomic_slots(t, slots, n->ring_stride, n->n_pad, items, pattern, gap, dq, grid, n->stream);
   if (err == hipSuccess) err = hipEventRecord(n->ev0, n->stream);
   if (err == hipSuccess)
-    err = launch_atomic_slots(t, slots, n->ring_stride, n->n_pad, items, pattern, gap, dcdf, grid, n->stream);
+    err = launch_atomic_slots(t, slots, n->ring_stride, n->n_pad, items, pattern, gap, dq, grid, n->stream);
   if (err == hipSuccess) err = hipEventRecord(n->ev1, n->stream);
   if (err == hipSuccess) err = hipEventSynchronize(n->ev1);
   float ms = 0;
   if (err == hipSuccess) err = hipEventElapsedTime(&ms, n->ev0, n->ev1);
   dev_free(n->alloc, t);
-  dev_free(n->alloc, dcdf);
+  dev_free(n->alloc, dq);
   if (err != hipSuccess) return set_error(MC_ERR_HIP, std::string("atomic probe: ") + hipGetErrorString(err));
   *gops = (double)items * 256.0 / (ms * 1e-3) / 1e9;
   return MC_OK;
@@ -1538,9 +1562,11 @@ static std::string tune_key(mc_net* n) {
   auto mix = [&](uint64_t v) {
     for (int k = 0; k < 8; ++k) { h ^= (v >> (8 * k)) & 0xFFu; h *= 1099511628211ULL; }
   };
-  mix((uint64_t)n->h.N); mix((uint64_t)n->h.M); mix((uint64_t)n->h.n_inst); mix((uint64_t)n->h.n_pops);
+  // sizes, and the synapse count to an eighth of an octave (about 9 %), so
+  // that networks drawn with other seeds share the entry
+  mix((uint64_t)n->h.N); mix((uint64_t)n->h.n_inst); mix((uint64_t)n->h.n_pops);
   for (int64_t v : n->h.pop_off) mix((uint64_t)v);
-  mix((uint64_t)n->h.max_delay); mix((uint64_t)n->h.max_row);
+  mix((uint64_t)std::llround(8.0 * std::log2((double)std::max<int64_t>(n->h.M, 1))));
   hipDeviceProp_t prop;
   std::string dev = "unknown";
   if (hipGetDeviceProperties(&prop, n->device) == hipSuccess) {

@@ -3,7 +3,8 @@
 // target-owner delivery into per-workgroup delay buckets.
 //
 // Every workgroup owns a block of at most B target neurons of one instance
-// (T consecutive targets per thread) and exchanges spike records only with
+// (Q consecutive quads per thread; the state in LDS) and exchanges spike
+// records only with
 // the workgroups of its own instance: instances never interact, so a batch
 // runs as independent groups inside one launch and a slow instance delays
 // only itself.
@@ -15,7 +16,8 @@
 // step for the batch's ~1.1e6 events).  Instead, the events of a step are
 // appended to buckets of the owner workgroup, one bucket per arrival step
 // (step mod 128): an LDS counter gives the position, the entry (local
-// target, weight) is stored to global memory.  When the arrival step comes,
+// target, weight) is stored to global memory with a plain (workgroup-scope)
+// store, so the L2 gathers a bucket's entries into whole lines.  When the arrival step comes,
 // the owner reads its bucket back (one coalesced pass) and sums it in LDS
 // with LDS atomics.  The events' global traffic becomes a streaming write
 // and a streaming read of 8 bytes each.  The sums are integer sums, so the
@@ -35,7 +37,7 @@
 //   4. every event of step n's spikes that lands in this block goes into the
 //      bucket of its arrival step.
 // Spike records: four per workgroup (step mod 4).  Word 0 = tag16 << 48 |
-// count << 36 | the block-local indices (11 bits each) of the first three
+// count << 36 | the block-local indices (12 bits each) of the first three
 // spikes; words 1..3 = (step + 1) << 32 | id of spikes 4..6; later ids in a
 // side array written before word 0.  The last workgroup to finish a launch
 // clears every record, so a tag needs to carry only the step.
@@ -49,7 +51,7 @@ namespace mc {
 
 namespace {
 
-constexpr int kBW0Ids = 3;              // ids in word 0 (11-bit block-local indices)
+constexpr int kBW0Ids = 3;              // ids in word 0 (12-bit block-local indices)
 constexpr int kBInline = kBW0Ids + 3;   // ids carried by a record
 constexpr int kBListCap = 1024;         // spikes of one step listed in LDS (more: chunked, from the records)
 constexpr int kBBigCap = 64;            // producers with more than kBInline spikes listed per step
@@ -63,6 +65,15 @@ __device__ __forceinline__ T bld(const T* p) {
 template <class T>
 __device__ __forceinline__ void bst(T* p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Bucket entries are written and read back by the same workgroup only (the
+// barriers between order them), so workgroup scope suffices: plain cached
+// accesses, which the L2 merges into whole lines.
+__device__ __forceinline__ unsigned long long wld(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void wst(unsigned long long* p, unsigned long long v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 __device__ __forceinline__ int bpoisson(const uint64_t* T, uint32_t u) {
@@ -90,8 +101,14 @@ __device__ __forceinline__ int bscan(int v, int* s_tmp, int* total) {
 
 }  // namespace
 
-// LDS (dynamic): s_x[B] i64 (input sums of the step being absorbed)
-template <int T>
+__host__ __device__ size_t bucket_sum_slots(int B) {
+  return (size_t)B > ((size_t)kBucketMaxProducers + 2) / 2 ? (size_t)B : ((size_t)kBucketMaxProducers + 2) / 2;
+}
+
+// LDS (dynamic): s_x[BX] i64 (input sums of the step being absorbed; BX =
+// max(B, room for the fallback's producer prefix)) | s_y[B] f64 | s_I[B] f64
+// | s_r[B] i32 | s_kd[B] u8 (Poisson count of the step) | s_pop[B] u8.  The
+// neuron state lives in LDS, so registers do not bound the block size.
 __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs a, int steps) {
   extern __shared__ __align__(16) unsigned char s_raw[];
   __shared__ uint64_t s_table[kMaxPops * kTableLen];
@@ -105,7 +122,14 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
   __shared__ int s_nids, s_nbig, s_abort, s_last;
   __shared__ unsigned long long s_events;
   __shared__ unsigned long long s_popcnt[kMaxPops];
+  const int B = a.B;
+  const size_t bx = bucket_sum_slots(B);
   long long* s_x = reinterpret_cast<long long*>(s_raw);
+  double* s_y = reinterpret_cast<double*>(s_x + bx);
+  double* s_I = s_y + B;
+  int* s_r = reinterpret_cast<int*>(s_I + B);
+  unsigned char* s_kd = reinterpret_cast<unsigned char*>(s_r + B);
+  unsigned char* s_pop = s_kd + B;
 
   const int g = blockIdx.x, tid = threadIdx.x, nthr = blockDim.x;
   const int lane = tid & 63, wave = tid >> 6, nw = nthr >> 6;
@@ -118,50 +142,33 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
   unsigned long long* bk = a.bk + (size_t)g * kRingSlots * a.cap;
 
   for (int k = tid; k < p.n_pops * kTableLen; k += nthr) s_table[k] = p.table[k];
-  for (int k = tid; k < a.B; k += nthr) s_x[k] = 0;
+  for (int k = tid; k < (int)bx; k += nthr) s_x[k] = 0;
   for (int k = tid; k < kRingSlots; k += nthr) s_bcnt[k] = 0;
   if (tid < kRingSlots / 32) s_dirty[tid] = 0;
   for (int k = tid; k < kBucketMaxProducers; k += nthr) s_cnt[k] = 0;
   if (tid == 0) { s_abort = 0; s_events = 0; }
   if (tid < kMaxPops) s_popcnt[tid] = 0;
+  for (int jl = tid; jl < Bg; jl += nthr) {
+    const long long j = j0 + jl;
+    s_y[jl] = p.y[j]; s_I[jl] = p.I[j]; s_r[jl] = p.r[j];
+    s_pop[jl] = (unsigned char)((p.qpops[j >> 2] >> (8 * (j & 3))) & 0xFFu);
+    s_kd[jl] = 0;
+  }
   __syncthreads();
 
-  // thread t owns targets j0 + t*T .. j0 + t*T + T-1 (those < Bg)
-  // population (0xFF: none) and Poisson count of target k in byte k & 3 of word k >> 2
-  constexpr int TW = (T + 3) / 4;
-  const int jt = tid * T;
-  double y[T], I[T];
-  int r[T];
-  unsigned popw[TW], kdw[TW];
+  // thread t owns the a.Q quads from local target 4 t Q on (those < Bg):
+  // ascending ids follow the thread order, and each quad takes one Philox block
+  const int lt0 = min(4 * tid * a.Q, Bg), lt1 = min(lt0 + 4 * a.Q, Bg);
+  auto drive = [&](long long m) {                // Poisson counts of my targets at step m
+    for (int q4 = lt0; q4 < lt1; q4 += 4) {
+      const long long q = (j0 + q4) >> 2;
+      const U64x4 v = philox4x64_10((uint64_t)m, (uint64_t)p.qlocal[q], 0, kTagDrive, p.qseed[q], 0);
 #pragma unroll
-  for (int w = 0; w < TW; ++w) { popw[w] = 0xFFFFFFFFu; kdw[w] = 0; }
-  auto pop_of = [&](int k) -> unsigned { return (popw[k >> 2] >> (8 * (k & 3))) & 0xFFu; };
-#pragma unroll
-  for (int k = 0; k < T; ++k) {
-    y[k] = 0.0; I[k] = 0.0; r[k] = 0;
-    if (jt + k < Bg) {
-      const long long j = j0 + jt + k;
-      const unsigned pk = (p.qpops[j >> 2] >> (8 * (j & 3))) & 0xFFu;
-      popw[k >> 2] = (popw[k >> 2] & ~(0xFFu << (8 * (k & 3)))) | (pk << (8 * (k & 3)));
-      y[k] = p.y[j]; I[k] = p.I[j]; r[k] = p.r[j];
-    }
-  }
-  // Poisson counts of my targets at step m (one Philox block per quad)
-  auto drive = [&](long long m) {
-    U64x4 v{0, 0, 0, 0};
-#pragma unroll
-    for (int w = 0; w < TW; ++w) kdw[w] = 0;
-#pragma unroll
-    for (int k = 0; k < T; ++k) {
-      if (jt + k >= Bg) continue;
-      const long long j = j0 + jt + k;
-      if (k == 0 || (j & 3) == 0) {              // one block per quad, shared by the quad's targets
-        const long long q = j >> 2;
-        v = philox4x64_10((uint64_t)m, (uint64_t)p.qlocal[q], 0, kTagDrive, p.qseed[q], 0);
+      for (int k = 0; k < 4; ++k) {
+        const int jl = q4 + k;
+        const unsigned pk = s_pop[jl];
+        s_kd[jl] = (pk == 0xFFu) ? 0 : (unsigned char)bpoisson(s_table + pk * kTableLen, hi32(pick(v, (unsigned)k)));
       }
-      const unsigned pk = pop_of(k);
-      if (pk != 0xFFu)
-        kdw[k >> 2] |= (unsigned)bpoisson(s_table + pk * kTableLen, hi32(pick(v, (unsigned)(j & 3)))) << (8 * (k & 3));
     }
   };
   long long rcnt = p.raster_cnt[g];
@@ -175,65 +182,61 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
 
-  auto decide = [&](long long m) -> unsigned {   // spike decision of step m: bit k = target k spiked
+  auto decide = [&](long long m) -> uint64_t {   // spike decision of step m: bit k = local target lt0 + k spiked
     if (p.ck_y) {
       if (ck_phase == 0 && ck_seg >= 0 && ck_seg < p.ck_count) {
-#pragma unroll
-        for (int k = 0; k < T; ++k)
-          if (jt + k < Bg) {
-            const size_t at = (size_t)ck_seg * p.ring_stride + j0 + jt + k;
-            p.ck_y[at] = y[k]; p.ck_I[at] = I[k]; p.ck_r[at] = r[k];
-          }
+        for (int jl = lt0; jl < lt1; ++jl) {
+          const size_t at = (size_t)ck_seg * p.ring_stride + j0 + jl;
+          p.ck_y[at] = s_y[jl]; p.ck_I[at] = s_I[jl]; p.ck_r[at] = s_r[jl];
+        }
       }
       if (++ck_phase == p.ck_every) { ck_phase = 0; ++ck_seg; }
     }
-    unsigned mask = 0;
-#pragma unroll
-    for (int k = 0; k < T; ++k) {
-      const unsigned pk = pop_of(k);
+    uint64_t mask = 0;
+    for (int jl = lt0; jl < lt1; ++jl) {
+      const unsigned pk = s_pop[jl];
       if (pk == 0xFFu) continue;
-      const bool free_ = (r[k] == 0);
+      const int r = s_r[jl];
+      const bool free_ = (r == 0);
+      double y = s_y[jl];
       if (free_) {
-        double yn = p.P22 * y[k] + p.P21 * I[k];
+        double yn = p.P22 * y + p.P21 * s_I[jl];
         if (p.i_e != 0.0) yn = yn + p.P20 * p.i_e;
-        y[k] = yn;
-      } else {
-        r[k] = r[k] - 1;
+        y = yn;
       }
-      if (free_ && y[k] >= p.theta) {
-        y[k] = p.y_reset;
-        r[k] = p.ref_steps;
-        mask |= 1u << k;
+      if (free_ && y >= p.theta) {
+        s_y[jl] = p.y_reset;
+        s_r[jl] = p.ref_steps;
+        mask |= 1ull << (jl - lt0);
         atomicAdd(&s_popcnt[pk], 1ull);
+      } else {
+        s_y[jl] = y;
+        if (!free_) s_r[jl] = r - 1;
       }
     }
     return mask;
   };
-  auto publish = [&](long long m, unsigned mask) {   // compaction (ascending ids), record of step m, raster
+  auto publish = [&](long long m, uint64_t mask) {   // compaction (ascending ids), record of step m, raster
     int nloc;
-    const int c = __popc(mask);
-    const int pre = bscan(c, s_tmp[0], &nloc);
+    const int pre = bscan(__popcll(mask), s_tmp[0], &nloc);
     const unsigned long long tag = (unsigned long long)(m + 1) << 32;
     const unsigned long long tag16 = (unsigned long long)((m + 1) % 65535 + 1) << 48;
     const size_t rec = (size_t)g * kRecSlots + (size_t)(m % kRecSlots);
     unsigned long long* myrec = a.flags + rec * kPersistFlagStride;
     const bool fits = rcnt + nloc <= p.raster_cap;
     int pos = pre;
-#pragma unroll
-    for (int k = 0; k < T; ++k) {
-      if (!((mask >> k) & 1u)) continue;
-      const int id = (int)(j0 + jt + k);
+    for (uint64_t mm = mask; mm; mm &= mm - 1, ++pos) {
+      const int id = (int)(j0 + lt0 + __builtin_ctzll(mm));
       if (pos < kBInline) s_first[pos] = id;
-      else bst(&a.pub[rec * a.B + pos], id);
+      else bst(&a.pub[rec * B + pos], id);
       if (fits) p.raster[(size_t)g * p.raster_cap + rcnt + pos] = make_int2((int)m, id);
-      ++pos;
     }
     if (nloc > kBInline) __builtin_amdgcn_s_waitcnt(0);   // side-array ids complete before word 0
     __syncthreads();
     if (tid >= kBW0Ids && tid < min(nloc, kBInline)) bst(&myrec[1 + tid - kBW0Ids], tag | (unsigned)s_first[tid]);
     if (tid == 0) {
-      unsigned long long w = tag16 | (unsigned long long)min(nloc, 4095) << 36;
-      for (int k = 0; k < min(nloc, kBW0Ids); ++k) w |= (unsigned long long)(s_first[k] - j0) << (11 * k);
+      unsigned long long w = tag16 | (unsigned long long)nloc << 36;
+      for (int k = 0; k < min(nloc, kBW0Ids); ++k) w |= (unsigned long long)(s_first[k] - j0) << (12 * k);
       bst(&myrec[0], w);
     }
     if (fits) rcnt += nloc;
@@ -242,9 +245,9 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
   // id k of producer h's record of step n (after its record has been accepted)
   auto rec_id = [&](int h, size_t rslot, int k) -> int {
     const unsigned long long* rec = a.flags + ((size_t)h * kRecSlots + rslot) * kPersistFlagStride;
-    if (k < kBW0Ids) return a.bt0[h] + (int)((bld(&rec[0]) >> (11 * k)) & 0x7FFu);
+    if (k < kBW0Ids) return a.bt0[h] + (int)((bld(&rec[0]) >> (12 * k)) & 0xFFFu);
     if (k < kBInline) return (int)(bld(&rec[1 + k - kBW0Ids]) & 0xFFFFFFFFu);
-    return bld(&a.pub[((size_t)h * kRecSlots + rslot) * a.B + k]);
+    return bld(&a.pub[((size_t)h * kRecSlots + rslot) * B + k]);
   };
   // one wavefront appends the events of spikes ids[k0..k1) of step ns that
   // land in this block to the buckets of their arrival steps
@@ -295,8 +298,7 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
           const int slot = (int)((ns + dd[u]) & kRingMask);
           const int at = atomicAdd(&s_bcnt[slot], 1);
           if (at < a.cap) {
-            bst(&bk[(size_t)slot * a.cap + at],
-                (unsigned long long)(unsigned)(tt[u] - j0) << 32 | (unsigned)ww[u]);
+            wst(&bk[(size_t)slot * a.cap + at], (unsigned long long)(unsigned)(tt[u] - j0) << 32 | (unsigned)ww[u]);
           } else {   // full bucket: the ring slot, read by the owner at that step
             atomicAdd(reinterpret_cast<unsigned long long*>(p.ring + (size_t)slot * p.ring_stride + tt[u]),
                       (unsigned long long)(long long)ww[u]);
@@ -308,7 +310,7 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
     *ev_out += ev;
   };
 
-  unsigned mask = 0;
+  uint64_t mask = 0;
   if (steps > 0) {
     mask = decide(n0);
     publish(n0, mask);
@@ -322,7 +324,7 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
       const int cnt = min(s_bcnt[slot], a.cap);
       const unsigned long long* bq = bk + (size_t)slot * a.cap;
       for (int e = tid; e < cnt; e += nthr) {
-        const unsigned long long v = bld(&bq[e]);
+        const unsigned long long v = wld(&bq[e]);
         atomicAdd(reinterpret_cast<unsigned long long*>(&s_x[v >> 32]), (unsigned long long)(long long)(int)(v & 0xFFFFFFFFu));
       }
     }
@@ -334,10 +336,7 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
       s_nids = 0;
       s_nbig = 0;
     }
-#pragma unroll
-    for (int k = 0; k < T; ++k) {
-      const int jl = jt + k;
-      if (jl >= Bg) continue;
+    for (int jl = lt0; jl < lt1; ++jl) {
       long long x_int = s_x[jl];
       s_x[jl] = 0;
       if (read_ring) {
@@ -345,11 +344,11 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
         const long long v = bld(e);
         if (v != 0) { bst(e, 0ll); x_int += v; }
       }
-      const unsigned pk = pop_of(k);
-      if (pk != 0xFFu) x_int += (long long)((kdw[k >> 2] >> (8 * (k & 3))) & 0xFFu) * p.jext_q;
+      const unsigned pk = s_pop[jl];
+      if (pk != 0xFFu) x_int += (long long)s_kd[jl] * p.jext_q;
       if (p.xrec && n - p.xrec_step0 >= 0 && n - p.xrec_step0 < p.xrec_steps)
         p.xrec[(size_t)(n - p.xrec_step0) * p.ring_stride + j0 + jl] = x_int;
-      if (pk != 0xFFu) I[k] = p.P11 * I[k] + (double)x_int * 0x1p-16;
+      if (pk != 0xFFu) s_I[jl] = p.P11 * s_I[jl] + (double)x_int * 0x1p-16;
     }
     // ---- 2. spike decision and record of step n+1 ---------------------------
     mask = 0;
@@ -365,7 +364,8 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
     const unsigned long long tag = (unsigned long long)(n + 1) << 32;
     const unsigned long long tag16 = (unsigned long long)((n + 1) % 65535 + 1) << 48;
     if (wave == nw - 1) {
-      const long long t_poll = wall_clock64();
+      long long t_poll = 0;          // the wall clock is read every 256 rounds only
+      unsigned spins = 0;
       unsigned todo = 0;
 #pragma unroll
       for (int rr = 0; rr < kBPollPerLane; ++rr)
@@ -399,7 +399,7 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
             const int hb = a.bt0[h];
             for (int k = 0; k < min(c, kBInline); ++k) {
               if (o + k >= kBListCap) break;
-              s_ids[o + k] = (k < kBW0Ids) ? hb + (int)((w0[rr] >> (11 * k)) & 0x7FFu)
+              s_ids[o + k] = (k < kBW0Ids) ? hb + (int)((w0[rr] >> (12 * k)) & 0xFFFu)
                                            : (int)(wk[k - kBW0Ids] & 0xFFFFFFFFu);
             }
             if (c > kBInline) {
@@ -411,7 +411,7 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
         }
         if (!todo) break;
         __builtin_amdgcn_s_sleep(1);
-        if (wall_clock64() - t_poll > a.wait_ticks) {
+        if ((++spins & 255u) == 0u && (t_poll == 0 ? ((t_poll = wall_clock64()), false) : wall_clock64() - t_poll > a.wait_ticks)) {
           atomicOr(p.overflow, 2u);
           s_abort = 1;
 #pragma unroll
@@ -432,7 +432,7 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
       if (nbig > 0) {
         for (int e = 0; e < nbig; ++e) {
           const int h = s_big[e].x, o = s_big[e].y, c = s_cnt[h - gi0];
-          for (int k = kBInline + tid; k < c; k += nthr) s_ids[o + k] = bld(&a.pub[((size_t)h * kRecSlots + rslot) * a.B + k]);
+          for (int k = kBInline + tid; k < c; k += nthr) s_ids[o + k] = bld(&a.pub[((size_t)h * kRecSlots + rslot) * B + k]);
         }
         __syncthreads();
       }
@@ -470,9 +470,7 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
     __syncthreads();
   }
   // ---- epilogue: state, counters; pending buckets summed into the ring -----
-#pragma unroll
-  for (int k = 0; k < T; ++k)
-    if (jt + k < Bg) { const long long j = j0 + jt + k; p.y[j] = y[k]; p.I[j] = I[k]; p.r[j] = r[k]; }
+  for (int jl = tid; jl < Bg; jl += nthr) { const long long j = j0 + jl; p.y[j] = s_y[jl]; p.I[j] = s_I[jl]; p.r[j] = s_r[jl]; }
   if (tid < p.n_pops) p.wg_spikes[(size_t)g * p.n_pops + tid] += s_popcnt[tid];
   if (tid == 0) {
     p.raster_cnt[g] = rcnt;
@@ -483,7 +481,7 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
     if (cnt == 0) continue;                      // uniform: every thread reads the same count
     const unsigned long long* bq = bk + (size_t)sl * a.cap;
     for (int e = tid; e < cnt; e += nthr) {
-      const unsigned long long v = bld(&bq[e]);
+      const unsigned long long v = wld(&bq[e]);
       atomicAdd(reinterpret_cast<unsigned long long*>(&s_x[v >> 32]), (unsigned long long)(long long)(int)(v & 0xFFFFFFFFu));
     }
     __syncthreads();
@@ -516,42 +514,25 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
   }
 }
 
-// Dynamic LDS: the step's input sums (B int64), which the fallback listing
-// also borrows for its producer prefix ((kBucketMaxProducers + 1) ints).
+// Dynamic LDS of a block of B targets: the input sums (room also for the
+// fallback listing's producer prefix), then y, I, r, the step's Poisson
+// counts and the populations.
 size_t bucket_lds_bytes(int B) {
-  return std::max((size_t)B * sizeof(long long), (size_t)(kBucketMaxProducers + 1) * sizeof(int));
-}
-
-template <int T>
-static hipError_t launch_bucket_t(const DevNet& p, const BucketArgs& a, int steps, int block, hipStream_t s) {
-  hipLaunchKernelGGL(k_bucket<T>, dim3(a.G), dim3(block), bucket_lds_bytes(a.B), s, p, a, steps);
-  return hipGetLastError();
-}
-
-int bucket_targets_per_thread(int B, int block) {
-  const int t = (B + block - 1) / block;
-  return t <= 1 ? 1 : t <= 2 ? 2 : t <= 4 ? 4 : t <= 6 ? 6 : 0;
+  return bucket_sum_slots(B) * sizeof(long long) + (size_t)B * (8 + 8 + 4 + 1 + 1);
 }
 
 hipError_t launch_bucket(const DevNet& p, const BucketArgs& a, int steps, int block, hipStream_t s) {
-  switch (bucket_targets_per_thread(a.B, block)) {
-    case 1: return launch_bucket_t<1>(p, a, steps, block, s);
-    case 2: return launch_bucket_t<2>(p, a, steps, block, s);
-    case 4: return launch_bucket_t<4>(p, a, steps, block, s);
-    case 6: return launch_bucket_t<6>(p, a, steps, block, s);
-    default: return hipErrorInvalidValue;
-  }
+  if (a.Q < 1 || 4 * a.Q * block < a.B || 4 * a.Q > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_bucket, dim3(a.G), dim3(block), bucket_lds_bytes(a.B), s, p, a, steps);
+  return hipGetLastError();
 }
 
 hipError_t bucket_occupancy(int B, int block, int* blocks_per_cu) {
-  const size_t lds = bucket_lds_bytes(B);
-  switch (bucket_targets_per_thread(B, block)) {
-    case 1: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_bucket<1>, block, lds);
-    case 2: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_bucket<2>, block, lds);
-    case 4: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_bucket<4>, block, lds);
-    case 6: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_bucket<6>, block, lds);
-    default: return hipErrorInvalidValue;
-  }
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_bucket, block, bucket_lds_bytes(B));
+}
+
+hipError_t bucket_set_lds_limit(size_t lds) {
+  return hipFuncSetAttribute((const void*)k_bucket, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
 }  // namespace mc

@@ -87,8 +87,8 @@ struct PersistArgs {
   unsigned long long* phase;   // optional [G*8]: summed wall_clock64 ticks per phase (nullptr: off)
   // near table: the delay-1/2 synapses of row i into workgroup g's block are
   // ne[nb[i][p] .. nb[i][p+1]) with p the position of g when the workgroups
-  // are ordered by XCD (g mod 8, then g), each (delay-2 flag | target -
-  // bstart[g]) << 32 | weight
+  // are ordered by XCD (g mod 8, then g), each (target - bstart[g]) << 32 |
+  // weight, bit 31 of the target field set for delay 2
   const unsigned* nb;          // [n_pad][G+1]
   const unsigned long long* ne;
 };
@@ -99,7 +99,8 @@ __host__ __device__ inline size_t persist_flag_words(int G) { return persist_rec
 constexpr int kPersistMaxB = 512;       // owned targets per workgroup (one per thread)
 constexpr int kPersistMaxBlock = 512;   // threads per workgroup: 256 VGPRs per lane, no scratch spills
 size_t persist_lds_bytes(int G, int B, int DL);
-// Near table: counts per (source, workgroup), then (after an exclusive scan) the fill.
+// Near table: counts per (source, workgroup), then (after an exclusive scan)
+// the fill.
 hipError_t launch_near_count(const int32_t* tgt, const uint8_t* dly, const long long* blk, long long n_pad, int G,
                              unsigned* cnt, hipStream_t s);
 hipError_t launch_near_fill(const int32_t* tgt, const int32_t* wq, const uint8_t* dly, const long long* blk,
@@ -119,7 +120,7 @@ hipError_t launch_replay(const int2* spikes, const long long* first_item, int n_
 hipError_t launch_atomic_rate(unsigned long long* table, long long n, long long per_thread, int grid, hipStream_t s);
 hipError_t launch_stream_read(const void* src, long long bytes, unsigned long long* sink, int grid, hipStream_t s);
 hipError_t launch_atomic_slots(unsigned long long* table, long long slots, long long stride, long long n_targets,
-                               long long n_items, int pattern, int gap, const unsigned* dcdf, int grid,
+                               long long n_items, int pattern, int gap, const unsigned char* dq, int grid,
                                hipStream_t s);
 // Empty persistent loop of G co-resident workgroups exchanging one spike
 // record per step (no neurons, no delivery): the exchange's latency floor.
@@ -164,7 +165,8 @@ hipError_t launch_adj_gather(const int4* srcs, const long long* first, int nsrc,
 // OwnerArgs (boff, blk2).
 struct BucketArgs {
   int G;                       // workgroups (all co-resident)
-  int B;                       // most targets of one workgroup (multiple of 4, <= kBucketMaxB, <= 6 * block)
+  int B;                       // most targets of one workgroup (multiple of 4, <= kBucketMaxB)
+  int Q;                       // quads per thread (4 Q block >= B, 4 Q <= 64)
   const int* bt0;              // [G+1]
   const int* binst;            // [G]
   const int* blb;              // [G]
@@ -180,10 +182,11 @@ struct BucketArgs {
 };
 constexpr int kBucketMaxProducers = 512;   // workgroups of one instance
 constexpr int kBucketMaxBlock = 512;       // threads per workgroup
-constexpr int kBucketMaxB = 2048;          // targets per workgroup (11-bit local indices in the records)
+constexpr int kBucketMaxB = 4092;          // targets per workgroup (12-bit local indices and count in the records)
 hipError_t launch_bucket(const DevNet& p, const BucketArgs& a, int steps, int block, hipStream_t s);
 hipError_t bucket_occupancy(int B, int block, int* blocks_per_cu);
-int bucket_targets_per_thread(int B, int block);   // 1, 2, 4 or 6 (0: more than 6 needed)
+hipError_t bucket_set_lds_limit(size_t lds);
+__host__ __device__ size_t bucket_sum_slots(int B);
 size_t bucket_lds_bytes(int B);
 
 // Target-owner delivery (one kernel per step after the update kernel):

@@ -59,7 +59,6 @@ constexpr int kW0Ids = 4;            // of which in word 0 (9-bit block-local in
 constexpr int kBigCap = 64;          // producers with more than kInline spikes listed per step
 constexpr int kUnroll = 4;           // entries in flight per lane
 constexpr int kPollPerLane = kPersistMaxBlock / 64;   // producers polled by one lane (G <= block <= 512)
-constexpr int kNearUnroll = 12;      // near-table rows in flight per wavefront (one round for <= 12 spikes per wave)
 constexpr unsigned kNearD2 = 0x80000000u;   // near-table flag: delay 2 (else 1)
 
 // Workgroups are dispatched to the XCDs round robin (workgroup g runs on XCD
@@ -307,16 +306,30 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
   // only the owner workgroup touches its targets' ring entries, so device-
   // scope loads and stores suffice (no read-modify-write).
   const int take = min(DL, a.horizon), scan = min(127, a.horizon);
-  for (int k = tid; k < scan * Bg; k += nthr) {
-    const int m = k / Bg, jl = k - m * Bg;
-    const long long step = n0 + m;
-    long long* e = p.ring + (size_t)(step & kRingMask) * p.ring_stride + j0 + jl;
-    const long long v = ld_dev(e);
-    if (m < take) {
-      acc[(size_t)(step % DL) * a.B + jl] = v;
-      if (v != 0) st_dev(e, 0ll);
-    } else if (m >= DL && v != 0) {
-      atomicOr(&fbits[(step & kRingMask) * a.BW + (jl >> 5)], 1u << (jl & 31));
+  constexpr int kPro = 8;                  // ring loads in flight per thread
+  for (int k0 = tid; k0 < scan * Bg; k0 += kPro * nthr) {
+    long long v[kPro];
+#pragma unroll
+    for (int u = 0; u < kPro; ++u) {
+      const int k = k0 + u * nthr;
+      v[u] = 0;
+      if (k < scan * Bg) {
+        const int m = k / Bg, jl = k - m * Bg;
+        v[u] = ld_dev(p.ring + (size_t)((n0 + m) & kRingMask) * p.ring_stride + j0 + jl);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kPro; ++u) {
+      const int k = k0 + u * nthr;
+      if (k >= scan * Bg) break;
+      const int m = k / Bg, jl = k - m * Bg;
+      const long long step = n0 + m;
+      if (m < take) {
+        acc[(size_t)(step % DL) * a.B + jl] = v[u];
+        if (v[u] != 0) st_dev(p.ring + (size_t)(step & kRingMask) * p.ring_stride + j0 + jl, 0ll);
+      } else if (m >= DL && v[u] != 0) {
+        atomicOr(&fbits[(step & kRingMask) * a.BW + (jl >> 5)], 1u << (jl & 31));
+      }
     }
   }
   // neuron state into registers: thread t < Bg owns neuron j0+t; the four
@@ -451,7 +464,6 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
     const bool timing = (a.phase != nullptr) && tid == 0;
     long long tp0 = timing ? wall_clock64() : 0;
     const int sn1 = (sn + 1 == DL) ? 0 : sn + 1;
-    const int sn2 = (sn1 + 1 == DL) ? 0 : sn1 + 1;
     const int snm2 = (sn >= 2) ? sn - 2 : sn - 2 + DL;   // slot of step n-2
     const int par = (int)(n & 1);
     const size_t rslot = (size_t)(n % kRecSlots);        // record slot of step n
@@ -476,7 +488,8 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
     const bool work_now = overlap && !pollw;
     if (pollw) {
       const int lane = tid & 63;
-      const long long t_poll = wall_clock64();
+      long long t_poll = 0;          // the wall clock is read every 256 rounds only
+      unsigned spins = 0;
       unsigned todo = 0;
 #pragma unroll
       for (int r = 0; r < kPollPerLane; ++r)
@@ -528,7 +541,7 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
         }
         if (!todo) break;
         __builtin_amdgcn_s_sleep(1);
-        if (wall_clock64() - t_poll > a.wait_ticks) {
+        if ((++spins & 255u) == 0u && (t_poll == 0 ? ((t_poll = wall_clock64()), false) : wall_clock64() - t_poll > a.wait_ticks)) {
           atomicOr(p.overflow, 2u);
           s_abort = 1;
 #pragma unroll
@@ -598,7 +611,7 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
       }
       const int k0 = (int)((long long)S * wave / nw), k1 = (int)((long long)S * (wave + 1) / nw);
       if (timing) { const long long t = wall_clock64(); ph[3] += t - tp0; tp0 = t; }
-      wave_near(a, blk, ids_n, k0, k1, gpos, sn1, sn2);
+      wave_near(a, blk, ids_n, k0, k1, gpos, sn1, sn1 + 1 == DL ? 0 : sn1 + 1);
       __syncthreads();
       if (timing) { const long long t = wall_clock64(); ph[4] += t - tp0; tp0 = t; }
       S2 = S1;
@@ -629,7 +642,7 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
       }
       if (timing) { const long long t = wall_clock64(); ph[3] += t - tp0; tp0 = t; }
       if (S <= kListCap) {
-        wave_near(a, blk, ids_n, k0, k1, gpos, sn1, sn2);   // reads the ids this wavefront wrote
+        wave_near(a, blk, ids_n, k0, k1, gpos, sn1, sn1 + 1 == DL ? 0 : sn1 + 1);   // reads the ids this wavefront wrote
       } else {
         // too many spikes to keep: deliver all events of this chunk now
         unsigned long long ev = 0;
@@ -741,7 +754,8 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_exchange_probe(unsigned lo
     const size_t rslot = (size_t)(n % kRecSlots);
     if (tid == 0) st_dev(&flags[((size_t)g * kRecSlots + rslot) * kPersistFlagStride], tag16);
     if (wave == nw - 1) {
-      const long long t_poll = wall_clock64();
+      long long t_poll = 0;          // the wall clock is read every 256 rounds only
+      unsigned spins = 0;
       unsigned todo = 0;
 #pragma unroll
       for (int r = 0; r < kPollPerLane; ++r)
@@ -757,7 +771,7 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_exchange_probe(unsigned lo
           if (((todo >> r) & 1u) && (w0[r] & 0xFFFF000000000000ull) == tag16) todo &= ~(1u << r);
         if (!todo) break;
         __builtin_amdgcn_s_sleep(1);
-        if (wall_clock64() - t_poll > wait_ticks) {
+        if ((++spins & 255u) == 0u && (t_poll == 0 ? ((t_poll = wall_clock64()), false) : wall_clock64() - t_poll > wait_ticks)) {
           atomicOr(err, 2u);
           s_abort = 1;
           break;

@@ -59,7 +59,7 @@ __global__ __launch_bounds__(256) void k_atomic_rate(unsigned long long* table, 
   }
 }
 
-// Streaming read of `n16` 16-byte words (grid-stride, four loads in flight
+// Streaming read of `n16` 16-byte words (grid-stride, eight loads in flight
 // per lane): the achievable HBM read bandwidth.  The XOR of what a thread
 // read is stored only if it equals a value the data never produce, so the
 // loads cannot be dropped.
@@ -67,65 +67,70 @@ __global__ __launch_bounds__(256) void k_stream_read(const ulonglong2* src, long
   const long long stride = (long long)gridDim.x * blockDim.x;
   unsigned long long x = 0;
   long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  for (; k + 3 * stride < n16; k += 4 * stride) {
-    const ulonglong2 a = src[k], b = src[k + stride], c = src[k + 2 * stride], d = src[k + 3 * stride];
-    x ^= a.x ^ a.y ^ b.x ^ b.y ^ c.x ^ c.y ^ d.x ^ d.y;
+  for (; k + 7 * stride < n16; k += 8 * stride) {
+    ulonglong2 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = src[k + u * stride];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) x ^= v[u].x ^ v[u].y;
   }
   for (; k < n16; k += stride) { const ulonglong2 a = src[k]; x ^= a.x ^ a.y; }
   if (x == 0x5A5A5A5A5A5A5A5Aull) sink[0] = x;
 }
 
 // Slot-major int64 atomic adds into table[slot][target] (slots x stride
-// entries), in work items of 256 events (4 per lane, one wavefront).
+// entries), in work items of 256 events (4 per lane, one wavefront).  The
+// addresses come from a cheap 32-bit hash and multiply-shift, so that the
+// probe is bound by the atomics, not by its own arithmetic.
 // pattern 0: every event at a uniformly random (slot, target);
 // pattern 1: the delivery's own pattern -- an item is a chunk of one source
 // row at spike step t (t advancing with the item index over the first
 // slots - 101 slots): targets ascending with gaps uniform in [1, 2 gap - 1],
-// each event's delay drawn from the network's delay histogram (dcdf: 32-bit
-// cumulative, dcdf[d] = P(delay <= d) 2^32), landing in slot t + delay.
-__device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
-  z += 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
+// each event's delay one of 1024 quantiles of the network's delay
+// histogram (dq), landing in slot t + delay.
+__device__ __forceinline__ unsigned hash32(unsigned x) {
+  x ^= x >> 16; x *= 0x7FEB352Du;
+  x ^= x >> 15; x *= 0x846CA68Bu;
+  x ^= x >> 16;
+  return x;
 }
+__device__ __forceinline__ unsigned scale32(unsigned h, unsigned n) { return (unsigned)(((unsigned long long)h * n) >> 32); }
+
 __global__ __launch_bounds__(256) void k_atomic_slots(unsigned long long* table, long long slots, long long stride,
                                                       long long n_targets, long long n_items, int pattern, int gap,
-                                                      const unsigned* dcdf) {
-  __shared__ unsigned s_cdf[128];
-  for (int k = threadIdx.x; k < 128; k += blockDim.x) s_cdf[k] = dcdf[k];
+                                                      const unsigned char* dq) {
+  __shared__ unsigned char s_dq[1024];
+  for (int k = threadIdx.x; k < 1024; k += blockDim.x) s_dq[k] = dq[k];
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const long long wave = (blockIdx.x * (long long)blockDim.x + threadIdx.x) >> 6;
   const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
   const long long tspan = slots > 101 ? slots - 101 : 1;
+  const unsigned ns = (unsigned)slots, nt = (unsigned)n_targets;
   for (long long item = wave; item < n_items; item += nwaves) {
-    const unsigned long long h0 = mix64((unsigned long long)item);
+    const unsigned h0 = hash32((unsigned)item * 0x9E3779B9u + 0x632BE5ABu);
     const long long t = item * tspan / n_items;
-    // row chunk: lane l of round u takes event 64u + l; its target is the
-    // chunk start plus the prefix of the gaps up to it
-    long long tg = (long long)(h0 % (unsigned long long)n_targets);
+    unsigned tg = scale32(h0, nt);
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const unsigned long long h = mix64(h0 ^ (unsigned long long)(u * 64 + lane + 1));
-      long long slot, target;
+      const unsigned h = hash32(h0 ^ (unsigned)(u * 64 + lane + 1) * 0x85EBCA6Bu);
+      unsigned slot, target;
       if (pattern == 0) {
-        slot = (long long)((h >> 40) % (unsigned long long)slots);
-        target = (long long)((h & 0xFFFFFFFFFFull) % (unsigned long long)n_targets);
+        slot = scale32(h, ns);
+        target = scale32(hash32(h ^ 0x5BD1E995u), nt);
       } else {
-        int g = 1 + (int)((h >> 8) % (unsigned long long)(2 * gap - 1));
+        const int g = 1 + (int)scale32(h, (unsigned)(2 * gap - 1));
         int x = g;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
           const int y = __shfl_up(x, o, 64);
           if (lane >= o) x += y;
         }
-        target = (tg + x) % n_targets;
-        tg += __shfl(x, 63, 64);
-        const unsigned r = (unsigned)(h >> 32);
-        int d = 1;
-        while (d < 127 && r >= s_cdf[d]) ++d;
-        slot = (t + d) % slots;
+        target = tg + (unsigned)x;
+        while (target >= nt) target -= nt;
+        tg += (unsigned)__shfl(x, 63, 64);
+        while (tg >= nt) tg -= nt;
+        slot = (unsigned)((t + s_dq[(h >> 8) & 1023]) % slots);
       }
       atomicAdd(&table[(size_t)slot * stride + target], 1ull);
     }
@@ -138,10 +143,10 @@ hipError_t launch_stream_read(const void* src, long long bytes, unsigned long lo
 }
 
 hipError_t launch_atomic_slots(unsigned long long* table, long long slots, long long stride, long long n_targets,
-                               long long n_items, int pattern, int gap, const unsigned* dcdf, int grid,
+                               long long n_items, int pattern, int gap, const unsigned char* dq, int grid,
                                hipStream_t s) {
   hipLaunchKernelGGL(k_atomic_slots, dim3(grid), dim3(256), 0, s, table, slots, stride, n_targets, n_items, pattern,
-                     gap, dcdf);
+                     gap, dq);
   return hipGetLastError();
 }
 

@@ -47,7 +47,7 @@ def small():
     return w, S, loss, g, g32, (rs, ri), o.state(), o.synapses()
 
 
-@pytest.mark.parametrize("scheme", [0, 1, 2])
+@pytest.mark.parametrize("scheme", [0, 1, 2, 3])
 def test_adjoint_fp64_matches_oracle(small, scheme):
     w, S, loss, g, _, (rs, ri), (oy, oI, orr), (rp, tg, wq, d) = small
     net = mc.Network(w)
@@ -55,6 +55,8 @@ def test_adjoint_fp64_matches_oracle(small, scheme):
         net.set_launch(scheme=1, block=512, neurons_per_wg=0, steps_per_graph=0)
     elif scheme == 2:
         net.set_launch(scheme=2, block=256, neurons_per_wg=256, steps_per_graph=0)
+    elif scheme == 3:
+        net.set_launch(scheme=3, block=256, neurons_per_wg=0, steps_per_graph=0)
     gl, gg = gpu_adjoint(net, S, w.adj_ckpt_every)
     assert abs(gl - loss) <= 1e-12 * abs(loss), (gl, loss)
     nz = np.count_nonzero(g)
@@ -138,7 +140,7 @@ def test_adjoint_window_after_presimulation(small):
     assert np.all(ga[~has] == 0.0) and np.count_nonzero(ga) > 1000
 
 
-@pytest.mark.parametrize("scheme", [0, 1])
+@pytest.mark.parametrize("scheme", [0, 1, 3])
 @pytest.mark.parametrize("S", [1, 2, 3, 5, 17])
 def test_adjoint_tiny_windows_after_presimulation(small, S, scheme):
     """Windows of 1 to 17 steps after 500 steps: the shortest delay is one
@@ -147,8 +149,8 @@ def test_adjoint_tiny_windows_after_presimulation(small, S, scheme):
     w = small[0]
     n0 = 500
     net = mc.Network(w)
-    if scheme == 1:
-        net.set_launch(scheme=1, block=512, neurons_per_wg=0, steps_per_graph=0)
+    if scheme in (1, 3):
+        net.set_launch(scheme=scheme, block=512, neurons_per_wg=0, steps_per_graph=0)
     net.simulate(n0)
     gl, gg = gpu_adjoint(net, S, 2)
     o = oracle.Oracle(w.to_dict())

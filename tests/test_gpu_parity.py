@@ -80,14 +80,17 @@ def test_balanced_network_full_protocol():
     (0, 64, 64, 1), (0, 256, 256, 1000), (0, 256, 1024, 7), (0, 1024, 512, 333), (0, 128, 16, 50), (0, 256, 256, 0),
     (1, 512, 0, 1000), (1, 256, 0, 100), (1, 512, 64, 7), (1, 512, 512, 250), (1, 512, 200, 0), (1, 128, 24, 50),
     (1, 64, 64, 50),
-    (2, 256, 256, 1000), (2, 64, 16, 7), (2, 1024, 1024, 0), (2, 128, 100, 33)])
+    (2, 256, 256, 1000), (2, 64, 16, 7), (2, 1024, 1024, 0), (2, 128, 100, 33),
+    (3, 256, 0, 1000), (3, 256, 16, 7), (3, 512, 2048, 0), (3, 128, 100, 33), (3, 64, 384, 50), (3, 512, 0, 1),
+    (3, 256, 4092, 20)])
 def test_launch_configuration_invariance(scheme, block, npw, spg):
     """Every launch shape of every scheme gives identical bits (integer sums,
     fixed FP order).  (1, 64, 64) runs the persistent scheme with one
     wavefront per workgroup, which polls and then delivers by itself.
     Persistent neurons_per_wg = 512 leaves room for only ~30 delay steps in
     LDS, so most events take the far (global) path; the target-owner shapes
-    range from 16 to 1024 targets per delivery block."""
+    range from 16 to 1024 targets per delivery block; the bucket scheme
+    from 16 to 4092 targets per workgroup (1 to 4 quads per thread)."""
     w = workloads.balanced()
     net, o = mc.Network(w), oracle.Oracle(w.to_dict())
     net.set_launch(scheme=scheme, block=block, neurons_per_wg=npw, steps_per_graph=spg)
@@ -99,7 +102,8 @@ def test_launch_configuration_invariance(scheme, block, npw, spg):
 # the launch shapes mc_tune times (same list and steps per graph)
 TUNER_CANDIDATES = [(1, 512, 0, 10000, 0), (1, 256, 0, 10000, 0), (1, 512, 256, 10000, 0), (1, 512, 512, 10000, 0),
                     (1, 256, 128, 10000, 0), (0, 256, 256, 1000, 0), (0, 256, 256, 1000, 1), (0, 256, 1024, 1000, 0),
-                    (0, 512, 512, 1000, 0), (0, 512, 512, 1000, 1), (0, 128, 128, 1000, 0), (0, 128, 128, 1000, 1)]
+                    (0, 512, 512, 1000, 0), (0, 512, 512, 1000, 1), (0, 128, 128, 1000, 0), (0, 128, 128, 1000, 1),
+                    (3, 256, 0, 10000, 0), (3, 512, 0, 10000, 0), (3, 128, 0, 10000, 0)]
 
 
 def test_every_autotuner_candidate_gives_the_same_bits():
@@ -116,7 +120,7 @@ def test_every_autotuner_candidate_gives_the_same_bits():
         net.close()
 
 
-@pytest.mark.parametrize("scheme", [0, 1, 2])
+@pytest.mark.parametrize("scheme", [0, 1, 2, 3])
 def test_all_delays_one_step(scheme):
     """Every synapse with the smallest delay (one step): every event must be
     in place by the next update, so a missing wait anywhere in the exchange
@@ -124,7 +128,7 @@ def test_all_delays_one_step(scheme):
     w = workloads.balanced().replace(name="delay1", d_max_steps=1)
     net, o = mc.Network(w), oracle.Oracle(w.to_dict())
     assert set(np.unique(net.synapses()[3])) == {1}
-    net.set_launch(scheme=scheme, block=512 if scheme == 1 else 256, neurons_per_wg=0 if scheme == 1 else 256,
+    net.set_launch(scheme=scheme, block=512 if scheme == 1 else 256, neurons_per_wg=0 if scheme in (1, 3) else 256,
                    steps_per_graph=100)
     net.simulate(1000)
     o.run(1000)
@@ -133,13 +137,17 @@ def test_all_delays_one_step(scheme):
 
 
 @pytest.mark.parametrize("scheme,block,npw,spg", [(0, 256, 256, 100), (1, 512, 0, 100), (1, 256, 64, 7),
-                                                   (2, 256, 256, 100)])
+                                                   (2, 256, 256, 100), (3, 256, 0, 100), (3, 512, 2048, 100),
+                                                   (3, 64, 64, 7)])
 def test_synchronous_bursts(scheme, block, npw, spg):
     """A DC current far above threshold makes every neuron fire at its first
     free step: all 5,000 fire together every 21 steps.  That is the densest
     raster the refractory period allows (the raster bound is met exactly) and,
-    in the persistent scheme, more spikes in one step than its LDS spike list
-    holds (the branch that delivers every event of such a step at once)."""
+    in the persistent schemes, more spikes in one step than their LDS spike
+    lists hold (the branches that deliver such a step at once, or in chunks
+    read back from the records).  With 2048 targets per workgroup a burst
+    brings ~1e6 events to one workgroup, far more than its buckets hold: the
+    overflow goes to the ring."""
     w = workloads.balanced().replace(name="bursts", i_e=1.0e5)
     net, o = mc.Network(w), oracle.Oracle(w.to_dict())
     net.set_launch(scheme=scheme, block=block, neurons_per_wg=npw, steps_per_graph=spg)
@@ -150,13 +158,13 @@ def test_synchronous_bursts(scheme, block, npw, spg):
     assert_same(net, o, what=f"bursts {scheme},{block},{npw},{spg}")
 
 
-@pytest.mark.parametrize("scheme", [0, 1, 2])
+@pytest.mark.parametrize("scheme", [0, 1, 2, 3])
 def test_silent_network(scheme):
     """No drive and no current: no neuron ever fires, nothing is delivered,
     and the membrane decays by the same propagator bits on both sides."""
     w = workloads.balanced().replace(name="silent", nu_ext=0.0, v0_lo=-65.0, v0_hi=-50.5)
     net, o = mc.Network(w), oracle.Oracle(w.to_dict())
-    net.set_launch(scheme=scheme, block=512 if scheme == 1 else 256, neurons_per_wg=0 if scheme == 1 else 256,
+    net.set_launch(scheme=scheme, block=512 if scheme == 1 else 256, neurons_per_wg=0 if scheme in (1, 3) else 256,
                    steps_per_graph=50)
     net.simulate(400)
     o.run(400)
@@ -254,9 +262,9 @@ def test_scheme_switch_midway():
     """Switching between the schemes in the middle of a run changes nothing."""
     w = workloads.balanced()
     net, o = mc.Network(w), oracle.Oracle(w.to_dict())
-    order = [1, 0, 2, 1, 1, 2, 0, 2]
+    order = [1, 0, 3, 2, 1, 3, 3, 1, 2, 0, 2]
     for k, sch in enumerate(order):
-        net.set_launch(scheme=sch, block=512 if sch == 1 else 256, neurons_per_wg=0 if sch == 1 else 256,
+        net.set_launch(scheme=sch, block=512 if sch == 1 else 256, neurons_per_wg=0 if sch in (1, 3) else 256,
                        steps_per_graph=97 + k)
         net.simulate(311)
     o.run(len(order) * 311)
@@ -284,7 +292,8 @@ def test_resume_and_checkpoint():
     assert np.array_equal(s_first, s2) and np.array_equal(i_first, i2)
 
 
-def test_short_rewinds_onto_other_states():
+@pytest.mark.parametrize("scheme", [1, 3])
+def test_short_rewinds_onto_other_states(scheme):
     """Loading a state a few steps back, alternately the network's own and
     that of another seed (same shape), then simulating: every run matches
     the oracle started from that state.  In the persistent scheme the spike
@@ -293,7 +302,7 @@ def test_short_rewinds_onto_other_states():
     wa, wb = workloads.balanced(seed=1), workloads.balanced(seed=2)
     a, b = mc.Network(wa), mc.Network(wb)
     for net in (a, b):
-        net.set_launch(scheme=1, block=512, neurons_per_wg=0, steps_per_graph=1000)
+        net.set_launch(scheme=scheme, block=512, neurons_per_wg=0, steps_per_graph=1000)
         net.simulate(100)
     blob_a, blob_b = a.save_state(), b.save_state()
     # expected: seed-1 network continued from its own state and from seed 2's
@@ -324,7 +333,7 @@ def test_short_rewinds_onto_other_states():
         assert np.array_equal(s, es[m]) and np.array_equal(i, ei[m]), (rep, name)
 
 
-@pytest.mark.parametrize("scheme", [0, 1, 2])
+@pytest.mark.parametrize("scheme", [0, 1, 2, 3])
 def test_batched_instances_match_standalone(scheme):
     """Instances of a batch are bit-identical to their standalone runs, in
     every scheme (target-owner blocks of 64 targets: several per instance,
@@ -337,6 +346,8 @@ def test_batched_instances_match_standalone(scheme):
         net.set_launch(scheme=1, block=512, neurons_per_wg=0, steps_per_graph=500)
     elif scheme == 2:
         net.set_launch(scheme=2, block=256, neurons_per_wg=64, steps_per_graph=300)
+    elif scheme == 3:
+        net.set_launch(scheme=3, block=64, neurons_per_wg=96, steps_per_graph=300)
     net.simulate(1500)
     s, i = net.spikes()
     y, I, r = net.state()
@@ -364,38 +375,45 @@ def test_batched_c2_full_shape_matches_per_instance_oracles():
     spike counters equal its standalone oracle's, run one instance after
     another on the host."""
     w = workloads.batched()
-    net = mc.Network(w, device_connect=True)
-    assert net.n_instances == 64 and net.N == 750_775
-    net.simulate(100)
-    best = net.tune(200)
-    print("c2 launch:", best, flush=True)
-    net.simulate(w.presim_steps - 100)
-    net.simulate(300)
-    s, i = net.spikes()
-    y, I, r = net.state()
-    ring = net.ring(8)
-    off = net.instance_offsets()
-    c = net.counters()
+    runs = []
+    for how in ("tuned", "buckets"):
+        net = mc.Network(w, device_connect=True)
+        assert net.n_instances == 64 and net.N == 750_775
+        net.simulate(100)
+        if how == "tuned":
+            launch = net.tune(200)
+        else:
+            net.set_launch(scheme=3, block=256, neurons_per_wg=0, steps_per_graph=1000)
+            launch = net.get_launch()
+        print(f"c2 {how} launch: {launch} shape {net.persist_shape()}", flush=True)
+        net.simulate(w.presim_steps - 100)
+        net.simulate(300)
+        runs.append((how, net.spikes(), net.state(), net.ring(8), net.counters()))
+        off = net.instance_offsets()
+        net.close()
     ev_total, sp_total = 0, np.zeros(w.n_pops, np.int64)
     for b in range(64):
         o = oracle.Oracle(w.instance(b).to_dict())
         o.run(w.presim_steps + 300)
         os_, oi = o.raster()
-        m = (i >= off[b]) & (i < off[b + 1])
-        assert np.array_equal(s[m], os_) and np.array_equal(i[m] - off[b], oi), (b, best)
         oy, oI, orr = o.state()
+        oring = o.ring(8)
         sl = slice(off[b], off[b + 1])
-        assert np.array_equal(y[sl].view(np.uint64), oy.view(np.uint64)), b
-        assert np.array_equal(I[sl].view(np.uint64), oI.view(np.uint64)), b
-        assert np.array_equal(r[sl], orr), b
-        assert np.array_equal(ring[:, sl], o.ring(8)), b
+        for how, (s, i), (y, I, r), ring, _ in runs:
+            m = (i >= off[b]) & (i < off[b + 1])
+            assert np.array_equal(s[m], os_) and np.array_equal(i[m] - off[b], oi), (b, how)
+            assert np.array_equal(y[sl].view(np.uint64), oy.view(np.uint64)), (b, how)
+            assert np.array_equal(I[sl].view(np.uint64), oI.view(np.uint64)), (b, how)
+            assert np.array_equal(r[sl], orr), (b, how)
+            assert np.array_equal(ring[:, sl], oring), (b, how)
         sp, ev = o.counters()
         ev_total += ev
         sp_total += sp
         del o
-        print(f"c2 instance {b}: {m.sum()} spikes equal", flush=True)
-    assert c["events"] == ev_total and np.array_equal(c["spikes_per_pop"], sp_total)
-    assert c["step"] == w.presim_steps + 300 and len(s) > 100_000
+        print(f"c2 instance {b}: {len(os_)} spikes equal in both launches", flush=True)
+    for how, (s, i), _, _, c in runs:
+        assert c["events"] == ev_total and np.array_equal(c["spikes_per_pop"], sp_total), how
+        assert c["step"] == w.presim_steps + 300 and len(s) > 100_000
 
 
 @pytest.fixture(scope="module")
@@ -411,7 +429,7 @@ def micro_oracle_runs():
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("scheme", [0, 1, 2])
+@pytest.mark.parametrize("scheme", [0, 1, 2, 3])
 def test_full_microcircuit_parity(micro_oracle_runs, scheme):
     """The full-scale microcircuit (77,169 neurons, ~3e8 synapses): raster,
     state bits and the first logical ring slots equal to the oracle's after
@@ -423,6 +441,8 @@ def test_full_microcircuit_parity(micro_oracle_runs, scheme):
         net.set_launch(scheme=1, block=512, neurons_per_wg=0, steps_per_graph=1000)
     elif scheme == 2:
         net.set_launch(scheme=2, block=256, neurons_per_wg=256, steps_per_graph=1000)
+    elif scheme == 3:
+        net.set_launch(scheme=3, block=256, neurons_per_wg=0, steps_per_graph=1000)
     assert (net.N, net.M) == (N, M)
     for steps, (ras, st, ring, cnt) in ((1000, a), (300, b)):
         net.simulate(steps)
@@ -487,27 +507,32 @@ def test_network_lives_in_torch_allocator_memory():
     tables) comes from torch's caching allocator and goes back to it; the
     trajectory is the oracle's."""
     import torch
-    allocs, frees = {}, []
+    live, total = {}, {"allocs": 0, "frees": 0, "bytes": 0}
 
     def fa(nbytes):
         p = torch.cuda.caching_allocator_alloc(nbytes)
-        allocs[p] = nbytes
+        assert p not in live                         # torch may hand out a freed block again
+        live[p] = nbytes
+        total["allocs"] += 1
+        total["bytes"] += nbytes
         return p
 
     def ff(ptr):
+        assert ptr in live
+        del live[ptr]
         torch.cuda.caching_allocator_delete(ptr)
-        frees.append(ptr)
+        total["frees"] += 1
 
     w = workloads.balanced()
     net = mc.Network(w, allocator=(fa, ff))
     o = oracle.Oracle(w.to_dict())
-    assert sum(allocs.values()) >= 9 * net.M          # the synapse store came from torch
+    assert total["bytes"] >= 9 * net.M               # the synapse store came from torch
     net.set_launch(scheme=1, block=512, neurons_per_wg=0, steps_per_graph=200)
     net.simulate(500)
     o.run(500)
     assert_same(net, o, what="torch allocator")
     net.close()
-    assert sorted(frees) == sorted(allocs) and len(frees) > 10
+    assert not live and total["frees"] == total["allocs"] > 10
 
 
 @pytest.mark.parametrize("block,npw,spg", [(256, 256, 1000), (64, 64, 1), (1024, 512, 333)])
