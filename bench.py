@@ -445,7 +445,7 @@ def run_plain(args, mc, w) -> dict:
             rep["same_table_rows_probe_per_s"] = pr["atomic_adds_per_s"].get(key)
             rep["frac_hbm_measured"] = r_gbs / pr["stream_read_gbs"]
         out["delivery_replay"] = rep
-    if args.phases and launch["scheme"] == mc.SCHEME_PERSISTENT_LDS:
+    if args.phases and launch["scheme"] in (mc.SCHEME_PERSISTENT_LDS, mc.SCHEME_PERSISTENT_BUCKETS):
         out["phases_us_per_step"] = net.profile_phases(args.phases)
     if args.adjoint_window > 0 and full:
         out["adjoint"] = adjoint_cost(net, args.adjoint_window, 100, -58.0, True)
@@ -466,6 +466,9 @@ def run_batched(args, mc, w) -> dict:
     launch = net.get_launch()
     N, M, n_inst = net.N, net.M, net.n_instances
     energy = energy_run(net, EnergyMeter(), args.energy_wall, gpu_ms / steps) if args.energy_wall > 0 else None
+    phases = None
+    if args.phases and launch["scheme"] in (mc.SCHEME_PERSISTENT_LDS, mc.SCHEME_PERSISTENT_BUCKETS):
+        phases = net.profile_phases(args.phases)
     net.close()
     seq_ms, seq_events, seq_launch = 0.0, 0, {}
     n_seq = n_inst if args.seq_instances <= 0 else min(args.seq_instances, n_inst)
@@ -496,6 +499,7 @@ def run_batched(args, mc, w) -> dict:
                        "launches": seq_launch},
         "speedup_vs_sequential": (seq_ms_all * 1e-3) / wall_s,
         "energy": energy,
+        "phases_us_per_step": phases,
     }
 
 

@@ -283,14 +283,15 @@ int mc_tune(mc_net* net, int64_t steps, mc_launch* best_out);
 int mc_get_persist_shape(mc_net* net, int32_t* workgroups_out, int32_t* targets_per_wg_out, int32_t* lds_steps_out);
 /* The time per phase of the cycle (Fig. 1b splits the run time into update,
  * deliver, communicate and other): simulates `steps` steps with per-phase
- * device timestamps (persistent scheme only) and returns the mean time per
+ * device timestamps (persistent schemes only) and returns the mean time per
  * step in microseconds, averaged
  * over workgroups: us_out[0] update, [1] compaction+publication, [2] wait
- * for every workgroup's spikes, [3] spike-list gather, [4] delay-1
- * delivery, [5] the sum of [0..4]; overlapping parts of [2]: [6] drive of
- * the next step and pending delivery of the previous one (first wavefront),
- * [7] polling (first polling thread).  The trajectory is the one
- * mc_simulate would produce. */
+ * for every workgroup's spikes, [3] spike-list gather, [4] delivery (LDS
+ * window: the delay-1 events; buckets: every event of the step), [5] the
+ * sum of [0..4]; overlapping parts of [2]: [6] drive of the next step (and,
+ * in the LDS window, pending delivery of the previous one; first
+ * wavefront), [7] polling (first polling thread).  The trajectory is the
+ * one mc_simulate would produce. */
 int mc_profile_phases(mc_net* net, int64_t steps, double* us_out_host);
 /* The per-workgroup times behind the last mc_profile_phases, [G][8] us per
  * step (columns 0..4 as us_out[0..4], 5: drive + pending delivery of
@@ -323,7 +324,8 @@ int mc_atomic_rate(mc_net* net, int64_t entries, double* gops_out);
  *                        events of a row: ascending targets at the store's
  *                        mean spacing N/mean out-degree, delays drawn from the
  *                        store's delay histogram, spike steps advancing over
- *                        the table); *gops_out 1e9 adds per second;
+ *                        the table); *gops_out 1e9 adds per second, of
+ *                        the fastest of three timed launches of 2^27 adds;
  *   mc_probe_exchange -- the persistent scheme in use with nothing but its
  *                        exchange: its workgroups publish and poll one record
  *                        per step; *us_per_step_out the time per step, the

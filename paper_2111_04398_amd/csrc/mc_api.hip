@@ -245,6 +245,7 @@ struct mc_net {
     a.flags = d_flags; a.pub = d_pub; a.bk = d_bk; a.cap = bk_cap;
     a.wait_ticks = (long long)wall_khz * 1000 * kWaitSeconds;
     a.horizon = horizon;
+    a.phase = phase_on ? d_phase : nullptr;
     return a;
   }
 
@@ -1338,12 +1339,14 @@ int mc_load_state(mc_net* n, const void* blob, size_t size) {
 
 int mc_profile_phases(mc_net* n, int64_t steps, double* us) {
   if (!device_ready(n) || !us) return set_error(MC_ERR_INVALID_ARG, "bad handle or NULL");
-  if (n->launch.scheme != MC_SCHEME_PERSISTENT_LDS) return set_error(MC_ERR_STATE, "phase timing needs the persistent scheme");
+  if (n->launch.scheme != MC_SCHEME_PERSISTENT_LDS && n->launch.scheme != MC_SCHEME_PERSISTENT_BUCKETS)
+    return set_error(MC_ERR_STATE, "phase timing needs a persistent scheme");
   if (steps < 1 || n->step + steps > 2147483647LL) return set_error(MC_ERR_INVALID_ARG, "steps out of range");
   int rc;
+  const int G = n->launch.scheme == MC_SCHEME_PERSISTENT_LDS ? n->pG : n->own_blocks;
   dev_free(n->alloc, n->d_phase);
-  if ((rc = dev_alloc(n->alloc, &n->d_phase, (size_t)n->pG * 8)) != MC_OK) return rc;
-  HIP_TRY(hipMemsetAsync(n->d_phase, 0, sizeof(unsigned long long) * n->pG * 8, n->stream));
+  if ((rc = dev_alloc(n->alloc, &n->d_phase, (size_t)G * 8)) != MC_OK) return rc;
+  HIP_TRY(hipMemsetAsync(n->d_phase, 0, sizeof(unsigned long long) * G * 8, n->stream));
   // direct launches: a captured graph would carry the timing-off arguments
   if (n->graph) { (void)hipGraphExecDestroy(n->graph); n->graph = nullptr; }
   const int spg = n->launch.steps_per_graph;
@@ -1354,16 +1357,16 @@ int mc_profile_phases(mc_net* n, int64_t steps, double* us) {
   n->launch.steps_per_graph = spg;
   if (rc != MC_OK) return rc;
   HIP_TRY(hipStreamSynchronize(n->stream));
-  std::vector<unsigned long long> h((size_t)n->pG * 8);
+  std::vector<unsigned long long> h((size_t)G * 8);
   HIP_TRY(hipMemcpy(h.data(), n->d_phase, sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost));
   int khz = 100000;
   if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, n->device) != hipSuccess || khz <= 0) khz = 100000;
   const double tick_us = 1e3 / (double)khz;
   double acc[7] = {0, 0, 0, 0, 0, 0, 0};
-  for (int g = 0; g < n->pG; ++g)
+  for (int g = 0; g < G; ++g)
     for (int k = 0; k < 7; ++k) acc[k] += (double)h[(size_t)g * 8 + k];
-  const double norm = tick_us / ((double)n->pG * (double)steps);
-  n->phase_wg.assign((size_t)n->pG * 8, 0.0);
+  const double norm = tick_us / ((double)G * (double)steps);
+  n->phase_wg.assign((size_t)G * 8, 0.0);
   for (size_t k = 0; k < h.size(); ++k) n->phase_wg[k] = (k % 8 == 7) ? 0.0 : (double)h[k] * tick_us / (double)steps;
   us[5] = 0;
   for (int k = 0; k < 5; ++k) { us[k] = acc[k] * norm; us[5] += us[k]; }
@@ -1513,13 +1516,18 @@ int mc_probe_atomics(mc_net* n, int64_t slots, int32_t pattern, double* gops) {
   if (err == hipSuccess) err = hipMemsetAsync(t, 0, sizeof(unsigned long long) * slots * n->ring_stride, n->stream);
   if (err == hipSuccess)
     err = launch_atomic_slots(t, slots, n->ring_stride, n->n_pad, items, pattern, gap, dq, grid, n->stream);
-  if (err == hipSuccess) err = hipEventRecord(n->ev0, n->stream);
-  if (err == hipSuccess)
-    err = launch_atomic_slots(t, slots, n->ring_stride, n->n_pad, items, pattern, gap, dq, grid, n->stream);
-  if (err == hipSuccess) err = hipEventRecord(n->ev1, n->stream);
-  if (err == hipSuccess) err = hipEventSynchronize(n->ev1);
+  // the fastest of three timed launches: the rate the memory system reaches
   float ms = 0;
-  if (err == hipSuccess) err = hipEventElapsedTime(&ms, n->ev0, n->ev1);
+  for (int rep = 0; rep < 3 && err == hipSuccess; ++rep) {
+    float one = 0;
+    err = hipEventRecord(n->ev0, n->stream);
+    if (err == hipSuccess)
+      err = launch_atomic_slots(t, slots, n->ring_stride, n->n_pad, items, pattern, gap, dq, grid, n->stream);
+    if (err == hipSuccess) err = hipEventRecord(n->ev1, n->stream);
+    if (err == hipSuccess) err = hipEventSynchronize(n->ev1);
+    if (err == hipSuccess) err = hipEventElapsedTime(&one, n->ev0, n->ev1);
+    if (err == hipSuccess && (rep == 0 || one < ms)) ms = one;
+  }
   dev_free(n->alloc, t);
   dev_free(n->alloc, dq);
   if (err != hipSuccess) return set_error(MC_ERR_HIP, std::string("atomic probe: ") + hipGetErrorString(err));

@@ -30,12 +30,18 @@
 // Step order per iteration n (as k_persist: the spike decision of step m
 // needs I from before step m's input, so step n+1's decision and record go
 // out before the wait for step n's records):
-//   1. bucket of step n -> LDS sums; input of step n (+ ring, + drive) into I;
+//   1. the rest of step n's bucket -> LDS sums; input of step n (+ ring, +
+//      drive) into I;
 //   2. spike decision of step n+1; compaction; record of step n+1;
-//   3. drive of step n+1; wait for the records of step n of the instance's
-//      workgroups, listing their spike ids;
+//   3. one wavefront waits for the records of step n of the instance's
+//      workgroups, listing their spike ids, while the others draw the drive
+//      of step n+1 and sum the entries step n+1's bucket already holds (all
+//      but those of delay 1, which arrive in 4.);
 //   4. every event of step n's spikes that lands in this block goes into the
-//      bucket of its arrival step.
+//      bucket of its arrival step.  The events of a spike that land in the
+//      block are one segment of its row; the segment bounds are found at
+//      offset (i - first id of the instance) * (blocks of the instance + 1)
+//      of the bounds table, so a batch of spikes costs one round of loads.
 // Spike records: four per workgroup (step mod 4).  Word 0 = tag16 << 48 |
 // count << 36 | the block-local indices (12 bits each) of the first three
 // spikes; words 1..3 = (step + 1) << 32 | id of spikes 4..6; later ids in a
@@ -101,14 +107,12 @@ __device__ __forceinline__ int bscan(int v, int* s_tmp, int* total) {
 
 }  // namespace
 
-__host__ __device__ size_t bucket_sum_slots(int B) {
-  return (size_t)B > ((size_t)kBucketMaxProducers + 2) / 2 ? (size_t)B : ((size_t)kBucketMaxProducers + 2) / 2;
-}
+__host__ __device__ size_t bucket_sum_slots(int B) { return (size_t)B; }
 
-// LDS (dynamic): s_x[BX] i64 (input sums of the step being absorbed; BX =
-// max(B, room for the fallback's producer prefix)) | s_y[B] f64 | s_I[B] f64
-// | s_r[B] i32 | s_kd[B] u8 (Poisson count of the step) | s_pop[B] u8.  The
-// neuron state lives in LDS, so registers do not bound the block size.
+// LDS (dynamic): s_x[B] i64 (input sums of the step being absorbed) | s_y[B]
+// f64 | s_I[B] f64 | s_r[B] i32 | s_kd[B] u8 (Poisson count of the step) |
+// s_pop[B] u8.  The neuron state lives in LDS, so registers do not bound the
+// block size.
 __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs a, int steps) {
   extern __shared__ __align__(16) unsigned char s_raw[];
   __shared__ uint64_t s_table[kMaxPops * kTableLen];
@@ -117,6 +121,7 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
   __shared__ int s_tmp[2][16];
   __shared__ int s_first[kBInline];             // ids of the step's first spikes (record)
   __shared__ int s_cnt[kBucketMaxProducers];    // spike count of each producer of the instance this step
+  __shared__ int s_hpre[kBucketMaxProducers + 1];  // their prefix (listing of a step beyond the LDS list)
   __shared__ int s_ids[kBListCap];
   __shared__ int2 s_big[kBBigCap];
   __shared__ int s_nids, s_nbig, s_abort, s_last;
@@ -138,6 +143,9 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
   const int Gi = ((b + 1 < p.n_inst) ? a.ifb[b + 1] : a.G) - gi0;   // its workgroups
   const long long j0 = a.bt0[g];
   const int Bg = a.bt0[g + 1] - a.bt0[g];
+  // the sources of this instance have Gi + 1 block bounds each, from its first id i0 on
+  const int i0 = a.bt0[gi0];
+  const int64_t boff0 = a.boff[i0] + lb;
   const long long n0 = *p.step_base;
   unsigned long long* bk = a.bk + (size_t)g * kRingSlots * a.cap;
 
@@ -159,8 +167,9 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
   // thread t owns the a.Q quads from local target 4 t Q on (those < Bg):
   // ascending ids follow the thread order, and each quad takes one Philox block
   const int lt0 = min(4 * tid * a.Q, Bg), lt1 = min(lt0 + 4 * a.Q, Bg);
-  auto drive = [&](long long m) {                // Poisson counts of my targets at step m
-    for (int q4 = lt0; q4 < lt1; q4 += 4) {
+  // Poisson counts of quads q0, q0 + dq, ... at step m (one Philox block per quad)
+  auto drive_quads = [&](long long m, int q0, int dq) {
+    for (int q4 = 4 * q0; q4 < Bg; q4 += 4 * dq) {
       const long long q = (j0 + q4) >> 2;
       const U64x4 v = philox4x64_10((uint64_t)m, (uint64_t)p.qlocal[q], 0, kTagDrive, p.qseed[q], 0);
 #pragma unroll
@@ -178,7 +187,7 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
     ck_seg = (k >= 0) ? k / p.ck_every : -1;
     ck_phase = (k >= 0) ? k % p.ck_every : 1;
   }
-  if (steps > 0) drive(n0);
+  if (steps > 0) drive_quads(n0, tid, nthr);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
 
@@ -258,9 +267,10 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
       int len = 0;
       if (base + lane < k1) {
         const int i = ids[base + lane];
-        const int64_t o = a.boff[i] + lb;
-        lo = p.row_ptr[i] + a.blk2[o];
-        len = a.blk2[o + 1] - a.blk2[o];
+        const int64_t o = boff0 + (int64_t)(i - i0) * (Gi + 1);
+        const int b0 = a.blk2[o], b1 = a.blk2[o + 1];
+        lo = p.row_ptr[i] + b0;
+        len = b1 - b0;
         ev += (unsigned long long)len;
       }
       int x = len;
@@ -269,27 +279,38 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
         const int yv = __shfl_up(x, o, 64);
         if (lane >= o) x += yv;
       }
-      const int total = __shfl(x, 63, 64);
+      const int total = __builtin_amdgcn_readlane(x, 63);   // uniform (an SGPR)
       const int excl = x - len;
+      const int lo_lo = (int)(unsigned)(lo & 0xFFFFFFFFll), lo_hi = (int)(lo >> 32);
+      // Event f of the batch belongs to the last spike j with excl[j] <= f.
+      // The spikes are walked in order by a uniform index (no cross-lane
+      // search): js is the spike of the first event of the current chunk
+      // of 64, and each lane moves past the segment starts inside its chunk.
+      int js = 0;
       for (int f0 = 0; f0 < total; f0 += 64 * kBUnroll) {
         int tt[kBUnroll], ww[kBUnroll], dd[kBUnroll];
 #pragma unroll
         for (int u = 0; u < kBUnroll; ++u) {
-          const int f = f0 + u * 64 + lane;
+          const int fb = f0 + u * 64, f = fb + lane;
           dd[u] = 0;
-          int lo_l = 0, hi_l = 64;
-#pragma unroll
-          for (int st = 0; st < 6; ++st) {
-            const int mid = (lo_l + hi_l) >> 1;
-            if (__shfl(excl, mid, 64) <= f) lo_l = mid; else hi_l = mid;
-          }
-          const long long lo_j = __shfl(lo, lo_l, 64);
-          const int ex_j = __shfl(excl, lo_l, 64);
-          if (f < total) {
-            const long long e = lo_j + (f - ex_j);
-            tt[u] = p.tgt[e];
-            ww[u] = p.wq[e];
-            dd[u] = p.dly[e];
+          if (fb < total) {
+            while (js < 63 && __builtin_amdgcn_readlane(excl, js + 1) <= fb) ++js;
+            int ex_j = __builtin_amdgcn_readlane(excl, js);
+            unsigned e_lo = (unsigned)__builtin_amdgcn_readlane(lo_lo, js);
+            int e_hi = __builtin_amdgcn_readlane(lo_hi, js);
+            for (int jj = js + 1; jj < 64; ++jj) {
+              const int ex = __builtin_amdgcn_readlane(excl, jj);
+              if (ex > fb + 63) break;
+              const unsigned l_lo = (unsigned)__builtin_amdgcn_readlane(lo_lo, jj);
+              const int l_hi = __builtin_amdgcn_readlane(lo_hi, jj);
+              if (f >= ex) { ex_j = ex; e_lo = l_lo; e_hi = l_hi; }
+            }
+            if (f < total) {
+              const long long e = (long long)(((unsigned long long)(unsigned)e_hi << 32) | e_lo) + (f - ex_j);
+              tt[u] = p.tgt[e];
+              ww[u] = p.wq[e];
+              dd[u] = p.dly[e];
+            }
           }
         }
 #pragma unroll
@@ -310,24 +331,40 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
     *ev_out += ev;
   };
 
+  // entries [from, cnt) of bucket `sl` summed into s_x by threads t of nt,
+  // kAbsorb entries in flight per thread
+  auto absorb_bucket = [&](int sl, int from, int cnt, int t, int nt) {
+    constexpr int kAbsorb = 8;
+    const unsigned long long* bq = bk + (size_t)sl * a.cap;
+    for (int e0 = from + t; e0 < cnt; e0 += kAbsorb * nt) {
+      unsigned long long v[kAbsorb];
+#pragma unroll
+      for (int u = 0; u < kAbsorb; ++u) v[u] = (e0 + u * nt < cnt) ? wld(&bq[e0 + u * nt]) : 0ull;
+#pragma unroll
+      for (int u = 0; u < kAbsorb; ++u)
+        if (e0 + u * nt < cnt)
+          atomicAdd(reinterpret_cast<unsigned long long*>(&s_x[v[u] >> 32]),
+                    (unsigned long long)(long long)(int)(v[u] & 0xFFFFFFFFu));
+    }
+  };
+
   uint64_t mask = 0;
   if (steps > 0) {
     mask = decide(n0);
     publish(n0, mask);
   }
+  long long ph[7] = {0, 0, 0, 0, 0, 0, 0};   // phase ticks (thread 0; [6]: the first polling thread)
+  // entries of the bucket of the coming step already summed into s_x while
+  // the previous step's records were awaited (the same count in every thread)
+  int absorbed = 0;
   for (int it = 0; it < steps; ++it) {
     const long long n = n0 + it;
     const int slot = (int)(n & kRingMask);
     const size_t rslot = (size_t)(n % kRecSlots);
+    const bool timing = (a.phase != nullptr) && tid == 0;
+    long long tp0 = timing ? wall_clock64() : 0;
     // ---- 1. input of step n: its bucket summed in LDS, then into I --------
-    {
-      const int cnt = min(s_bcnt[slot], a.cap);
-      const unsigned long long* bq = bk + (size_t)slot * a.cap;
-      for (int e = tid; e < cnt; e += nthr) {
-        const unsigned long long v = wld(&bq[e]);
-        atomicAdd(reinterpret_cast<unsigned long long*>(&s_x[v >> 32]), (unsigned long long)(long long)(int)(v & 0xFFFFFFFFu));
-      }
-    }
+    absorb_bucket(slot, absorbed, min(s_bcnt[slot], a.cap), tid, nthr);
     const bool read_ring = (it < a.horizon) || ((s_dirty[slot >> 5] >> (slot & 31)) & 1u);
     __syncthreads();
     if (tid == 0) {
@@ -354,16 +391,28 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
     mask = 0;
     if (it + 1 < steps) {
       mask = decide(n + 1);
+      if (timing) { const long long t = wall_clock64(); ph[0] += t - tp0; tp0 = t; }
       publish(n + 1, mask);
     } else {
+      if (timing) { const long long t = wall_clock64(); ph[0] += t - tp0; tp0 = t; }
       __syncthreads();
     }
-    // ---- 3. drive of step n+1; wait for the instance's records of step n ---
-    //      (the polling wavefront draws its drive after the poll)
-    if (wave != nw - 1 && it + 1 < steps) drive(n + 1);
+    if (timing) { const long long t = wall_clock64(); ph[1] += t - tp0; tp0 = t; }
+    // ---- 3. while one wavefront waits for the instance's records of step n:
+    //      the drive of step n+1 and the entries step n+1's bucket already
+    //      holds (it gains more only in the delivery below), by the others --
+    const int nwork = (nw > 1) ? nthr - 64 : 0;   // threads that do not poll
+    const int sl1 = (int)((n + 1) & kRingMask);
+    absorbed = (it + 1 < steps && nwork > 0) ? min(s_bcnt[sl1], a.cap) : 0;
+    if (tid < nwork && it + 1 < steps) {
+      drive_quads(n + 1, tid, nwork);
+      absorb_bucket(sl1, 0, absorbed, tid, nwork);
+    }
+    if (timing) ph[5] += wall_clock64() - tp0;
     const unsigned long long tag = (unsigned long long)(n + 1) << 32;
     const unsigned long long tag16 = (unsigned long long)((n + 1) % 65535 + 1) << 48;
     if (wave == nw - 1) {
+      const long long tp_poll = (a.phase != nullptr) ? wall_clock64() : 0;
       long long t_poll = 0;          // the wall clock is read every 256 rounds only
       unsigned spins = 0;
       unsigned todo = 0;
@@ -420,9 +469,11 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
           break;
         }
       }
-      if (it + 1 < steps) drive(n + 1);
+      if (a.phase != nullptr && tid == nthr - 64) ph[6] += wall_clock64() - tp_poll;
+      if (nwork == 0 && it + 1 < steps) drive_quads(n + 1, tid, nthr);   // a one-wavefront block
     }
     __syncthreads();
+    if (timing) { const long long t = wall_clock64(); ph[2] += t - tp0; tp0 = t; }
     if (s_abort) break;
     // ---- 4. events of step n's spikes into the buckets ----------------------
     const int S = s_nids;
@@ -436,6 +487,7 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
         }
         __syncthreads();
       }
+      if (timing) { const long long t = wall_clock64(); ph[3] += t - tp0; tp0 = t; }
       const int k0 = (int)((long long)S * wave / nw), k1 = (int)((long long)S * (wave + 1) / nw);
       deliver(s_ids, k0, k1, n, &ev);
     } else {
@@ -446,7 +498,7 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
       int Sall;
       const int pre_h = bscan(c0 + c1, s_tmp[1], &Sall);
       __syncthreads();
-      int* s_pre = reinterpret_cast<int*>(s_x);      // the sums are all zero here: borrow their LDS
+      int* s_pre = s_hpre;
       if (2 * tid < Gi) s_pre[2 * tid] = pre_h;
       if (2 * tid + 1 < Gi) s_pre[2 * tid + 1] = pre_h + c0;
       if (tid == 0) s_pre[Gi] = Sall;
@@ -464,11 +516,16 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
         deliver(s_ids, k0, k1, n, &ev);
         __syncthreads();
       }
-      for (int k = tid; k <= Gi; k += nthr) s_pre[k] = 0;
     }
     if (ev) atomicAdd(&s_events, ev);
     __syncthreads();
+    if (timing) ph[4] += wall_clock64() - tp0;
   }
+  if (tid == 0 && a.phase) {
+    for (int k = 0; k < 6; ++k) a.phase[(size_t)g * 8 + k] += (unsigned long long)ph[k];
+    a.phase[(size_t)g * 8 + 7] += (unsigned long long)steps;
+  }
+  if (a.phase && tid == nthr - 64) a.phase[(size_t)g * 8 + 6] += (unsigned long long)ph[6];
   // ---- epilogue: state, counters; pending buckets summed into the ring -----
   for (int jl = tid; jl < Bg; jl += nthr) { const long long j = j0 + jl; p.y[j] = s_y[jl]; p.I[j] = s_I[jl]; p.r[j] = s_r[jl]; }
   if (tid < p.n_pops) p.wg_spikes[(size_t)g * p.n_pops + tid] += s_popcnt[tid];
@@ -476,14 +533,12 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
     p.raster_cnt[g] = rcnt;
     p.wg_events[g] += s_events;
   }
+  // (after an abandoned wait s_x may hold part of the next bucket: start from zero)
+  for (int jl = tid; jl < Bg; jl += nthr) s_x[jl] = 0;
+  __syncthreads();
   for (int sl = 0; sl < kRingSlots; ++sl) {
-    const int cnt = min(s_bcnt[sl], a.cap);
-    if (cnt == 0) continue;                      // uniform: every thread reads the same count
-    const unsigned long long* bq = bk + (size_t)sl * a.cap;
-    for (int e = tid; e < cnt; e += nthr) {
-      const unsigned long long v = wld(&bq[e]);
-      atomicAdd(reinterpret_cast<unsigned long long*>(&s_x[v >> 32]), (unsigned long long)(long long)(int)(v & 0xFFFFFFFFu));
-    }
+    if (s_bcnt[sl] == 0) continue;               // uniform: every thread reads the same count
+    absorb_bucket(sl, 0, min(s_bcnt[sl], a.cap), tid, nthr);
     __syncthreads();
     for (int jl = tid; jl < Bg; jl += nthr) {
       const long long v = s_x[jl];

@@ -179,6 +179,7 @@ struct BucketArgs {
   int cap;                     // entries per bucket (more: device atomics into the ring)
   long long wait_ticks;        // longest wait for one step's records (wall_clock64 ticks)
   int horizon;                 // ring slots ahead of the first step that may hold input at launch
+  unsigned long long* phase;   // optional [G*8]: summed wall_clock64 ticks per phase (nullptr: off)
 };
 constexpr int kBucketMaxProducers = 512;   // workgroups of one instance
 constexpr int kBucketMaxBlock = 512;       // threads per workgroup

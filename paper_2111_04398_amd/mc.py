@@ -341,7 +341,9 @@ class Network:
     def profile_phases(self, steps: int) -> dict:
         us = np.zeros(8, np.float64)
         _check(lib().mc_profile_phases(self.h, steps, us), "mc_profile_phases")
-        return dict(zip(["update", "publish", "wait", "gather", "deliver_d1", "total", "pending_delivery",
+        # deliver: the delay-1 events (LDS window) or every event of the step (buckets);
+        # drive_pending: drive of the next step (and pending delivery in the LDS window)
+        return dict(zip(["update", "publish", "wait", "gather", "deliver", "total", "drive_pending",
                          "poll"], us.tolist()))
 
     def phase_table(self) -> np.ndarray:

@@ -497,7 +497,12 @@ def test_autotuner_and_phase_profile_keep_the_trajectory():
     ph = net.profile_phases(300)
     assert ph["total"] > 0 and net.phase_table().shape == (net.persist_shape()["workgroups"], 8)
     net.simulate(200)
-    o.run(1200)
+    net.set_launch(scheme=3, block=256, neurons_per_wg=0, steps_per_graph=100)
+    ph = net.profile_phases(200)
+    assert ph["total"] > 0 and ph["deliver"] > 0
+    assert net.phase_table().shape == (net.persist_shape()["workgroups"], 8)
+    net.simulate(100)
+    o.run(1500)
     assert_same(net, o, what=f"tuned {best}")
 
 
