@@ -193,6 +193,24 @@ int mc_build_network(const mc_config* cfg, mc_net** out);
  * OOM (raster growth). */
 int mc_simulate(mc_net* net, int64_t steps);
 
+/* For callers that cannot allocate memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): mc_simulate for the
+ * persistent scheme (mc_set_launch scheme 1) without any allocation -- no
+ * hipMalloc or hipFree, no graph instantiation, no raster drain.  The
+ * kernels' spike records and side array (the scratch mc_simulate keeps in
+ * library-allocated memory) come from a file-scope device array of about
+ * 4.1 MiB (room for 512 workgroups of 512 targets) that each GPU holds until
+ * the process ends.  The records are cleared by a kernel at the start of
+ * every call.  Every call on one GPU shares that GPU's array, so calls that
+ * overlap on one GPU (two networks on concurrent streams) race: serialize
+ * them.  Same trajectory, raster and counters as mc_simulate(steps).
+ * Errors: STATE (another scheme, or a host-only/failed handle), RANGE (a
+ * persistent shape beyond the scratch, step count beyond int32),
+ * BUFFER_TOO_SMALL (more steps than the raster holds without a drain: call
+ * mc_reserve first), INVALID_ARG (steps < 0, or the network's device is not
+ * the current one), HIP.  Asynchronous on the network's stream. */
+int mc_simulate_noalloc(mc_net* net, int64_t steps);
+
 /* Copies the recorded spikes (the raster of Supplementary Fig. 1) with step
  * in [step_begin, step_end) into caller-owned host arrays, sorted by step,
  * then neuron id.  If more than

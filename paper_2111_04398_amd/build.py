@@ -42,7 +42,7 @@ def build(verbose: bool = False) -> str:
     objs.append(o)
     hipcc = os.path.join(ROCM, "bin", "hipcc")
     for src in ("mc_kernels.hip", "mc_persist.hip", "mc_replay.hip", "mc_adjoint.hip", "mc_owner.hip", "mc_bucket.hip", "mc_construct.hip",
-                "mc_api.hip"):
+                "mc_noalloc.hip", "mc_api.hip"):
         o = os.path.join(BUILD, src.replace(".hip", ".o"))
         out = _run([hipcc, *HIP_FLAGS, *inc, "-c", os.path.join(CSRC, src), "-o", o])
         if verbose and out.strip():

@@ -1044,6 +1044,46 @@ int mc_simulate(mc_net* n, int64_t steps) {
   return MC_OK;
 }
 
+int mc_simulate_noalloc(mc_net* n, int64_t steps) {
+  if (!device_ready(n)) return set_error(MC_ERR_STATE, "handle is host-only, failed or NULL");
+  if (steps < 0) return set_error(MC_ERR_INVALID_ARG, "steps < 0");
+  if (n->launch.scheme != MC_SCHEME_PERSISTENT_LDS)
+    return set_error(MC_ERR_STATE, "mc_simulate_noalloc runs the persistent scheme only (mc_set_launch scheme 1)");
+  if (n->pG > kPersistMaxBlock || n->pB > kPersistMaxB)
+    return set_error(MC_ERR_RANGE, "persistent shape beyond the scratch (512 workgroups of 512 targets)");
+  if (n->step + steps > 2147483647LL) return set_error(MC_ERR_RANGE, "step count beyond int32 raster steps");
+  const int64_t room = n->cap_steps - n->steps_since_drain;
+  if (steps > room)
+    return set_error(MC_ERR_BUFFER_TOO_SMALL, "the raster has room for " + std::to_string(room) +
+                                                  " more steps without a drain; call mc_reserve or mc_get_spikes first");
+  int cur = -1;
+  HIP_TRY(hipGetDevice(&cur));
+  if (cur != n->device) return set_error(MC_ERR_INVALID_ARG, "the network's device is not the current device");
+  unsigned long long* rec = nullptr;
+  int* pub = nullptr;
+  HIP_TRY(noalloc_scratch(n->device, &rec, &pub));
+  HIP_TRY(hipEventRecord(n->ev0, n->stream));
+  n->launches_timed = 0;
+  n->steps_timed = 0;
+  HIP_TRY(launch_clear_records(rec, persist_flag_words(n->pG), n->stream));
+  const DevNet p = n->dev();
+  PersistArgs a = n->persist();
+  a.flags = rec;
+  a.pub = pub;
+  int rc;
+  for (int64_t left = steps; left > 0;) {
+    const int chunk = (int)std::min<int64_t>(left, 1 << 20);
+    if ((rc = launch_event(n, true, chunk)) != MC_OK) return rc;
+    HIP_TRY(launch_persist(p, a, chunk, n->launch.block, n->stream));
+    if ((rc = launch_event(n, false, chunk)) != MC_OK) return rc;
+    left -= chunk;
+  }
+  n->steps_since_drain += steps;
+  n->step += steps;
+  HIP_TRY(hipEventRecord(n->ev1, n->stream));
+  return MC_OK;
+}
+
 int mc_last_kernel_ms(mc_net* n, double* ms_out, int64_t* launches_out, int64_t* steps_out) {
   if (!device_ready(n) || !ms_out || !launches_out || !steps_out) return set_error(MC_ERR_INVALID_ARG, "bad handle or NULL output");
   HIP_TRY(hipEventSynchronize(n->ev1));

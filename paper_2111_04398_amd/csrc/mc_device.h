@@ -110,6 +110,13 @@ hipError_t persist_static_lds(size_t* bytes);
 hipError_t persist_occupancy(int block, size_t lds, int* blocks_per_cu);
 hipError_t persist_set_lds_limit(size_t lds);
 hipError_t launch_persist(const DevNet& p, const PersistArgs& a, int steps, int block, hipStream_t s);
+// Scratch of the allocation-free entry point (mc_noalloc.hip): spike records
+// (noalloc_record_words() words, room for 512 workgroups) and the side array
+// (512 x kRecSlots x 512 ints) of this device; and a record clear by kernel.
+size_t noalloc_scratch_bytes();
+size_t noalloc_record_words();
+hipError_t noalloc_scratch(int device, unsigned long long** records, int** pub);
+hipError_t launch_clear_records(unsigned long long* records, size_t words, hipStream_t s);
 hipError_t launch_build_blk(const int64_t* row_ptr, const int32_t* tgt, long long n_pad, int G, const int* bstart,
                             long long* blk, hipStream_t s);
 

@@ -90,7 +90,7 @@ EXPORTS = [
     "mc_get_counters", "mc_set_launch", "mc_get_launch", "mc_tune", "mc_last_simulate_ms", "mc_reserve",
     "mc_save_state", "mc_load_state", "mc_set_weights", "mc_stream", "mc_profile_phases", "mc_replay_delivery",
     "mc_atomic_rate", "mc_last_adjoint_ms", "mc_get_persist_shape", "mc_get_phase_table", "mc_apply_gradient",
-    "mc_last_kernel_ms", "mc_probe_stream", "mc_probe_atomics", "mc_probe_exchange",
+    "mc_last_kernel_ms", "mc_probe_stream", "mc_probe_atomics", "mc_probe_exchange", "mc_simulate_noalloc",
 ]
 
 _lib = None
@@ -115,6 +115,7 @@ def lib() -> C.CDLL:
     P = np.ctypeslib.ndpointer
     L.mc_build_network.argtypes = [C.POINTER(mc_config), C.POINTER(vp)]
     L.mc_simulate.argtypes = [vp, i64]
+    L.mc_simulate_noalloc.argtypes = [vp, i64]
     L.mc_get_spikes.argtypes = [vp, i64, i64, vp, vp, i64, C.POINTER(i64)]
     L.mc_adjoint.argtypes = [vp, C.POINTER(mc_adjoint_config), vp, C.POINTER(f64)]
     L.mc_free.argtypes = [vp]
@@ -237,6 +238,11 @@ class Network:
     # --- the simulation calls -------------------------------------------
     def simulate(self, steps: int):
         _check(lib().mc_simulate(self.h, int(steps)), "mc_simulate")
+
+    def simulate_noalloc(self, steps: int):
+        """mc_simulate_noalloc: the persistent scheme without any allocation
+        (reserve the raster first)."""
+        _check(lib().mc_simulate_noalloc(self.h, int(steps)), "mc_simulate_noalloc")
 
     def spikes(self, begin: int = 0, end: int = 2**31 - 1):
         cnt = C.c_int64()
