@@ -51,6 +51,7 @@
 
 #include <algorithm>
 
+#include <hip/hip_ext.h>
 #include "mc_device.h"
 
 namespace mc {
@@ -576,9 +577,13 @@ size_t bucket_lds_bytes(int B) {
   return bucket_sum_slots(B) * sizeof(long long) + (size_t)B * (8 + 8 + 4 + 1 + 1);
 }
 
-hipError_t launch_bucket(const DevNet& p, const BucketArgs& a, int steps, int block, hipStream_t s) {
+hipError_t launch_bucket(const DevNet& p, const BucketArgs& a, int steps, int block, hipStream_t s, hipEvent_t t0,
+                         hipEvent_t t1) {
   if (a.Q < 1 || 4 * a.Q * block < a.B || 4 * a.Q > 64) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_bucket, dim3(a.G), dim3(block), bucket_lds_bytes(a.B), s, p, a, steps);
+  if (t0 || t1)
+    hipExtLaunchKernelGGL(k_bucket, dim3(a.G), dim3(block), bucket_lds_bytes(a.B), s, t0, t1, 0, p, a, steps);
+  else
+    hipLaunchKernelGGL(k_bucket, dim3(a.G), dim3(block), bucket_lds_bytes(a.B), s, p, a, steps);
   return hipGetLastError();
 }
 

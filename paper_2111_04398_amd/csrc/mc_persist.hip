@@ -47,6 +47,7 @@
 // kernel sets error bit 2 and every workgroup leaves the loop.
 #pragma clang fp contract(off)
 
+#include <hip/hip_ext.h>
 #include "mc_device.h"
 
 namespace mc {
@@ -882,9 +883,13 @@ hipError_t persist_occupancy(int block, size_t lds, int* blocks_per_cu) {
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_persist, block, lds);
 }
 
-hipError_t launch_persist(const DevNet& p, const PersistArgs& a, int steps, int block, hipStream_t s) {
+hipError_t launch_persist(const DevNet& p, const PersistArgs& a, int steps, int block, hipStream_t s, hipEvent_t t0,
+                          hipEvent_t t1) {
   const size_t lds = persist_lds_bytes(a.G, a.B, a.DL);
-  hipLaunchKernelGGL(k_persist, dim3(a.G), dim3(block), lds, s, p, a, steps);
+  if (t0 || t1)
+    hipExtLaunchKernelGGL(k_persist, dim3(a.G), dim3(block), lds, s, t0, t1, 0, p, a, steps);
+  else
+    hipLaunchKernelGGL(k_persist, dim3(a.G), dim3(block), lds, s, p, a, steps);
   return hipGetLastError();
 }
 
