@@ -29,7 +29,10 @@
 //
 // Spike exchange: workgroup g publishes a record per step (four per
 // workgroup, by step mod 4, so a record is never rewritten while a consumer
-// one step behind may still read it).  Word 0 = tag16 << 48 | count
+// one step behind may still read it).  Compaction is one ballot per
+// wavefront (kept in LDS by step parity): a spike's position is the number
+// of spikes of lower threads, and each spiking thread stores its own id into
+// the record or the side array.  Word 0 = tag16 << 48 | count
 // << 36 | the block-local indices (9 bits each) of the first four spikes,
 // with tag16 = (step + 1) mod 65535 + 1 (never 0, distinct for consecutive
 // steps); words 1..3 = (step + 1) << 32 | id of spikes 5..7.  About four in
@@ -43,8 +46,9 @@
 // the seventh are written to a side array before word 0 (with a wait for
 // their completion), so they are visible once word 0 is.  All of these are
 // device-scope atomic accesses (coherent at the memory side), so the step
-// needs no L2 writeback or invalidate.  Every wait is bounded in time (wall clock); on timeout the
-// kernel sets error bit 2 and every workgroup leaves the loop.
+// needs no L2 writeback or invalidate.  Every wait is bounded in time (wall
+// clock); on timeout the kernel sets error bit 2 and every workgroup leaves
+// the loop.
 #pragma clang fp contract(off)
 
 #include <hip/hip_ext.h>
@@ -262,7 +266,7 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
   extern __shared__ __align__(16) unsigned char s_raw[];
   __shared__ uint64_t s_table[kMaxPops * kTableLen];
   __shared__ int s_tmp[2][16];
-  __shared__ int s_local[kPersistMaxB];
+  __shared__ uint64_t s_mask[2][kPersistMaxBlock / 64];   // spike ballots per wavefront, by step parity
   __shared__ int s_cnt[kPersistMaxBlock];   // spike count of every producer in the current step
   __shared__ int s_abort, s_last;
   __shared__ int s_nids, s_nbig;                 // ids listed by the poller this step; producers with more
@@ -290,6 +294,7 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
   const bool overlap = nw > 1;
   const int nwd = overlap ? nw - 1 : nw;                             // wavefronts working while polling
   const bool pollw = overlap ? (wave == nw - 1) : true;
+  auto par_m = [](long long m) { return (int)(m & 1); };
   const Block blk{acc, fbits, a.B, a.BW, DL, j0};
   auto bounds_of = [&](int par_) {
     return [=](int k, long long* lo, int* len) { *lo = s_lo[par_ * kListCap + k]; *len = s_len[par_ * kListCap + k]; };
@@ -429,30 +434,48 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
     if (pop != 0xFFu) I = p.P11 * I + (double)x_int * 0x1p-16;
   };
   auto publish = [&](long long m, int spiked) {   // compaction (ascending ids), record of step m, raster
-    int nloc;
-    const int pre = block_exscan(spiked, s_tmp[0], &nloc);
-    if (spiked) s_local[pre] = (int)(j0 + tid);
+    // one ballot per wavefront; a spike's position is the count of spikes of
+    // lower threads (thread order = id order)
+    const uint64_t bal = __ballot(spiked);
+    if ((tid & 63) == 0) s_mask[par_m(m)][wave] = bal;
     __syncthreads();
+    const uint64_t* msk = s_mask[par_m(m)];
+    int nloc = 0, pos = 0;
+    for (int w = 0; w < nw; ++w) {
+      const int c = __popcll(msk[w]);
+      pos += (w < wave) ? c : 0;
+      nloc += c;
+    }
+    pos += __popcll(bal & ((tid & 63) ? (~0ull >> (64 - (tid & 63))) : 0ull));
     const unsigned long long tag = (unsigned long long)(m + 1) << 32;
     const unsigned long long tag16 = (unsigned long long)((m + 1) % 65535 + 1) << 48;
     const size_t rec = (size_t)g * kRecSlots + (size_t)(m % kRecSlots);
     unsigned long long* myrec = a.flags + rec * kPersistFlagStride;
-    for (int k = tid; k < nloc; k += nthr) {
-      const int id = s_local[k];
-      if (k >= kInline) st_dev(&a.pub[rec * a.B + k], id);
-      if (rcnt + nloc <= p.raster_cap) p.raster[(size_t)g * p.raster_cap + rcnt + k] = make_int2((int)m, id);
+    const bool fits = rcnt + nloc <= p.raster_cap;
+    if (spiked) {
+      const int id = (int)(j0 + tid);
+      if (pos >= kInline) st_dev(&a.pub[rec * a.B + pos], id);
+      else if (pos >= kW0Ids) st_dev(&myrec[1 + pos - kW0Ids], tag | (unsigned)id);
+      if (fits) p.raster[(size_t)g * p.raster_cap + rcnt + pos] = make_int2((int)m, id);
     }
     if (nloc > kInline) {                   // side-array ids complete before word 0
       __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
     }
-    if (tid >= kW0Ids && tid < min(nloc, kInline)) st_dev(&myrec[1 + tid - kW0Ids], tag | (unsigned)s_local[tid]);
-    if (tid == 0) {
-      unsigned long long w = tag16 | (unsigned long long)nloc << 36;
-      for (int k = 0; k < min(nloc, kW0Ids); ++k) w |= (unsigned long long)(s_local[k] - j0) << (9 * k);
-      st_dev(&myrec[0], w);
+    if (tid == 0) {                         // word 0: count and the local indices of the first four spikes
+      unsigned long long w0 = tag16 | (unsigned long long)nloc << 36;
+      int f = 0;
+      for (int w = 0; w < nw && f < kW0Ids; ++w) {
+        uint64_t mm = msk[w];
+        while (mm && f < kW0Ids) {
+          w0 |= (unsigned long long)(64 * w + __builtin_ctzll(mm)) << (9 * f);
+          mm &= mm - 1;
+          ++f;
+        }
+      }
+      st_dev(&myrec[0], w0);
     }
-    if (rcnt + nloc <= p.raster_cap) rcnt += nloc;
+    if (fits) rcnt += nloc;
     else if (tid == 0) atomicOr(p.overflow, 1u);
   };
 
