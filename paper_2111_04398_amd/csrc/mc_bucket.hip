@@ -3,7 +3,7 @@
 // target-owner delivery into per-workgroup delay buckets.
 //
 // Every workgroup owns a block of at most B target neurons of one instance
-// (Q consecutive quads per thread; the state in LDS) and exchanges spike
+// (every nthr-th target per thread; the state in LDS) and exchanges spike
 // records only with
 // the workgroups of its own instance: instances never interact, so a batch
 // runs as independent groups inside one launch and a slow instance delays
@@ -123,6 +123,7 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
   __shared__ int s_first[kBInline];             // ids of the step's first spikes (record)
   __shared__ int s_cnt[kBucketMaxProducers];    // spike count of each producer of the instance this step
   __shared__ int s_hpre[kBucketMaxProducers + 1];  // their prefix (listing of a step beyond the LDS list)
+  __shared__ int s_kcnt[64 * (kBucketMaxBlock / 64)];  // spikes per (target round, wavefront) of a step
   __shared__ int s_ids[kBListCap];
   __shared__ int2 s_big[kBBigCap];
   __shared__ int s_nids, s_nbig, s_abort, s_last;
@@ -165,9 +166,11 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
   }
   __syncthreads();
 
-  // thread t owns the a.Q quads from local target 4 t Q on (those < Bg):
-  // ascending ids follow the thread order, and each quad takes one Philox block
-  const int lt0 = min(4 * tid * a.Q, Bg), lt1 = min(lt0 + 4 * a.Q, Bg);
+  // thread t owns local targets t, t + nthr, t + 2 nthr, ... (K rounds):
+  // the lanes of a wavefront touch consecutive LDS words, with no bank
+  // conflicts (consecutive targets per thread put the lanes 64 bytes apart).
+  // Ascending ids go round by round, threads in order.
+  const int K = (Bg + nthr - 1) / nthr;
   // Poisson counts of quads q0, q0 + dq, ... at step m (one Philox block per quad)
   auto drive_quads = [&](long long m, int q0, int dq) {
     for (int q4 = 4 * q0; q4 < Bg; q4 += 4 * dq) {
@@ -192,10 +195,10 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
 
-  auto decide = [&](long long m) -> uint64_t {   // spike decision of step m: bit k = local target lt0 + k spiked
+  auto decide = [&](long long m) -> uint64_t {   // spike decision of step m: bit k = local target tid + k nthr spiked
     if (p.ck_y) {
       if (ck_phase == 0 && ck_seg >= 0 && ck_seg < p.ck_count) {
-        for (int jl = lt0; jl < lt1; ++jl) {
+        for (int jl = tid; jl < Bg; jl += nthr) {
           const size_t at = (size_t)ck_seg * p.ring_stride + j0 + jl;
           p.ck_y[at] = s_y[jl]; p.ck_I[at] = s_I[jl]; p.ck_r[at] = s_r[jl];
         }
@@ -203,7 +206,9 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
       if (++ck_phase == p.ck_every) { ck_phase = 0; ++ck_seg; }
     }
     uint64_t mask = 0;
-    for (int jl = lt0; jl < lt1; ++jl) {
+    for (int k = 0; k < K; ++k) {
+      const int jl = tid + k * nthr;
+      if (jl >= Bg) break;
       const unsigned pk = s_pop[jl];
       if (pk == 0xFFu) continue;
       const int r = s_r[jl];
@@ -217,7 +222,7 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
       if (free_ && y >= p.theta) {
         s_y[jl] = p.y_reset;
         s_r[jl] = p.ref_steps;
-        mask |= 1ull << (jl - lt0);
+        mask |= 1ull << k;
         atomicAdd(&s_popcnt[pk], 1ull);
       } else {
         s_y[jl] = y;
@@ -227,19 +232,50 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
     return mask;
   };
   auto publish = [&](long long m, uint64_t mask) {   // compaction (ascending ids), record of step m, raster
-    int nloc;
-    const int pre = bscan(__popcll(mask), s_tmp[0], &nloc);
+    // spikes per (round, wavefront) from one ballot each, then every
+    // wavefront scans those counts itself (round-major: ascending ids), 64
+    // cells per pass; a spike's position is the spikes before its cell plus
+    // those of lower lanes in it
+    const uint64_t lower = lane ? (~0ull >> (64 - lane)) : 0ull;
+    for (int k = 0; k < K; ++k) {
+      const uint64_t bal = __ballot((int)((mask >> k) & 1u));
+      if (lane == 0) s_kcnt[k * nw + wave] = __popcll(bal);
+    }
+    __syncthreads();
+    const int cells = K * nw;
+    int nloc = 0;
+    for (int c = lane; c < cells; c += 64) nloc += s_kcnt[c];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) nloc += __shfl_xor(nloc, o, 64);
     const unsigned long long tag = (unsigned long long)(m + 1) << 32;
     const unsigned long long tag16 = (unsigned long long)((m + 1) % 65535 + 1) << 48;
     const size_t rec = (size_t)g * kRecSlots + (size_t)(m % kRecSlots);
     unsigned long long* myrec = a.flags + rec * kPersistFlagStride;
     const bool fits = rcnt + nloc <= p.raster_cap;
-    int pos = pre;
-    for (uint64_t mm = mask; mm; mm &= mm - 1, ++pos) {
-      const int id = (int)(j0 + lt0 + __builtin_ctzll(mm));
-      if (pos < kBInline) s_first[pos] = id;
-      else bst(&a.pub[rec * B + pos], id);
-      if (fits) p.raster[(size_t)g * p.raster_cap + rcnt + pos] = make_int2((int)m, id);
+    int carry = 0;
+    for (int c0 = 0; c0 < cells; c0 += 64) {
+      const int v = (c0 + lane < cells) ? s_kcnt[c0 + lane] : 0;
+      int x = v;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+      }
+      const int excl = carry + x - v;
+      carry += __shfl(x, 63, 64);
+      for (int k = 0; k < K; ++k) {
+        const int idx = k * nw + wave;
+        if (idx < c0 || idx >= c0 + 64) continue;   // uniform in the wavefront
+        const int pre = __shfl(excl, idx - c0, 64);
+        const uint64_t bal = __ballot((int)((mask >> k) & 1u));
+        if ((mask >> k) & 1u) {
+          const int pos = pre + __popcll(bal & lower);
+          const int id = (int)(j0 + tid + k * nthr);
+          if (pos < kBInline) s_first[pos] = id;
+          else bst(&a.pub[rec * B + pos], id);
+          if (fits) p.raster[(size_t)g * p.raster_cap + rcnt + pos] = make_int2((int)m, id);
+        }
+      }
     }
     if (nloc > kBInline) __builtin_amdgcn_s_waitcnt(0);   // side-array ids complete before word 0
     __syncthreads();
@@ -374,7 +410,7 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
       s_nids = 0;
       s_nbig = 0;
     }
-    for (int jl = lt0; jl < lt1; ++jl) {
+    for (int jl = tid; jl < Bg; jl += nthr) {
       long long x_int = s_x[jl];
       s_x[jl] = 0;
       if (read_ring) {
