@@ -379,15 +379,17 @@ int drain(mc_net* n, hipEvent_t upto = nullptr) {
   HIP_TRY(hipMemsetAsync(n->d_raster_cnt, 0, sizeof(long long) * n->n_wg, s));
   HIP_TRY(hipStreamSynchronize(s));
   // Workgroup g's segment holds its own neurons, whose ids all exceed those
-  // of workgroups < g, by step and ascending id within a step; a stable
-  // counting sort by step over the segments in order is therefore the sort
-  // by (step, id).
+  // of workgroups < g, by step; a stable counting sort by step over the
+  // segments in order groups a step's spikes by workgroup.  The persistent
+  // and step kernels write a step's ids in ascending order, the bucket
+  // kernel in any order: a step whose ids are not ascending is sorted.
   if (total > 0) {
     int smin = buf[0].x, smax = buf[0].x;
     for (const int2& e : buf) { smin = std::min(smin, e.x); smax = std::max(smax, e.x); }
     std::vector<size_t> pos((size_t)(smax - smin) + 2, 0);
     for (const int2& e : buf) ++pos[(size_t)(e.x - smin) + 1];
     for (size_t k = 1; k < pos.size(); ++k) pos[k] += pos[k - 1];
+    const std::vector<size_t> first(pos);
     const size_t base = n->r_step.size();
     n->r_step.resize(base + (size_t)total);
     n->r_id.resize(base + (size_t)total);
@@ -395,6 +397,10 @@ int drain(mc_net* n, hipEvent_t upto = nullptr) {
       const size_t k = base + pos[(size_t)(e.x - smin)]++;
       n->r_step[k] = e.x;
       n->r_id[k] = (int32_t)n->dense_of(e.y);
+    }
+    for (size_t k = 0; k + 1 < first.size(); ++k) {
+      auto b = n->r_id.begin() + (std::ptrdiff_t)(base + first[k]), e = n->r_id.begin() + (std::ptrdiff_t)(base + first[k + 1]);
+      if (!std::is_sorted(b, e)) std::sort(b, e);
     }
   }
   n->steps_since_drain = 0;

@@ -123,7 +123,7 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
   __shared__ int s_first[kBInline];             // ids of the step's first spikes (record)
   __shared__ int s_cnt[kBucketMaxProducers];    // spike count of each producer of the instance this step
   __shared__ int s_hpre[kBucketMaxProducers + 1];  // their prefix (listing of a step beyond the LDS list)
-  __shared__ int s_kcnt[64 * (kBucketMaxBlock / 64)];  // spikes per (target round, wavefront) of a step
+  __shared__ int s_npub;                       // spikes of the step being published
   __shared__ int s_ids[kBListCap];
   __shared__ int2 s_big[kBBigCap];
   __shared__ int s_nids, s_nbig, s_abort, s_last;
@@ -156,7 +156,7 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
   for (int k = tid; k < kRingSlots; k += nthr) s_bcnt[k] = 0;
   if (tid < kRingSlots / 32) s_dirty[tid] = 0;
   for (int k = tid; k < kBucketMaxProducers; k += nthr) s_cnt[k] = 0;
-  if (tid == 0) { s_abort = 0; s_events = 0; }
+  if (tid == 0) { s_abort = 0; s_events = 0; s_npub = 0; }
   if (tid < kMaxPops) s_popcnt[tid] = 0;
   for (int jl = tid; jl < Bg; jl += nthr) {
     const long long j = j0 + jl;
@@ -231,51 +231,33 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
     }
     return mask;
   };
-  auto publish = [&](long long m, uint64_t mask) {   // compaction (ascending ids), record of step m, raster
-    // spikes per (round, wavefront) from one ballot each, then every
-    // wavefront scans those counts itself (round-major: ascending ids), 64
-    // cells per pass; a spike's position is the spikes before its cell plus
-    // those of lower lanes in it
-    const uint64_t lower = lane ? (~0ull >> (64 - lane)) : 0ull;
-    for (int k = 0; k < K; ++k) {
-      const uint64_t bal = __ballot((int)((mask >> k) & 1u));
-      if (lane == 0) s_kcnt[k * nw + wave] = __popcll(bal);
-    }
-    __syncthreads();
-    const int cells = K * nw;
-    int nloc = 0;
-    for (int c = lane; c < cells; c += 64) nloc += s_kcnt[c];
+  auto publish = [&](long long m, uint64_t mask) {   // compaction, record of step m, raster
+    // slots in any order (delivery sums integers; the raster of a step is
+    // ordered on the host): a lane-prefix of the spike counts, one LDS atomic
+    // per wavefront for its base
+    const int c = __popcll(mask);
+    int x = c;
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) nloc += __shfl_xor(nloc, o, 64);
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    int wbase = 0;
+    if (lane == 63 && x > 0) wbase = atomicAdd(&s_npub, x);
+    wbase = __shfl(wbase, 63, 64);
+    __syncthreads();
+    const int nloc = s_npub;
     const unsigned long long tag = (unsigned long long)(m + 1) << 32;
     const unsigned long long tag16 = (unsigned long long)((m + 1) % 65535 + 1) << 48;
     const size_t rec = (size_t)g * kRecSlots + (size_t)(m % kRecSlots);
     unsigned long long* myrec = a.flags + rec * kPersistFlagStride;
     const bool fits = rcnt + nloc <= p.raster_cap;
-    int carry = 0;
-    for (int c0 = 0; c0 < cells; c0 += 64) {
-      const int v = (c0 + lane < cells) ? s_kcnt[c0 + lane] : 0;
-      int x = v;
-#pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-      }
-      const int excl = carry + x - v;
-      carry += __shfl(x, 63, 64);
-      for (int k = 0; k < K; ++k) {
-        const int idx = k * nw + wave;
-        if (idx < c0 || idx >= c0 + 64) continue;   // uniform in the wavefront
-        const int pre = __shfl(excl, idx - c0, 64);
-        const uint64_t bal = __ballot((int)((mask >> k) & 1u));
-        if ((mask >> k) & 1u) {
-          const int pos = pre + __popcll(bal & lower);
-          const int id = (int)(j0 + tid + k * nthr);
-          if (pos < kBInline) s_first[pos] = id;
-          else bst(&a.pub[rec * B + pos], id);
-          if (fits) p.raster[(size_t)g * p.raster_cap + rcnt + pos] = make_int2((int)m, id);
-        }
-      }
+    int pos = wbase + x - c;
+    for (uint64_t mm = mask; mm; mm &= mm - 1, ++pos) {
+      const int id = (int)(j0 + tid + __builtin_ctzll(mm) * nthr);
+      if (pos < kBInline) s_first[pos] = id;
+      else bst(&a.pub[rec * B + pos], id);
+      if (fits) p.raster[(size_t)g * p.raster_cap + rcnt + pos] = make_int2((int)m, id);
     }
     if (nloc > kBInline) __builtin_amdgcn_s_waitcnt(0);   // side-array ids complete before word 0
     __syncthreads();
@@ -284,6 +266,7 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
       unsigned long long w = tag16 | (unsigned long long)nloc << 36;
       for (int k = 0; k < min(nloc, kBW0Ids); ++k) w |= (unsigned long long)(s_first[k] - j0) << (12 * k);
       bst(&myrec[0], w);
+      s_npub = 0;                              // read by every thread before the barrier above
     }
     if (fits) rcnt += nloc;
     else if (tid == 0) atomicOr(p.overflow, 1u);
