@@ -25,6 +25,7 @@ MC_ERR_INVALID_ARG = -1
 MC_ERR_BUFFER_TOO_SMALL = -6
 MC_ERR_MISMATCH = -8
 MC_ERR_RANGE = -2
+MC_ERR_STATE = -5
 MC_ERR_TIMEOUT = -9
 MC_MAX_POPS = 16
 RING_SLOTS = 128

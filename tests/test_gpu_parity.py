@@ -573,3 +573,35 @@ def test_tune_cache_skips_the_second_tuning(tmp_path, monkeypatch):
     b.simulate(500)
     o.run(500)
     assert_same(b, o, what="cached launch")
+
+
+def test_probes_and_launch_timing_leave_the_trajectory():
+    """The memory probes (streaming read, slot-major atomics, the empty
+    persistent exchange) measure within physical bounds and leave the
+    network untouched; the persistent kernel's launches are timed one by
+    one (graph replays and the direct remainder) and their summed time lies
+    inside the simulate span.  The trajectory stays the oracle's."""
+    w = workloads.balanced()
+    net, o = mc.Network(w), oracle.Oracle(w.to_dict())
+    net.simulate(100)
+    with pytest.raises(mc.MCError) as e:               # the exchange probe needs a persistent scheme
+        net.probe_exchange(100)
+    assert e.value.code == mc.MC_ERR_STATE
+    assert net.last_kernel_ms()["launches"] == 0        # step kernels: no persistent launch
+    gbs = net.probe_stream(256 << 20)
+    assert 500.0 < gbs < 8500.0, gbs
+    for pattern in (0, 1):
+        rate = net.probe_atomics(128, pattern)
+        assert 1.0 < rate < 1000.0, rate                # 1e9 adds/s
+    for scheme, block in ((1, 512), (3, 256)):
+        net.set_launch(scheme=scheme, block=block, neurons_per_wg=0, steps_per_graph=100)
+        floor = net.probe_exchange(500) if scheme == 1 else None   # the LDS-window scheme's shape only
+        net.reserve(250)
+        net.simulate(250)                               # two graph replays of 100 steps, one direct launch of 50
+        k = net.last_kernel_ms()
+        assert k["launches"] == 3 and k["steps"] == 250
+        assert 0.0 < k["ms"] <= net.last_simulate_ms()
+        if floor is not None:
+            assert 0.0 < floor * 250 * 1e-3 <= k["ms"] * 1.5, (floor, k)
+    o.run(600)
+    assert_same(net, o, what="after probes and timed launches")
