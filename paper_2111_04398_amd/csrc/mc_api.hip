@@ -240,7 +240,6 @@ struct mc_net {
   BucketArgs bucket() const {
     BucketArgs a{};
     a.G = own_blocks; a.B = wg_neurons;
-    a.Q = (wg_neurons + 4 * launch.block - 1) / (4 * launch.block);
     a.bt0 = d_bt0; a.binst = d_binst; a.blb = d_blb; a.ifb = d_ifb; a.boff = d_boff; a.blk2 = d_blk2;
     a.flags = d_flags; a.pub = d_pub; a.bk = d_bk; a.cap = bk_cap;
     a.wait_ticks = (long long)wall_khz * 1000 * kWaitSeconds;

@@ -598,7 +598,8 @@ size_t bucket_lds_bytes(int B) {
 
 hipError_t launch_bucket(const DevNet& p, const BucketArgs& a, int steps, int block, hipStream_t s, hipEvent_t t0,
                          hipEvent_t t1) {
-  if (a.Q < 1 || 4 * a.Q * block < a.B || 4 * a.Q > 64) return hipErrorInvalidValue;
+  // a thread owns at most 64 targets (its spike mask), so B <= 64 threads
+  if (a.B < 4 || a.B > 64 * block) return hipErrorInvalidValue;
   if (t0 || t1)
     hipExtLaunchKernelGGL(k_bucket, dim3(a.G), dim3(block), bucket_lds_bytes(a.B), s, t0, t1, 0, p, a, steps);
   else

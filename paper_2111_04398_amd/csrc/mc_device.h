@@ -176,7 +176,6 @@ hipError_t launch_adj_gather(const int4* srcs, const long long* first, int nsrc,
 struct BucketArgs {
   int G;                       // workgroups (all co-resident)
   int B;                       // most targets of one workgroup (multiple of 4, <= kBucketMaxB)
-  int Q;                       // quads per thread (4 Q block >= B, 4 Q <= 64)
   const int* bt0;              // [G+1]
   const int* binst;            // [G]
   const int* blb;              // [G]
