@@ -51,6 +51,7 @@
 // the loop.
 #pragma clang fp contract(off)
 
+#include <algorithm>
 #include <hip/hip_ext.h>
 #include "mc_device.h"
 
@@ -262,6 +263,11 @@ __device__ __forceinline__ void wave_near(const PersistArgs& a, const Block& b, 
 
 // LDS (dynamic): acc[DL*B] i64 | fbits[128*BW] u32 | s_pre[G+1] | s_inl[G*7] | s_ids[2][kListCap]
 //                | s_len[2][kListCap] | s_lo[2][kListCap] i64
+// kRec: the adjoint's forward recording (input x and state checkpoints);
+// kTime: phase timestamps.  Plain simulation runs the instance with neither,
+// whose smaller register footprint shortens the step (fewer scalar
+// registers spilled to vector lanes).
+template <bool kRec, bool kTime>
 __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistArgs a, int steps) {
   extern __shared__ __align__(16) unsigned char s_raw[];
   __shared__ uint64_t s_table[kMaxPops * kTableLen];
@@ -367,7 +373,7 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
   // checkpoint schedule of an adjoint's forward: segment of step n0 and n0's
   // phase in it (a checkpoint is due at phase 0)
   long long ck_seg = -1, ck_phase = 1;
-  if (p.ck_y) {
+  if (kRec && p.ck_y) {
     const long long k = n0 - p.ck_step0;
     ck_seg = (k >= 0) ? k / p.ck_every : -1;
     ck_phase = (k >= 0) ? k % p.ck_every : 1;
@@ -389,7 +395,7 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
   // record therefore go out before the wait for step m's records, and every
   // workgroup can run up to one step ahead of the slowest.
   auto decide = [&](long long m) -> int {     // spike decision of step m
-    if (p.ck_y) {                           // adjoint forward: checkpoint before the update
+    if (kRec && p.ck_y) {                   // adjoint forward: checkpoint before the update
       if (upd && ck_phase == 0 && ck_seg >= 0 && ck_seg < p.ck_count) {
         const size_t at = (size_t)ck_seg * p.ring_stride + j0 + tid;
         p.ck_y[at] = y; p.ck_I[at] = I; p.ck_r[at] = r;
@@ -429,7 +435,7 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     if (pop != 0xFFu) x_int += (long long)kdrive * p.jext_q;
-    if (p.xrec && m - p.xrec_step0 >= 0 && m - p.xrec_step0 < p.xrec_steps)
+    if (kRec && p.xrec && m - p.xrec_step0 >= 0 && m - p.xrec_step0 < p.xrec_steps)
       p.xrec[(size_t)(m - p.xrec_step0) * p.ring_stride + j0 + jl] = x_int;
     if (pop != 0xFFu) I = p.P11 * I + (double)x_int * 0x1p-16;
   };
@@ -485,7 +491,7 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
   }
   for (int it = 0; it < steps; ++it) {
     const long long n = n0 + it;
-    const bool timing = (a.phase != nullptr) && tid == 0;
+    const bool timing = kTime && tid == 0;
     long long tp0 = timing ? wall_clock64() : 0;
     const int sn1 = (sn + 1 == DL) ? 0 : sn + 1;
     const int snm2 = (sn >= 2) ? sn - 2 : sn - 2 + DL;   // slot of step n-2
@@ -507,7 +513,7 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
     // ---- while the records of step n arrive: drive of step n+1 (updaters);
     //      block bounds of step n-1 and entries of step n-2 (working
     //      wavefronts); polling (poller wavefronts) -----------------------------
-    const long long tp_wait = (a.phase != nullptr) ? wall_clock64() : 0;
+    const long long tp_wait = kTime ? wall_clock64() : 0;
     if (upd && it + 1 < steps) kdrive = (int)((drive_counts(n + 1, qlocal, seed, qpops, s_table) >> (8 * qk)) & 0xFFu);
     const bool work_now = overlap && !pollw;
     if (pollw) {
@@ -574,7 +580,7 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
           break;
         }
       }
-      if (a.phase != nullptr && tid == nthr - 64) ph[6] += wall_clock64() - tp_wait;
+      if (kTime && tid == nthr - 64) ph[6] += wall_clock64() - tp_wait;
     }
     if (work_now || !overlap) {
       if (!overlap) __syncthreads();      // no spare wavefronts: after the poll, all wavefronts
@@ -715,11 +721,11 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
   // ---- epilogue: state, counters, LDS window back into the global ring ------
   if (upd) { p.y[j0 + tid] = y; p.I[j0 + tid] = I; p.r[j0 + tid] = r; }
   if (tid < p.n_pops) p.wg_spikes[(size_t)g * p.n_pops + tid] += s_popcnt[tid];
-  if (tid == 0 && a.phase) {
+  if (kTime && tid == 0) {
     for (int k = 0; k < 6; ++k) a.phase[(size_t)g * 8 + k] += (unsigned long long)ph[k];
     a.phase[(size_t)g * 8 + 7] += (unsigned long long)steps;
   }
-  if (a.phase && tid == nthr - 64) a.phase[(size_t)g * 8 + 6] += (unsigned long long)ph[6];
+  if (kTime && tid == nthr - 64) a.phase[(size_t)g * 8 + 6] += (unsigned long long)ph[6];
   if (tid == 0) {
     p.raster_cnt[g] = rcnt;
     p.wg_events[g] += s_events;
@@ -895,24 +901,51 @@ size_t persist_lds_bytes(int G, int B, int DL) {
   return b + (size_t)2 * kListCap * 8;
 }
 
+// The four instances of k_persist (recording, timing); shapes are checked
+// against all of them.
+const void* const kPersistFns[4] = {(const void*)k_persist<false, false>, (const void*)k_persist<true, false>,
+                                    (const void*)k_persist<false, true>, (const void*)k_persist<true, true>};
+
 hipError_t persist_static_lds(size_t* bytes) {
-  hipFuncAttributes attr;
-  hipError_t e = hipFuncGetAttributes(&attr, (const void*)k_persist);
-  *bytes = (e == hipSuccess) ? attr.sharedSizeBytes : 0;
-  return e;
+  *bytes = 0;
+  for (const void* f : kPersistFns) {
+    hipFuncAttributes attr;
+    const hipError_t e = hipFuncGetAttributes(&attr, f);
+    if (e != hipSuccess) return e;
+    *bytes = std::max<size_t>(*bytes, attr.sharedSizeBytes);
+  }
+  return hipSuccess;
 }
 
 hipError_t persist_occupancy(int block, size_t lds, int* blocks_per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_persist, block, lds);
+  *blocks_per_cu = 1 << 30;
+  for (const void* f : kPersistFns) {
+    int occ = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, block, lds);
+    if (e != hipSuccess) return e;
+    *blocks_per_cu = std::min(*blocks_per_cu, occ);
+  }
+  return hipSuccess;
+}
+
+template <bool kRec, bool kTime>
+static void launch_persist_as(const DevNet& p, const PersistArgs& a, int steps, int block, size_t lds, hipStream_t s,
+                              hipEvent_t t0, hipEvent_t t1) {
+  auto* const kf = k_persist<kRec, kTime>;
+  if (t0 || t1)
+    hipExtLaunchKernelGGL(kf, dim3(a.G), dim3(block), lds, s, t0, t1, 0, p, a, steps);
+  else
+    hipLaunchKernelGGL(kf, dim3(a.G), dim3(block), lds, s, p, a, steps);
 }
 
 hipError_t launch_persist(const DevNet& p, const PersistArgs& a, int steps, int block, hipStream_t s, hipEvent_t t0,
                           hipEvent_t t1) {
   const size_t lds = persist_lds_bytes(a.G, a.B, a.DL);
-  if (t0 || t1)
-    hipExtLaunchKernelGGL(k_persist, dim3(a.G), dim3(block), lds, s, t0, t1, 0, p, a, steps);
-  else
-    hipLaunchKernelGGL(k_persist, dim3(a.G), dim3(block), lds, s, p, a, steps);
+  const bool rec = p.xrec != nullptr || p.ck_y != nullptr, tim = a.phase != nullptr;
+  if (rec && tim) launch_persist_as<true, true>(p, a, steps, block, lds, s, t0, t1);
+  else if (rec) launch_persist_as<true, false>(p, a, steps, block, lds, s, t0, t1);
+  else if (tim) launch_persist_as<false, true>(p, a, steps, block, lds, s, t0, t1);
+  else launch_persist_as<false, false>(p, a, steps, block, lds, s, t0, t1);
   return hipGetLastError();
 }
 
@@ -941,7 +974,11 @@ hipError_t launch_near_fill(const int32_t* tgt, const int32_t* wq, const uint8_t
 }
 
 hipError_t persist_set_lds_limit(size_t lds) {
-  return hipFuncSetAttribute((const void*)k_persist, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  for (const void* f : kPersistFns) {
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace mc
