@@ -114,6 +114,9 @@ __host__ __device__ size_t bucket_sum_slots(int B) { return (size_t)B; }
 // f64 | s_I[B] f64 | s_r[B] i32 | s_kd[B] u8 (Poisson count of the step) |
 // s_pop[B] u8.  The neuron state lives in LDS, so registers do not bound the
 // block size.
+// kRec: the adjoint's forward recording; kTime: phase timestamps.  Plain
+// simulation runs the instance with neither (fewer registers in use).
+template <bool kRec, bool kTime>
 __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs a, int steps) {
   extern __shared__ __align__(16) unsigned char s_raw[];
   __shared__ uint64_t s_table[kMaxPops * kTableLen];
@@ -186,7 +189,7 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
   };
   long long rcnt = p.raster_cnt[g];
   long long ck_seg = -1, ck_phase = 1;
-  if (p.ck_y) {
+  if (kRec && p.ck_y) {
     const long long k = n0 - p.ck_step0;
     ck_seg = (k >= 0) ? k / p.ck_every : -1;
     ck_phase = (k >= 0) ? k % p.ck_every : 1;
@@ -196,7 +199,7 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
   __syncthreads();
 
   auto decide = [&](long long m) -> uint64_t {   // spike decision of step m: bit k = local target tid + k nthr spiked
-    if (p.ck_y) {
+    if (kRec && p.ck_y) {
       if (ck_phase == 0 && ck_seg >= 0 && ck_seg < p.ck_count) {
         for (int jl = tid; jl < Bg; jl += nthr) {
           const size_t at = (size_t)ck_seg * p.ring_stride + j0 + jl;
@@ -381,7 +384,7 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
     const long long n = n0 + it;
     const int slot = (int)(n & kRingMask);
     const size_t rslot = (size_t)(n % kRecSlots);
-    const bool timing = (a.phase != nullptr) && tid == 0;
+    const bool timing = kTime && tid == 0;
     long long tp0 = timing ? wall_clock64() : 0;
     // ---- 1. input of step n: its bucket summed in LDS, then into I --------
     absorb_bucket(slot, absorbed, min(s_bcnt[slot], a.cap), tid, nthr);
@@ -403,7 +406,7 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
       }
       const unsigned pk = s_pop[jl];
       if (pk != 0xFFu) x_int += (long long)s_kd[jl] * p.jext_q;
-      if (p.xrec && n - p.xrec_step0 >= 0 && n - p.xrec_step0 < p.xrec_steps)
+      if (kRec && p.xrec && n - p.xrec_step0 >= 0 && n - p.xrec_step0 < p.xrec_steps)
         p.xrec[(size_t)(n - p.xrec_step0) * p.ring_stride + j0 + jl] = x_int;
       if (pk != 0xFFu) s_I[jl] = p.P11 * s_I[jl] + (double)x_int * 0x1p-16;
     }
@@ -432,7 +435,7 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
     const unsigned long long tag = (unsigned long long)(n + 1) << 32;
     const unsigned long long tag16 = (unsigned long long)((n + 1) % 65535 + 1) << 48;
     if (wave == nw - 1) {
-      const long long tp_poll = (a.phase != nullptr) ? wall_clock64() : 0;
+      const long long tp_poll = kTime ? wall_clock64() : 0;
       long long t_poll = 0;          // the wall clock is read every 256 rounds only
       unsigned spins = 0;
       unsigned todo = 0;
@@ -489,7 +492,7 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
           break;
         }
       }
-      if (a.phase != nullptr && tid == nthr - 64) ph[6] += wall_clock64() - tp_poll;
+      if (kTime && tid == nthr - 64) ph[6] += wall_clock64() - tp_poll;
       if (nwork == 0 && it + 1 < steps) drive_quads(n + 1, tid, nthr);   // a one-wavefront block
     }
     __syncthreads();
@@ -541,11 +544,11 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
     __syncthreads();
     if (timing) ph[4] += wall_clock64() - tp0;
   }
-  if (tid == 0 && a.phase) {
+  if (kTime && tid == 0) {
     for (int k = 0; k < 6; ++k) a.phase[(size_t)g * 8 + k] += (unsigned long long)ph[k];
     a.phase[(size_t)g * 8 + 7] += (unsigned long long)steps;
   }
-  if (a.phase && tid == nthr - 64) a.phase[(size_t)g * 8 + 6] += (unsigned long long)ph[6];
+  if (kTime && tid == nthr - 64) a.phase[(size_t)g * 8 + 6] += (unsigned long long)ph[6];
   // ---- epilogue: state, counters; pending buckets summed into the ring -----
   for (int jl = tid; jl < Bg; jl += nthr) { const long long j = j0 + jl; p.y[j] = s_y[jl]; p.I[j] = s_I[jl]; p.r[j] = s_r[jl]; }
   if (tid < p.n_pops) p.wg_spikes[(size_t)g * p.n_pops + tid] += s_popcnt[tid];
@@ -596,23 +599,50 @@ size_t bucket_lds_bytes(int B) {
   return bucket_sum_slots(B) * sizeof(long long) + (size_t)B * (8 + 8 + 4 + 1 + 1);
 }
 
+// The four instances of k_bucket (recording, timing); shapes are checked
+// against all of them.
+const void* const kBucketFns[4] = {(const void*)k_bucket<false, false>, (const void*)k_bucket<true, false>,
+                                   (const void*)k_bucket<false, true>, (const void*)k_bucket<true, true>};
+
+template <bool kRec, bool kTime>
+static void launch_bucket_as(const DevNet& p, const BucketArgs& a, int steps, int block, hipStream_t s, hipEvent_t t0,
+                             hipEvent_t t1) {
+  auto* const kf = k_bucket<kRec, kTime>;
+  if (t0 || t1)
+    hipExtLaunchKernelGGL(kf, dim3(a.G), dim3(block), bucket_lds_bytes(a.B), s, t0, t1, 0, p, a, steps);
+  else
+    hipLaunchKernelGGL(kf, dim3(a.G), dim3(block), bucket_lds_bytes(a.B), s, p, a, steps);
+}
+
 hipError_t launch_bucket(const DevNet& p, const BucketArgs& a, int steps, int block, hipStream_t s, hipEvent_t t0,
                          hipEvent_t t1) {
   // a thread owns at most 64 targets (its spike mask), so B <= 64 threads
   if (a.B < 4 || a.B > 64 * block) return hipErrorInvalidValue;
-  if (t0 || t1)
-    hipExtLaunchKernelGGL(k_bucket, dim3(a.G), dim3(block), bucket_lds_bytes(a.B), s, t0, t1, 0, p, a, steps);
-  else
-    hipLaunchKernelGGL(k_bucket, dim3(a.G), dim3(block), bucket_lds_bytes(a.B), s, p, a, steps);
+  const bool rec = p.xrec != nullptr || p.ck_y != nullptr, tim = a.phase != nullptr;
+  if (rec && tim) launch_bucket_as<true, true>(p, a, steps, block, s, t0, t1);
+  else if (rec) launch_bucket_as<true, false>(p, a, steps, block, s, t0, t1);
+  else if (tim) launch_bucket_as<false, true>(p, a, steps, block, s, t0, t1);
+  else launch_bucket_as<false, false>(p, a, steps, block, s, t0, t1);
   return hipGetLastError();
 }
 
 hipError_t bucket_occupancy(int B, int block, int* blocks_per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_bucket, block, bucket_lds_bytes(B));
+  *blocks_per_cu = 1 << 30;
+  for (const void* f : kBucketFns) {
+    int occ = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, block, bucket_lds_bytes(B));
+    if (e != hipSuccess) return e;
+    *blocks_per_cu = std::min(*blocks_per_cu, occ);
+  }
+  return hipSuccess;
 }
 
 hipError_t bucket_set_lds_limit(size_t lds) {
-  return hipFuncSetAttribute((const void*)k_bucket, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  for (const void* f : kBucketFns) {
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace mc
