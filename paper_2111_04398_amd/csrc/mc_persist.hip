@@ -63,6 +63,7 @@ constexpr int kListCap = 1024;       // spikes of one step kept in LDS (more: de
 constexpr int kInline = 7;           // spike ids carried by a record (more: side array)
 constexpr int kW0Ids = 4;            // of which in word 0 (9-bit block-local indices)
 constexpr int kBigCap = 64;          // producers with more than kInline spikes listed per step
+constexpr int kItemSpikes = 16;      // spikes per claimed item of pipelined entries (~ one 256-entry chunk)
 constexpr int kUnroll = 4;           // entries in flight per lane
 constexpr int kPollPerLane = kPersistMaxBlock / 64;   // producers polled by one lane (G <= block <= 512)
 constexpr unsigned kNearD2 = 0x80000000u;   // near-table flag: delay 2 (else 1)
@@ -278,6 +279,8 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
   __shared__ int s_nids, s_nbig;                 // ids listed by the poller this step; producers with more
   __shared__ int2 s_big[kBigCap];                // (producer, list offset) of those producers
   __shared__ unsigned long long s_events;
+  __shared__ int s_work;                         // next item of the step's pipelined delivery
+  __shared__ int s_pubcnt, s_sidecnt;            // arrivals of the updating wavefronts (monotonic)
   __shared__ unsigned long long s_popcnt[kMaxPops];
   long long* acc = reinterpret_cast<long long*>(s_raw);
   unsigned* fbits = reinterpret_cast<unsigned*>(acc + (size_t)a.DL * a.B);
@@ -298,7 +301,6 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
   // producers l, l+64, ...); the other wavefronts work on the pipelined
   // delivery meanwhile.  A one-wavefront workgroup polls, then works.
   const bool overlap = nw > 1;
-  const int nwd = overlap ? nw - 1 : nw;                             // wavefronts working while polling
   const bool pollw = overlap ? (wave == nw - 1) : true;
   auto par_m = [](long long m) { return (int)(m & 1); };
   const Block blk{acc, fbits, a.B, a.BW, DL, j0};
@@ -309,7 +311,7 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
   for (int k = tid; k < p.n_pops * kTableLen; k += nthr) s_table[k] = p.table[k];
   for (int k = tid; k < DL * a.B; k += nthr) acc[k] = 0;
   for (int k = tid; k < 128 * a.BW; k += nthr) fbits[k] = 0;
-  if (tid == 0) { s_abort = 0; s_events = 0; }
+  if (tid == 0) { s_abort = 0; s_events = 0; s_work = 0; s_pubcnt = 0; s_sidecnt = 0; }
   if (tid < kMaxPops) s_popcnt[tid] = 0;
   __syncthreads();
   // take the next DL steps of pending input of my targets into LDS; mark far
@@ -353,6 +355,29 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
   int kdrive = 0;
   uint64_t seed = 0;
   const bool upd = tid < Bg;
+  // Wavefronts holding owned targets update, spike and publish; they meet
+  // for the publication on an LDS arrival count, not a block barrier, so the
+  // poller and the wavefronts without targets start the step's waiting work
+  // (polling, pipelined delivery) at its top.
+  const int nupd_w = (Bg + 63) >> 6;
+  const bool updw = wave < nupd_w;
+  int pub_epoch = 0, side_epoch = 0;
+  auto upd_sync = [&](int* cnt, int& epoch) {
+    ++epoch;
+    if ((tid & 63) == 0) __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    const int target = epoch * nupd_w;
+    long long t_sp = 0;
+    unsigned spins = 0;
+    while (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < target) {
+      __builtin_amdgcn_s_sleep(1);
+      if ((++spins & 1023u) == 0u &&
+          (t_sp == 0 ? ((t_sp = wall_clock64()), false) : wall_clock64() - t_sp > a.wait_ticks)) {
+        atomicOr(p.overflow, 2u);
+        s_abort = 1;
+        break;
+      }
+    }
+  };
   const long long q = (j0 + tid) >> 2;
   const int qk = tid & 3;
   __syncthreads();
@@ -444,10 +469,10 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
     // lower threads (thread order = id order)
     const uint64_t bal = __ballot(spiked);
     if ((tid & 63) == 0) s_mask[par_m(m)][wave] = bal;
-    __syncthreads();
+    upd_sync(&s_pubcnt, pub_epoch);
     const uint64_t* msk = s_mask[par_m(m)];
     int nloc = 0, pos = 0;
-    for (int w = 0; w < nw; ++w) {
+    for (int w = 0; w < nupd_w; ++w) {
       const int c = __popcll(msk[w]);
       pos += (w < wave) ? c : 0;
       nloc += c;
@@ -466,12 +491,12 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
     }
     if (nloc > kInline) {                   // side-array ids complete before word 0
       __builtin_amdgcn_s_waitcnt(0);
-      __syncthreads();
+      upd_sync(&s_sidecnt, side_epoch);
     }
     if (tid == 0) {                         // word 0: count and the local indices of the first four spikes
       unsigned long long w0 = tag16 | (unsigned long long)nloc << 36;
       int f = 0;
-      for (int w = 0; w < nw && f < kW0Ids; ++w) {
+      for (int w = 0; w < nupd_w && f < kW0Ids; ++w) {
         uint64_t mm = msk[w];
         while (mm && f < kW0Ids) {
           w0 |= (unsigned long long)(64 * w + __builtin_ctzll(mm)) << (9 * f);
@@ -485,7 +510,7 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
     else if (tid == 0) atomicOr(p.overflow, 1u);
   };
 
-  if (steps > 0) {                            // step n0's spike decision and record
+  if (steps > 0 && updw) {                    // step n0's spike decision and record
     const int sp = decide(n0);
     publish(n0, sp);
   }
@@ -499,25 +524,27 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
     const size_t rslot = (size_t)(n % kRecSlots);        // record slot of step n
     // ---- rest of the update of step n (its input into I), spike decision of
     //      step n+1 ------------------------------------------------------------
-    absorb(n, sn);
-    int spiked = 0;
-    if (it + 1 < steps) spiked = decide(n + 1);
-    if (tid == 0) { s_nids = 0; s_nbig = 0; }   // read after the previous wait; next used after a barrier below
-    if (timing) { const long long t = wall_clock64(); ph[0] += t - tp0; tp0 = t; }
-    // ---- record of step n+1 ---------------------------------------------------
-    if (it + 1 < steps) publish(n + 1, spiked);
-    else __syncthreads();
-    if (timing) { const long long t = wall_clock64(); ph[1] += t - tp0; tp0 = t; }
+    if (updw) {
+      absorb(n, sn);
+      int spiked = 0;
+      if (it + 1 < steps) spiked = decide(n + 1);
+      if (timing) { const long long t = wall_clock64(); ph[0] += t - tp0; tp0 = t; }
+      // ---- record of step n+1 -------------------------------------------------
+      if (it + 1 < steps) publish(n + 1, spiked);
+      if (timing) { const long long t = wall_clock64(); ph[1] += t - tp0; tp0 = t; }
+      // drive of step n+1
+      if (upd && it + 1 < steps) kdrive = (int)((drive_counts(n + 1, qlocal, seed, qpops, s_table) >> (8 * qk)) & 0xFFu);
+    }
     const unsigned long long tag = (unsigned long long)(n + 1) << 32;              // records of step n
     const unsigned long long tag16 = (unsigned long long)((n + 1) % 65535 + 1) << 48;
-    // ---- while the records of step n arrive: drive of step n+1 (updaters);
-    //      block bounds of step n-1 and entries of step n-2 (working
-    //      wavefronts); polling (poller wavefronts) -----------------------------
+    // ---- while the records of step n arrive: polling (the last wavefront,
+    //      from the top of the step unless it holds targets); the pipelined
+    //      delivery (block bounds of step n-1, entries of step n-2) in items
+    //      claimed by the other wavefronts, those without targets from the top
     const long long tp_wait = kTime ? wall_clock64() : 0;
-    if (upd && it + 1 < steps) kdrive = (int)((drive_counts(n + 1, qlocal, seed, qpops, s_table) >> (8 * qk)) & 0xFFu);
-    const bool work_now = overlap && !pollw;
     if (pollw) {
       const int lane = tid & 63;
+      if (lane == 0) { s_nids = 0; s_nbig = 0; }   // read after the previous wait
       long long t_poll = 0;          // the wall clock is read every 256 rounds only
       unsigned spins = 0;
       unsigned todo = 0;
@@ -582,47 +609,34 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
       }
       if (kTime && tid == nthr - 64) ph[6] += wall_clock64() - tp_wait;
     }
-    if (work_now || !overlap) {
-      if (!overlap) __syncthreads();      // no spare wavefronts: after the poll, all wavefronts
-      const int nwork = overlap ? nwd : nw;
+    if (!pollw || !overlap) {
       const int pn1 = par ^ 1, pn2 = par;  // parity of steps n-1 and n-2
-      // block bounds of this wavefront's share of step n-1 (loads in flight ...)
-      const int kb0 = (int)((long long)S1 * wave / nwork), kb1 = (int)((long long)S1 * (wave + 1) / nwork);
-      long long blo[2] = {0, 0}, bhi[2] = {0, 0};
+      const int nb2 = (S2 + kItemSpikes - 1) / kItemSpikes, items = nb2 + ((S1 + 63) >> 6);
       const int lane = tid & 63;
-#pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int k = kb0 + u * 64 + lane;
-        if (k < kb1) {
-          const long long* bi = a.blk + (size_t)s_ids[pn1 * kListCap + k] * (a.G + 1) + g;
-          blo[u] = bi[0];
-          bhi[u] = bi[1];
-        }
-      }
-      // ... while the entries of step n-2 (delay >= 3) are added
-      const int ka0 = (int)((long long)S2 * wave / nwork), ka1 = (int)((long long)S2 * (wave + 1) / nwork);
-      wave_entries(p, blk, ka0, ka1, n - 2, snm2, 3, bounds_of(pn2));
       unsigned long long ev = 0;
-#pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int k = kb0 + u * 64 + lane;
-        if (k < kb1) {
-          s_lo[pn1 * kListCap + k] = blo[u];
-          s_len[pn1 * kListCap + k] = (int)(bhi[u] - blo[u]);
-          ev += (unsigned long long)(bhi[u] - blo[u]);
+      for (;;) {
+        int i = 0;
+        if (lane == 0) i = atomicAdd(&s_work, 1);
+        i = __builtin_amdgcn_readfirstlane(i);
+        if (i >= items) break;
+        if (i < nb2) {                     // entries (delay >= 3) of kItemSpikes spikes of step n-2
+          wave_entries(p, blk, kItemSpikes * i, min(S2, kItemSpikes * (i + 1)), n - 2, snm2, 3, bounds_of(pn2));
+        } else {                           // block bounds of spikes 64(i - nb2).. of step n-1
+          const int k = 64 * (i - nb2) + lane;
+          if (k < S1) {
+            const long long* bi = a.blk + (size_t)s_ids[pn1 * kListCap + k] * (a.G + 1) + g;
+            const long long b0 = bi[0], b1 = bi[1];
+            s_lo[pn1 * kListCap + k] = b0;
+            s_len[pn1 * kListCap + k] = (int)(b1 - b0);
+            ev += (unsigned long long)(b1 - b0);
+          }
         }
-      }
-      for (int k = kb0 + 128 + lane; k < kb1; k += 64) {   // more than 128 spikes for one wavefront
-        const long long* bi = a.blk + (size_t)s_ids[pn1 * kListCap + k] * (a.G + 1) + g;
-        const long long b0 = bi[0], b1 = bi[1];
-        s_lo[pn1 * kListCap + k] = b0;
-        s_len[pn1 * kListCap + k] = (int)(b1 - b0);
-        ev += (unsigned long long)(b1 - b0);
       }
       if (ev) atomicAdd(&s_events, ev);
       if (timing) ph[5] += wall_clock64() - tp_wait;
     }
     __syncthreads();                       // s_cnt, the inline ids and the poller's list complete
+    if (tid == 0) s_work = 0;              // no claims until the next step (barriers below)
     if (s_abort) break;
     int S = s_nids;
     int* ids_n = s_ids + par * kListCap;
