@@ -27,6 +27,16 @@
 // ids of each record as it arrives, so the list is complete when the wait
 // ends.
 //
+// Wavefront roles within a step.  Only the wavefronts that hold owned
+// targets update, spike and publish; they meet for the compaction on an LDS
+// arrival count instead of a block barrier.  The poller (the last wavefront)
+// and the wavefronts without targets therefore start at the top of the
+// step: the poller polls, the others take items of the pipelined delivery
+// (entries of 16 spikes, block bounds of 64) from an LDS counter, and the
+// updating wavefronts join the claiming once their record is out.  In a
+// quiet step the memory round trips of the pipelined delivery thus overlap
+// the update and the publication instead of following them.
+//
 // Spike exchange: workgroup g publishes a record per step (four per
 // workgroup, by step mod 4, so a record is never rewritten while a consumer
 // one step behind may still read it).  Compaction is one ballot per
