@@ -474,23 +474,28 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
       p.xrec[(size_t)(m - p.xrec_step0) * p.ring_stride + j0 + jl] = x_int;
     if (pop != 0xFFu) I = p.P11 * I + (double)x_int * 0x1p-16;
   };
-  auto publish = [&](long long m, int spiked) {   // compaction (ascending ids), record of step m, raster
+  // t16m = (m + 1) mod 65535 + 1, kept by the caller as a running count
+  auto publish = [&](long long m, int spiked, unsigned t16m) {   // compaction (ascending ids), record of step m, raster
     // one ballot per wavefront; a spike's position is the count of spikes of
     // lower threads (thread order = id order)
     const uint64_t bal = __ballot(spiked);
     if ((tid & 63) == 0) s_mask[par_m(m)][wave] = bal;
     upd_sync(&s_pubcnt, pub_epoch);
     const uint64_t* msk = s_mask[par_m(m)];
+    uint64_t mr[kPersistMaxBlock / 64];      // the masks, read once into registers
+#pragma unroll
+    for (int w = 0; w < kPersistMaxBlock / 64; ++w) mr[w] = (w < nupd_w) ? msk[w] : 0ull;
     int nloc = 0, pos = 0;
-    for (int w = 0; w < nupd_w; ++w) {
-      const int c = __popcll(msk[w]);
+#pragma unroll
+    for (int w = 0; w < kPersistMaxBlock / 64; ++w) {
+      const int c = __popcll(mr[w]);
       pos += (w < wave) ? c : 0;
       nloc += c;
     }
     pos += __popcll(bal & ((tid & 63) ? (~0ull >> (64 - (tid & 63))) : 0ull));
     const unsigned long long tag = (unsigned long long)(m + 1) << 32;
-    const unsigned long long tag16 = (unsigned long long)((m + 1) % 65535 + 1) << 48;
-    const size_t rec = (size_t)g * kRecSlots + (size_t)(m % kRecSlots);
+    const unsigned long long tag16 = (unsigned long long)t16m << 48;
+    const size_t rec = (size_t)g * kRecSlots + (size_t)(m & (kRecSlots - 1));
     unsigned long long* myrec = a.flags + rec * kPersistFlagStride;
     const bool fits = rcnt + nloc <= p.raster_cap;
     if (spiked) {
@@ -506,8 +511,9 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
     if (tid == 0) {                         // word 0: count and the local indices of the first four spikes
       unsigned long long w0 = tag16 | (unsigned long long)nloc << 36;
       int f = 0;
-      for (int w = 0; w < nupd_w && f < kW0Ids; ++w) {
-        uint64_t mm = msk[w];
+#pragma unroll
+      for (int w = 0; w < kPersistMaxBlock / 64; ++w) {
+        uint64_t mm = mr[w];
         while (mm && f < kW0Ids) {
           w0 |= (unsigned long long)(64 * w + __builtin_ctzll(mm)) << (9 * f);
           mm &= mm - 1;
@@ -520,9 +526,12 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
     else if (tid == 0) atomicOr(p.overflow, 1u);
   };
 
+  static_assert((kRecSlots & (kRecSlots - 1)) == 0, "record slots by step & (kRecSlots - 1)");
+  auto next16 = [](unsigned t) { return t == 65535u ? 1u : t + 1u; };
+  unsigned t16n = (unsigned)((n0 + 1) % 65535 + 1);   // tag of step n0's record; advanced every step
   if (steps > 0 && updw) {                    // step n0's spike decision and record
     const int sp = decide(n0);
-    publish(n0, sp);
+    publish(n0, sp, t16n);
   }
   for (int it = 0; it < steps; ++it) {
     const long long n = n0 + it;
@@ -531,7 +540,7 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
     const int sn1 = (sn + 1 == DL) ? 0 : sn + 1;
     const int snm2 = (sn >= 2) ? sn - 2 : sn - 2 + DL;   // slot of step n-2
     const int par = (int)(n & 1);
-    const size_t rslot = (size_t)(n % kRecSlots);        // record slot of step n
+    const size_t rslot = (size_t)(n & (kRecSlots - 1));  // record slot of step n
     // ---- rest of the update of step n (its input into I), spike decision of
     //      step n+1 ------------------------------------------------------------
     if (updw) {
@@ -540,13 +549,13 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
       if (it + 1 < steps) spiked = decide(n + 1);
       if (timing) { const long long t = wall_clock64(); ph[0] += t - tp0; tp0 = t; }
       // ---- record of step n+1 -------------------------------------------------
-      if (it + 1 < steps) publish(n + 1, spiked);
+      if (it + 1 < steps) publish(n + 1, spiked, next16(t16n));
       if (timing) { const long long t = wall_clock64(); ph[1] += t - tp0; tp0 = t; }
       // drive of step n+1
       if (upd && it + 1 < steps) kdrive = (int)((drive_counts(n + 1, qlocal, seed, qpops, s_table) >> (8 * qk)) & 0xFFu);
     }
     const unsigned long long tag = (unsigned long long)(n + 1) << 32;              // records of step n
-    const unsigned long long tag16 = (unsigned long long)((n + 1) % 65535 + 1) << 48;
+    const unsigned long long tag16 = (unsigned long long)t16n << 48;
     // ---- while the records of step n arrive: polling (the last wavefront,
     //      from the top of the step unless it holds targets); the pipelined
     //      delivery (block bounds of step n-1, entries of step n-2) in items
@@ -671,6 +680,7 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
       S2 = S1;
       S1 = S;
       sn = sn1;
+      t16n = next16(t16n);
       continue;
     }
     // ---- more spikes than the list holds: listing by producer order
@@ -715,6 +725,7 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
     S2 = S1;
     S1 = (S <= kListCap) ? S : 0;
     sn = sn1;
+    t16n = next16(t16n);
   }
   // ---- pipelined events still due: entries of step n_end-2, bounds and
   //      entries of step n_end-1 --------------------------------------------
