@@ -225,7 +225,7 @@ __device__ __forceinline__ void wave_entries(const DevNet& p, const Block& b, in
 // (delay-2 flag | local target) << 32 | weight).  Lanes load the offsets of 64
 // spikes, scan the counts and walk the concatenated entries.
 __device__ __forceinline__ void wave_near(const PersistArgs& a, const Block& b, const int* list, int k0, int k1, int gpos,
-                                          int slot1, int slot2) {
+                                          int slot1, int slot2, int sign = 1) {
   const int lane = threadIdx.x & 63;
   for (int base = k0; base < k1; base += 64) {
     unsigned lo = 0;
@@ -264,7 +264,7 @@ __device__ __forceinline__ void wave_near(const PersistArgs& a, const Block& b, 
         const unsigned hi = (unsigned)(v[u] >> 32);
         const int slot = (hi & kNearD2) ? slot2 : slot1;
         atomicAdd(reinterpret_cast<unsigned long long*>(&b.acc[(size_t)slot * b.B + (hi & 0xFFFFu)]),
-                  (unsigned long long)(long long)(int)(v[u] & 0xFFFFFFFFu));
+                  (unsigned long long)((long long)(int)(v[u] & 0xFFFFFFFFu) * sign));
       }
     }
   }
@@ -291,6 +291,7 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
   __shared__ unsigned long long s_events;
   __shared__ int s_work;                         // next item of the step's pipelined delivery
   __shared__ int s_pubcnt, s_sidecnt;            // arrivals of the updating wavefronts (monotonic)
+  __shared__ int s_nready, s_polldone, s_ndone;  // ids listed in complete rounds; poll over; ids near-delivered early
   __shared__ unsigned long long s_popcnt[kMaxPops];
   long long* acc = reinterpret_cast<long long*>(s_raw);
   unsigned* fbits = reinterpret_cast<unsigned*>(acc + (size_t)a.DL * a.B);
@@ -321,7 +322,7 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
   for (int k = tid; k < p.n_pops * kTableLen; k += nthr) s_table[k] = p.table[k];
   for (int k = tid; k < DL * a.B; k += nthr) acc[k] = 0;
   for (int k = tid; k < 128 * a.BW; k += nthr) fbits[k] = 0;
-  if (tid == 0) { s_abort = 0; s_events = 0; s_work = 0; s_pubcnt = 0; s_sidecnt = 0; }
+  if (tid == 0) { s_abort = 0; s_events = 0; s_work = 0; s_pubcnt = 0; s_sidecnt = 0; s_nready = 0; s_polldone = 0; s_ndone = 0; }
   if (tid < kMaxPops) s_popcnt[tid] = 0;
   __syncthreads();
   // take the next DL steps of pending input of my targets into LDS; mark far
@@ -615,6 +616,10 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
           }
           todo &= ~(1u << r);
         }
+        // the ids listed so far are complete records (a busy producer's
+        // later ids come after the wait, so the count stops advancing there)
+        if (lane == 0 && s_nbig == 0 && s_nids <= kListCap)
+          __hip_atomic_store(&s_nready, s_nids, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (!todo) break;
         __builtin_amdgcn_s_sleep(1);
         if ((++spins & 255u) == 0u && (t_poll == 0 ? ((t_poll = wall_clock64()), false) : wall_clock64() - t_poll > a.wait_ticks)) {
@@ -626,6 +631,7 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
           break;
         }
       }
+      if (lane == 0) __hip_atomic_store(&s_polldone, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
       if (kTime && tid == nthr - 64) ph[6] += wall_clock64() - tp_wait;
     }
     if (!pollw || !overlap) {
@@ -652,10 +658,28 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
         }
       }
       if (ev) atomicAdd(&s_events, ev);
+      // the last wavefront without targets, its items done, adds the near
+      // events of the ids listed so far while the poll goes on
+      if (overlap && wave == nw - 2 && !updw) {
+        int done = 0;
+        for (;;) {
+          const int pd = __hip_atomic_load(&s_polldone, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+          const int ready = __hip_atomic_load(&s_nready, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+          if (ready > done) {
+            wave_near(a, blk, s_ids + par * kListCap, done, ready, gpos, sn1, sn1 + 1 == DL ? 0 : sn1 + 1);
+            done = ready;
+            continue;
+          }
+          if (pd) break;
+          __builtin_amdgcn_s_sleep(1);
+        }
+        if (lane == 0) s_ndone = done;
+      }
       if (timing) ph[5] += wall_clock64() - tp_wait;
     }
     __syncthreads();                       // s_cnt, the inline ids and the poller's list complete
-    if (tid == 0) s_work = 0;              // no claims until the next step (barriers below)
+    const int ndone = s_ndone;             // ids whose near events are in already
+    if (tid == 0) { s_work = 0; s_nready = 0; s_polldone = 0; }   // untouched until the next step (barriers below)
     if (s_abort) break;
     int S = s_nids;
     int* ids_n = s_ids + par * kListCap;
@@ -672,7 +696,7 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
         }
         __syncthreads();
       }
-      const int k0 = (int)((long long)S * wave / nw), k1 = (int)((long long)S * (wave + 1) / nw);
+      const int k0 = ndone + (int)((long long)(S - ndone) * wave / nw), k1 = ndone + (int)((long long)(S - ndone) * (wave + 1) / nw);
       if (timing) { const long long t = wall_clock64(); ph[3] += t - tp0; tp0 = t; }
       wave_near(a, blk, ids_n, k0, k1, gpos, sn1, sn1 + 1 == DL ? 0 : sn1 + 1);
       __syncthreads();
@@ -685,6 +709,11 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
     }
     // ---- more spikes than the list holds: listing by producer order
     //      (count scan), then every event of the step delivered at once ----
+    if (ndone > 0) {   // the early near events come out again (exact integer sums), the listing overwrites their ids
+      const int k0 = (int)((long long)ndone * wave / nw), k1 = (int)((long long)ndone * (wave + 1) / nw);
+      wave_near(a, blk, ids_n, k0, k1, gpos, sn1, sn1 + 1 == DL ? 0 : sn1 + 1, -1);
+      __syncthreads();
+    }
     // thread t sums producers 2t and 2t+1 (G <= 2 * threads)
     const int c0 = (2 * tid < a.G) ? s_cnt[2 * tid] : 0;
     const int c1 = (2 * tid + 1 < a.G) ? s_cnt[2 * tid + 1] : 0;
