@@ -73,6 +73,7 @@ constexpr int kListCap = 1024;       // spikes of one step kept in LDS (more: de
 constexpr int kInline = 7;           // spike ids carried by a record (more: side array)
 constexpr int kW0Ids = 4;            // of which in word 0 (9-bit block-local indices)
 constexpr int kBigCap = 64;          // producers with more than kInline spikes listed per step
+constexpr int kEarlyNear = 64;       // ids near-delivered during the poll at most (all waves share the rest)
 constexpr int kItemSpikes = 16;      // spikes per claimed item of pipelined entries (~ one 256-entry chunk)
 constexpr int kUnroll = 4;           // entries in flight per lane
 constexpr int kPollPerLane = kPersistMaxBlock / 64;   // producers polled by one lane (G <= block <= 512)
@@ -659,18 +660,20 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
       }
       if (ev) atomicAdd(&s_events, ev);
       // the last wavefront without targets, its items done, adds the near
-      // events of the ids listed so far while the poll goes on
+      // events of the first ids listed (at most kEarlyNear) while the poll
+      // goes on
       if (overlap && wave == nw - 2 && !updw) {
         int done = 0;
         for (;;) {
           const int pd = __hip_atomic_load(&s_polldone, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
           const int ready = __hip_atomic_load(&s_nready, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
-          if (ready > done) {
-            wave_near(a, blk, s_ids + par * kListCap, done, ready, gpos, sn1, sn1 + 1 == DL ? 0 : sn1 + 1);
-            done = ready;
+          const int upto = min(ready, kEarlyNear);
+          if (upto > done) {
+            wave_near(a, blk, s_ids + par * kListCap, done, upto, gpos, sn1, sn1 + 1 == DL ? 0 : sn1 + 1);
+            done = upto;
             continue;
           }
-          if (pd) break;
+          if (done >= kEarlyNear || pd) break;
           __builtin_amdgcn_s_sleep(1);
         }
         if (lane == 0) s_ndone = done;
