@@ -76,7 +76,6 @@ constexpr int kBigCap = 64;          // producers with more than kInline spikes 
 constexpr int kEarlyNear = 64;       // ids near-delivered during the poll at most (all waves share the rest)
 constexpr int kItemSpikes = 16;      // spikes per claimed item of pipelined entries (~ one 256-entry chunk)
 constexpr int kUnroll = 4;           // entries in flight per lane
-constexpr int kPollPerLane = kPersistMaxBlock / 64;   // producers polled by one lane (G <= block <= 512)
 constexpr unsigned kNearD2 = 0x80000000u;   // near-table flag: delay 2 (else 1)
 
 // Workgroups are dispatched to the XCDs round robin (workgroup g runs on XCD
@@ -278,8 +277,9 @@ __device__ __forceinline__ void wave_near(const PersistArgs& a, const Block& b, 
 // kRec: the adjoint's forward recording (input x and state checkpoints);
 // kTime: phase timestamps.  Plain simulation runs the instance with neither,
 // whose smaller register footprint shortens the step (fewer scalar
-// registers spilled to vector lanes).
-template <bool kRec, bool kTime>
+// registers spilled to vector lanes).  kPoll: producers polled per lane (4
+// when G <= 256: a smaller poll loop, fewer registers; else 8).
+template <bool kRec, bool kTime, int kPoll>
 __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistArgs a, int steps) {
   extern __shared__ __align__(16) unsigned char s_raw[];
   __shared__ uint64_t s_table[kMaxPops * kTableLen];
@@ -400,9 +400,9 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
     if (steps > 0) kdrive = (int)((drive_counts(n0, qlocal, seed, qpops, s_table) >> (8 * qk)) & 0xFFu);
   }
   // first owned target of each producer this lane polls (word 0 carries block-local indices)
-  int pbs[kPollPerLane];
+  int pbs[kPoll];
 #pragma unroll
-  for (int r = 0; r < kPollPerLane; ++r) {
+  for (int r = 0; r < kPoll; ++r) {
     const int h = (tid & 63) + 64 * r;
     pbs[r] = (h < a.G) ? a.bstart[h] : 0;
   }
@@ -570,16 +570,16 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
       unsigned spins = 0;
       unsigned todo = 0;
 #pragma unroll
-      for (int r = 0; r < kPollPerLane; ++r)
+      for (int r = 0; r < kPoll; ++r)
         if (lane + 64 * r < a.G) todo |= 1u << r;
       while (todo) {
-        unsigned long long w0[kPollPerLane];
+        unsigned long long w0[kPoll];
 #pragma unroll
-        for (int r = 0; r < kPollPerLane; ++r)
+        for (int r = 0; r < kPoll; ++r)
           w0[r] = ((todo >> r) & 1u) ? ld_dev(&a.flags[((size_t)(lane + 64 * r) * kRecSlots + rslot) * kPersistFlagStride])
                                      : 0ull;
 #pragma unroll
-        for (int r = 0; r < kPollPerLane; ++r) {
+        for (int r = 0; r < kPoll; ++r) {
           if (!((todo >> r) & 1u) || (w0[r] & 0xFFFF000000000000ull) != tag16) continue;
           const int h = lane + 64 * r;
           const int c = (int)((w0[r] >> 36) & 0x3FFu);
@@ -627,7 +627,7 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
           atomicOr(p.overflow, 2u);
           s_abort = 1;
 #pragma unroll
-          for (int r = 0; r < kPollPerLane; ++r)
+          for (int r = 0; r < kPoll; ++r)
             if ((todo >> r) & 1u) s_cnt[lane + 64 * r] = 0;
           break;
         }
@@ -835,10 +835,11 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
 // The exchange of k_persist with nothing else: every step, each of the G
 // workgroups publishes a step-tagged record (word 0 as in k_persist, no
 // spikes) and its last wavefront polls all G records of the step the same
-// way (eight producers per lane, device-scope loads, a short sleep between
+// way (four or eight producers per lane, device-scope loads, a short sleep between
 // rounds); then a barrier and the next step.  The time per step is the floor
 // the persistent kernel's step cannot go below.  Records are cleared by the
 // last workgroup to finish, as in k_persist.
+template <int kPoll>
 __global__ __launch_bounds__(kPersistMaxBlock) void k_exchange_probe(unsigned long long* flags, int G, long long steps,
                                                                      long long wait_ticks, unsigned* err) {
   __shared__ int s_abort, s_last;
@@ -855,16 +856,16 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_exchange_probe(unsigned lo
       unsigned spins = 0;
       unsigned todo = 0;
 #pragma unroll
-      for (int r = 0; r < kPollPerLane; ++r)
+      for (int r = 0; r < kPoll; ++r)
         if (lane + 64 * r < G) todo |= 1u << r;
       while (todo) {
-        unsigned long long w0[kPollPerLane];
+        unsigned long long w0[kPoll];
 #pragma unroll
-        for (int r = 0; r < kPollPerLane; ++r)
+        for (int r = 0; r < kPoll; ++r)
           w0[r] = ((todo >> r) & 1u) ? ld_dev(&flags[((size_t)(lane + 64 * r) * kRecSlots + rslot) * kPersistFlagStride])
                                      : 0ull;
 #pragma unroll
-        for (int r = 0; r < kPollPerLane; ++r)
+        for (int r = 0; r < kPoll; ++r)
           if (((todo >> r) & 1u) && (w0[r] & 0xFFFF000000000000ull) == tag16) todo &= ~(1u << r);
         if (!todo) break;
         __builtin_amdgcn_s_sleep(1);
@@ -897,7 +898,10 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_exchange_probe(unsigned lo
 hipError_t launch_exchange_probe(unsigned long long* flags, int G, int block, long long steps, long long wait_ticks,
                                  unsigned* err, hipStream_t s) {
   if (G < 1 || G > kPersistMaxBlock || block < 64 || block > kPersistMaxBlock || block % 64) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_exchange_probe, dim3(G), dim3(block), 0, s, flags, G, steps, wait_ticks, err);
+  if (G <= 256)
+    hipLaunchKernelGGL(k_exchange_probe<4>, dim3(G), dim3(block), 0, s, flags, G, steps, wait_ticks, err);
+  else
+    hipLaunchKernelGGL(k_exchange_probe<8>, dim3(G), dim3(block), 0, s, flags, G, steps, wait_ticks, err);
   return hipGetLastError();
 }
 
@@ -968,10 +972,13 @@ size_t persist_lds_bytes(int G, int B, int DL) {
   return b + (size_t)2 * kListCap * 8;
 }
 
-// The four instances of k_persist (recording, timing); shapes are checked
-// against all of them.
-const void* const kPersistFns[4] = {(const void*)k_persist<false, false>, (const void*)k_persist<true, false>,
-                                    (const void*)k_persist<false, true>, (const void*)k_persist<true, true>};
+// The instances of k_persist (recording, timing, poll width); shapes are
+// checked against all of them.
+const void* const kPersistFns[8] = {
+    (const void*)k_persist<false, false, 4>, (const void*)k_persist<true, false, 4>,
+    (const void*)k_persist<false, true, 4>,  (const void*)k_persist<true, true, 4>,
+    (const void*)k_persist<false, false, 8>, (const void*)k_persist<true, false, 8>,
+    (const void*)k_persist<false, true, 8>,  (const void*)k_persist<true, true, 8>};
 
 hipError_t persist_static_lds(size_t* bytes) {
   *bytes = 0;
@@ -998,7 +1005,7 @@ hipError_t persist_occupancy(int block, size_t lds, int* blocks_per_cu) {
 template <bool kRec, bool kTime>
 static void launch_persist_as(const DevNet& p, const PersistArgs& a, int steps, int block, size_t lds, hipStream_t s,
                               hipEvent_t t0, hipEvent_t t1) {
-  auto* const kf = k_persist<kRec, kTime>;
+  auto* const kf = (a.G <= 256) ? k_persist<kRec, kTime, 4> : k_persist<kRec, kTime, 8>;
   if (t0 || t1)
     hipExtLaunchKernelGGL(kf, dim3(a.G), dim3(block), lds, s, t0, t1, 0, p, a, steps);
   else
