@@ -165,7 +165,7 @@ struct mc_net {
   int* d_ifb = nullptr;                // [n_inst] first block of each instance
   int64_t* d_boff = nullptr;           // [n_pad+1]
   int32_t* d_blk2 = nullptr;
-  int own_blocks = 0, own_bmax = 0, own_targets = 0;
+  int own_blocks = 0, own_bmax = 0, own_targets = 0, own_inst_max = 0;
   // input record of an adjoint's forward (owned by that mc_adjoint call)
   long long* d_xrec = nullptr;
   long long xrec_step0 = 0, xrec_steps = 0;
@@ -245,6 +245,7 @@ struct mc_net {
     a.wait_ticks = (long long)wall_khz * 1000 * kWaitSeconds;
     a.horizon = horizon;
     a.phase = phase_on ? d_phase : nullptr;
+    a.inst_wg_max = own_inst_max;
     return a;
   }
 
@@ -549,12 +550,15 @@ int bucket_shape(mc_net* n, const mc_launch& l, int* B_out) {
   HIP_TRY(bucket_set_lds_limit(std::min<size_t>((size_t)n->lds_max, bucket_lds_bytes(bmax))));
   auto fits = [&](int B, std::string* why) -> bool {
     int occ = 0;
-    if (bucket_lds_bytes(B) > (size_t)n->lds_max) occ = 0;
-    else if (bucket_occupancy(B, l.block, &occ) != hipSuccess) { (void)hipGetLastError(); occ = 0; }
     const int64_t G = owner_block_count(n, B);
     int64_t gmax = 0;
     for (int b = 0; b < n->h.n_inst; ++b)
       gmax = std::max<int64_t>(gmax, (n->inst_off_pad[b + 1] - n->inst_off_pad[b] + B - 1) / B);
+    if (bucket_lds_bytes(B) <= (size_t)n->lds_max &&
+        bucket_occupancy(B, l.block, (int)std::min<int64_t>(gmax, kBucketMaxProducers), &occ) != hipSuccess) {
+      (void)hipGetLastError();
+      occ = 0;
+    }
     if (gmax > kBucketMaxProducers || gmax > 2 * l.block) {
       if (why) *why = "an instance would have more than min(512, 2 x threads) workgroups";
       return false;
@@ -572,10 +576,10 @@ int bucket_shape(mc_net* n, const mc_launch& l, int* B_out) {
     *B_out = l.neurons_per_wg;
     return MC_OK;
   }
-  int occ = 1;
-  (void)bucket_occupancy(bmax, l.block, &occ);
-  int B = (int)align_up(std::max<int64_t>(4, (n->n_pad + (int64_t)n->n_cu * std::max(occ, 1) - 1) /
-                                                  ((int64_t)n->n_cu * std::max(occ, 1))), 4);
+  // the smallest block for which every workgroup is co-resident: several
+  // per compute unit where registers and LDS allow (the search starts at
+  // sixteen per compute unit)
+  int B = (int)align_up(std::max<int64_t>(4, (n->n_pad + (int64_t)n->n_cu * 16 - 1) / ((int64_t)n->n_cu * 16)), 4);
   for (; B <= bmax; B += 4)
     if (fits(B, &why)) { *B_out = B; return MC_OK; }
   return set_error(MC_ERR_RANGE, "bucket scheme: no co-resident shape for this network at this block size");
@@ -605,8 +609,10 @@ int setup_owner(mc_net* n, int targets, int max_targets) {
   for (int k = 0; k < nb; ++k) bmax = std::max(bmax, bt0[k + 1] - bt0[k]);
   if (bmax > max_targets) return set_error(MC_ERR_INVALID_ARG, "target blocks hold at most " + std::to_string(max_targets) + " targets");
   std::vector<int64_t> boff((size_t)n->n_pad + 1, 0);
+  int inst_max = 1;
   for (int b = 0; b < ni; ++b) {
     const int nblk = ((b + 1 < ni) ? ifb[b + 1] : nb) - ifb[b];
+    inst_max = std::max(inst_max, nblk);
     for (int64_t i = n->inst_off_pad[b]; i < n->inst_off_pad[b + 1]; ++i) boff[i + 1] = boff[i] + nblk + 1;
   }
   int rc;
@@ -628,6 +634,7 @@ int setup_owner(mc_net* n, int targets, int max_targets) {
   HIP_TRY(hipStreamSynchronize(n->stream));
   n->own_blocks = nb;
   n->own_bmax = bmax;
+  n->own_inst_max = inst_max;
   n->own_targets = targets;
   return MC_OK;
 }
@@ -1709,6 +1716,7 @@ int mc_tune(mc_net* n, int64_t steps, mc_launch* best) {
       {sizeof(mc_launch), MC_SCHEME_PERSISTENT_LDS, 512, 256, kPersistSteps, 0},
       {sizeof(mc_launch), MC_SCHEME_PERSISTENT_LDS, 512, 512, kPersistSteps, 0},
       {sizeof(mc_launch), MC_SCHEME_PERSISTENT_LDS, 256, 128, kPersistSteps, 0},
+      {sizeof(mc_launch), MC_SCHEME_PERSISTENT_BUCKETS, 192, 0, kPersistSteps, 0},
       {sizeof(mc_launch), MC_SCHEME_PERSISTENT_BUCKETS, 256, 0, kPersistSteps, 0},
       {sizeof(mc_launch), MC_SCHEME_PERSISTENT_BUCKETS, 512, 0, kPersistSteps, 0},
       {sizeof(mc_launch), MC_SCHEME_PERSISTENT_BUCKETS, 128, 0, kPersistSteps, 0},

@@ -116,7 +116,9 @@ __host__ __device__ size_t bucket_sum_slots(int B) { return (size_t)B; }
 // block size.
 // kRec: the adjoint's forward recording; kTime: phase timestamps.  Plain
 // simulation runs the instance with neither (fewer registers in use).
-template <bool kRec, bool kTime>
+// kBPoll: producers polled per lane (1 when no instance has more than 64
+// workgroups, else 8).
+template <bool kRec, bool kTime, int kBPoll>
 __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs a, int steps) {
   extern __shared__ __align__(16) unsigned char s_raw[];
   __shared__ uint64_t s_table[kMaxPops * kTableLen];
@@ -440,17 +442,17 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
       unsigned spins = 0;
       unsigned todo = 0;
 #pragma unroll
-      for (int rr = 0; rr < kBPollPerLane; ++rr)
+      for (int rr = 0; rr < kBPoll; ++rr)
         if (lane + 64 * rr < Gi) todo |= 1u << rr;
       while (todo) {
-        unsigned long long w0[kBPollPerLane];
+        unsigned long long w0[kBPoll];
 #pragma unroll
-        for (int rr = 0; rr < kBPollPerLane; ++rr)
+        for (int rr = 0; rr < kBPoll; ++rr)
           w0[rr] = ((todo >> rr) & 1u)
                        ? bld(&a.flags[((size_t)(gi0 + lane + 64 * rr) * kRecSlots + rslot) * kPersistFlagStride])
                        : 0ull;
 #pragma unroll
-        for (int rr = 0; rr < kBPollPerLane; ++rr) {
+        for (int rr = 0; rr < kBPoll; ++rr) {
           if (!((todo >> rr) & 1u) || (w0[rr] & 0xFFFF000000000000ull) != tag16) continue;
           const int hl = lane + 64 * rr, h = gi0 + hl;
           const int c = (int)((w0[rr] >> 36) & 0xFFFu);
@@ -487,7 +489,7 @@ __global__ __launch_bounds__(kBucketMaxBlock) void k_bucket(DevNet p, BucketArgs
           atomicOr(p.overflow, 2u);
           s_abort = 1;
 #pragma unroll
-          for (int rr = 0; rr < kBPollPerLane; ++rr)
+          for (int rr = 0; rr < kBPoll; ++rr)
             if ((todo >> rr) & 1u) s_cnt[lane + 64 * rr] = 0;
           break;
         }
@@ -599,15 +601,18 @@ size_t bucket_lds_bytes(int B) {
   return bucket_sum_slots(B) * sizeof(long long) + (size_t)B * (8 + 8 + 4 + 1 + 1);
 }
 
-// The four instances of k_bucket (recording, timing); shapes are checked
-// against all of them.
-const void* const kBucketFns[4] = {(const void*)k_bucket<false, false>, (const void*)k_bucket<true, false>,
-                                   (const void*)k_bucket<false, true>, (const void*)k_bucket<true, true>};
+// The instances of k_bucket (recording, timing, poll width); shapes are
+// checked against all of them.
+const void* const kBucketFns[8] = {
+    (const void*)k_bucket<false, false, 1>, (const void*)k_bucket<true, false, 1>,
+    (const void*)k_bucket<false, true, 1>,  (const void*)k_bucket<true, true, 1>,
+    (const void*)k_bucket<false, false, kBPollPerLane>, (const void*)k_bucket<true, false, kBPollPerLane>,
+    (const void*)k_bucket<false, true, kBPollPerLane>,  (const void*)k_bucket<true, true, kBPollPerLane>};
 
 template <bool kRec, bool kTime>
 static void launch_bucket_as(const DevNet& p, const BucketArgs& a, int steps, int block, hipStream_t s, hipEvent_t t0,
                              hipEvent_t t1) {
-  auto* const kf = k_bucket<kRec, kTime>;
+  auto* const kf = (a.inst_wg_max <= 64) ? k_bucket<kRec, kTime, 1> : k_bucket<kRec, kTime, kBPollPerLane>;
   if (t0 || t1)
     hipExtLaunchKernelGGL(kf, dim3(a.G), dim3(block), bucket_lds_bytes(a.B), s, t0, t1, 0, p, a, steps);
   else
@@ -626,9 +631,11 @@ hipError_t launch_bucket(const DevNet& p, const BucketArgs& a, int steps, int bl
   return hipGetLastError();
 }
 
-hipError_t bucket_occupancy(int B, int block, int* blocks_per_cu) {
+hipError_t bucket_occupancy(int B, int block, int inst_wg_max, int* blocks_per_cu) {
   *blocks_per_cu = 1 << 30;
-  for (const void* f : kBucketFns) {
+  const int first = (inst_wg_max <= 64) ? 0 : 4;   // the poll width launch_bucket picks
+  for (int k = first; k < first + 4; ++k) {
+    const void* f = kBucketFns[k];
     int occ = 0;
     const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, block, bucket_lds_bytes(B));
     if (e != hipSuccess) return e;

@@ -189,13 +189,16 @@ struct BucketArgs {
   long long wait_ticks;        // longest wait for one step's records (wall_clock64 ticks)
   int horizon;                 // ring slots ahead of the first step that may hold input at launch
   unsigned long long* phase;   // optional [G*8]: summed wall_clock64 ticks per phase (nullptr: off)
+  int inst_wg_max;             // most workgroups of one instance (<= 64: one producer polled per lane)
 };
 constexpr int kBucketMaxProducers = 512;   // workgroups of one instance
 constexpr int kBucketMaxBlock = 512;       // threads per workgroup
 constexpr int kBucketMaxB = 4092;          // targets per workgroup (12-bit local indices and count in the records)
 hipError_t launch_bucket(const DevNet& p, const BucketArgs& a, int steps, int block, hipStream_t s,
                          hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
-hipError_t bucket_occupancy(int B, int block, int* blocks_per_cu);
+// co-resident workgroups per CU of the instances launched when no instance
+// has more than inst_wg_max workgroups
+hipError_t bucket_occupancy(int B, int block, int inst_wg_max, int* blocks_per_cu);
 hipError_t bucket_set_lds_limit(size_t lds);
 __host__ __device__ size_t bucket_sum_slots(int B);
 size_t bucket_lds_bytes(int B);

@@ -103,7 +103,7 @@ def test_launch_configuration_invariance(scheme, block, npw, spg):
 TUNER_CANDIDATES = [(1, 512, 0, 10000, 0), (1, 256, 0, 10000, 0), (1, 512, 256, 10000, 0), (1, 512, 512, 10000, 0),
                     (1, 256, 128, 10000, 0), (0, 256, 256, 1000, 0), (0, 256, 256, 1000, 1), (0, 256, 1024, 1000, 0),
                     (0, 512, 512, 1000, 0), (0, 512, 512, 1000, 1), (0, 128, 128, 1000, 0), (0, 128, 128, 1000, 1),
-                    (3, 256, 0, 10000, 0), (3, 512, 0, 10000, 0), (3, 128, 0, 10000, 0)]
+                    (3, 192, 0, 10000, 0), (3, 256, 0, 10000, 0), (3, 512, 0, 10000, 0), (3, 128, 0, 10000, 0)]
 
 
 def test_every_autotuner_candidate_gives_the_same_bits():
