@@ -19,8 +19,8 @@
 // n+2's.  (The spike decision of a step needs I from before the step, so it
 // runs one step earlier: see the loop.)
 // Both come from a "near" table (the delay-1/2 synapses per source and
-// workgroup, as a CSR), delivered right after the spike list of step n is
-// complete.  The other events are pipelined over the two following steps,
+// workgroup, as a CSR), delivered as the spike list of step n fills (the
+// first ids while the poll goes on, the rest once the list is complete).  The other events are pipelined over the two following steps,
 // while the workgroup waits for the next spike lists: in step n+1 the block
 // bounds blk[i][g] of step n's spikes are loaded, in step n+2 their entries
 // (delay >= 3, landing at step n+3 or later) are added.  The poller lists the
@@ -35,7 +35,11 @@
 // (entries of 16 spikes, block bounds of 64) from an LDS counter, and the
 // updating wavefronts join the claiming once their record is out.  In a
 // quiet step the memory round trips of the pipelined delivery thus overlap
-// the update and the publication instead of following them.
+// the update and the publication instead of following them.  The last
+// wavefront without targets then adds the near events of the first ids the
+// poller lists (at most kEarlyNear) while the poll goes on; a step that
+// turns out to need the whole-step fallback takes them out again (the same
+// events with the opposite sign: integer sums cancel exactly) first.
 //
 // Spike exchange: workgroup g publishes a record per step (four per
 // workgroup, by step mod 4, so a record is never rewritten while a consumer
@@ -689,7 +693,7 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
     if (S <= kListCap && s_nbig <= kBigCap) {
       // ---- the spikes of step n are listed: fetch the ids beyond the
       //      seventh of busy producers, then each wavefront delivers the near
-      //      events of its share -------------------------------------------
+      //      events of its share of the ids not delivered during the poll ---
       if (timing) { const long long t = wall_clock64(); ph[2] += t - tp0; tp0 = t; }
       const int nbig = s_nbig;
       if (nbig > 0) {
