@@ -190,7 +190,11 @@ int mc_build_network(const mc_config* cfg, mc_net** out);
  * call over T_model after a presimulation), recording every spike.  Asynchronous on the network's stream;
  * getters synchronize.  Resumable: consecutive calls continue the same
  * trajectory bit for bit.  Errors: STATE (host-only or failed handle), HIP,
- * OOM (raster growth). */
+ * OOM (raster growth).  Test hook: the environment variable
+ * MC_PERSIST_LIST_CAP = k (1..1024) makes the persistent scheme, in the
+ * steps that mc_profile_phases runs, list every step of more than k spikes
+ * in producer order after the wait (the path of a step beyond its LDS
+ * list); results are unchanged. */
 int mc_simulate(mc_net* net, int64_t steps);
 
 /* For callers that cannot allocate memory (code under HIP graph capture,

@@ -265,6 +265,7 @@ struct mc_net {
     a.wait_ticks = (long long)wall_khz * 1000 * kWaitSeconds;
     a.phase = phase_on ? d_phase : nullptr;
     a.nb = d_nb; a.ne = d_ne;
+    if (const char* lc = getenv("MC_PERSIST_LIST_CAP")) a.list_cap = std::max(0, atoi(lc));
     return a;
   }
 

@@ -91,6 +91,10 @@ struct PersistArgs {
   // weight, bit 31 of the target field set for delay 2
   const unsigned* nb;          // [n_pad][G+1]
   const unsigned long long* ne;
+  // spikes of a step above which it is listed in producer order after the
+  // wait (0: the LDS list's capacity); a smaller value is a test hook that
+  // sends ordinary steps down that path (phase-timing instance only)
+  int list_cap;
 };
 constexpr int kPersistFlagStride = 8;
 constexpr int kRecSlots = 4;            // spike records (and side arrays) per workgroup, by step mod 4

@@ -313,6 +313,8 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
   const int Bg = a.bstart[g + 1] - a.bstart[g];                     // owned targets (multiple of 4, <= B)
   const long long n0 = *p.step_base;
   const int DL = a.DL;
+  // the listing threshold (a test hook, read by the phase-timing instance only)
+  const int list_cap = (kTime && a.list_cap > 0 && a.list_cap < kListCap) ? a.list_cap : kListCap;
   // Polling: the last wavefront polls every producer workgroup (lane l takes
   // producers l, l+64, ...); the other wavefronts work on the pipelined
   // delivery meanwhile.  A one-wavefront workgroup polls, then works.
@@ -623,7 +625,7 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
         }
         // the ids listed so far are complete records (a busy producer's
         // later ids come after the wait, so the count stops advancing there)
-        if (lane == 0 && s_nbig == 0 && s_nids <= kListCap)
+        if (lane == 0 && s_nbig == 0 && s_nids <= list_cap)
           __hip_atomic_store(&s_nready, s_nids, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (!todo) break;
         __builtin_amdgcn_s_sleep(1);
@@ -690,7 +692,7 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
     if (s_abort) break;
     int S = s_nids;
     int* ids_n = s_ids + par * kListCap;
-    if (S <= kListCap && s_nbig <= kBigCap) {
+    if (S <= list_cap && s_nbig <= kBigCap) {
       // ---- the spikes of step n are listed: fetch the ids beyond the
       //      seventh of busy producers, then each wavefront delivers the near
       //      events of its share of the ids not delivered during the poll ---

@@ -120,6 +120,27 @@ def test_every_autotuner_candidate_gives_the_same_bits():
         net.close()
 
 
+@pytest.mark.parametrize("block", [512, 256])
+def test_producer_order_listing_after_early_near_delivery(block, monkeypatch):
+    """The persistent scheme adds the near events of the first listed ids
+    while the poll goes on; a step that is then listed in producer order
+    after the wait takes those events out again before delivering the step.
+    With the listing threshold lowered to 8 spikes (a test hook, honoured by
+    the phase-timing kernel that mc_profile_phases runs), most steps of the
+    balanced network (~15 spikes each) take that path, with the early
+    delivery in a wavefront without targets: the trajectory is still the
+    oracle's, bit for bit."""
+    monkeypatch.setenv("MC_PERSIST_LIST_CAP", "8")
+    w = workloads.balanced()
+    o = oracle.Oracle(w.to_dict())
+    o.run(900)
+    net = mc.Network(w)
+    net.set_launch(scheme=1, block=block, neurons_per_wg=0, steps_per_graph=300)
+    net.profile_phases(900)
+    assert_same(net, o, ring_depth=128, what=f"list threshold 8, block {block}")
+    net.close()
+
+
 @pytest.mark.parametrize("scheme", [0, 1, 2, 3])
 def test_all_delays_one_step(scheme):
     """Every synapse with the smallest delay (one step): every event must be
