@@ -361,11 +361,10 @@ int mc_probe_exchange(mc_net* net, int64_t steps, double* us_per_step_out);
 int mc_last_simulate_ms(mc_net* net, double* ms_out);
 /* Persistent schemes: the summed durations (ms) of the persistent kernel's
  * launches in the most recent mc_simulate (or mc_simulate_noalloc), how many
- * launches were timed (at most 64) and the steps they covered.  A direct
- * launch is timed by HIP events its own dispatch timestamps (kernel start and
- * end); a launch replayed from a graph by HIP events recorded on the
- * simulation stream right before and after the graph launch.  Zero launches
- * under the other schemes.  Synchronizes on that call. */
+ * launches were timed (at most 64) and the steps they covered.  Every launch,
+ * direct or replayed from a graph, is timed by HIP events recorded on the
+ * simulation stream right before and after it.  Zero launches under the
+ * other schemes.  Synchronizes on that call. */
 int mc_last_kernel_ms(mc_net* net, double* ms_out, int64_t* launches_out, int64_t* steps_out);
 /* GPU time (ms, HIP events) of the most recent mc_adjoint: its forward
  * (S steps with checkpoints) and its reverse pass (recompute, adjoint,

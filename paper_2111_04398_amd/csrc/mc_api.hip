@@ -739,8 +739,7 @@ int apply_launch(mc_net* n, const mc_launch& l) {
 }
 
 // Enqueues `count` steps directly (no graph) on stream s.
-// t0/t1: events the persistent kernel's dispatch timestamps (nullptr: untimed)
-hipError_t enqueue_direct(mc_net* n, int count, hipStream_t s, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr) {
+hipError_t enqueue_direct(mc_net* n, int count, hipStream_t s) {
   const DevNet p = n->dev();
   hipError_t e = hipSuccess;
   if (n->launch.scheme == MC_SCHEME_STEP_KERNELS) {
@@ -754,9 +753,9 @@ hipError_t enqueue_direct(mc_net* n, int count, hipStream_t s, hipEvent_t t0 = n
       if (e == hipSuccess) e = launch_owner(p, a, k, s);
     }
   } else if (n->launch.scheme == MC_SCHEME_PERSISTENT_BUCKETS) {
-    return launch_bucket(p, n->bucket(), count, n->launch.block, s, t0, t1);     // advances the step counter itself
+    return launch_bucket(p, n->bucket(), count, n->launch.block, s);     // advances the step counter itself
   } else {
-    return launch_persist(p, n->persist(), count, n->launch.block, s, t0, t1);   // advances the step counter itself
+    return launch_persist(p, n->persist(), count, n->launch.block, s);   // advances the step counter itself
   }
   if (e == hipSuccess) e = launch_advance(n->d_step, count, s);
   return e;
@@ -797,18 +796,6 @@ int launch_event(mc_net* n, bool begin, int64_t steps) {
   return MC_OK;
 }
 
-// The event pair of the next timed persistent launch that the dispatch
-// itself timestamps (kernel start and end, no launch gap), if any is left.
-bool dispatch_events(mc_net* n, hipEvent_t* t0, hipEvent_t* t1) {
-  *t0 = *t1 = nullptr;
-  if ((n->launch.scheme != MC_SCHEME_PERSISTENT_LDS && n->launch.scheme != MC_SCHEME_PERSISTENT_BUCKETS) ||
-      n->ev_launch.size() < (size_t)kLaunchEvents || 2 * n->launches_timed + 1 >= kLaunchEvents)
-    return false;
-  *t0 = n->ev_launch[(size_t)2 * n->launches_timed];
-  *t1 = n->ev_launch[(size_t)2 * n->launches_timed + 1];
-  return true;
-}
-
 // Enqueues `steps` steps (no synchronization).  Steps are replayed from a
 // graph of steps_per_graph steps where possible (0: never).
 int enqueue_steps(mc_net* n, int64_t steps) {
@@ -833,10 +820,11 @@ int enqueue_steps(mc_net* n, int64_t steps) {
       chunk = reps * S;
     } else {
       chunk = std::min<int64_t>(chunk, 1 << 20);
-      hipEvent_t t0, t1;
-      const bool timed = dispatch_events(n, &t0, &t1);
-      HIP_TRY(enqueue_direct(n, (int)chunk, n->stream, t0, t1));
-      if (timed) { ++n->launches_timed; n->steps_timed += chunk; }
+      // stream events around the launch (events that the dispatch itself
+      // timestamps cost ~17 us per launch, a tenth of a 20-step call)
+      if ((rc = launch_event(n, true, chunk)) != MC_OK) return rc;
+      HIP_TRY(enqueue_direct(n, (int)chunk, n->stream));
+      if ((rc = launch_event(n, false, chunk)) != MC_OK) return rc;
     }
     n->steps_since_drain += chunk;
     n->step += chunk;
@@ -1100,10 +1088,9 @@ int mc_simulate_noalloc(mc_net* n, int64_t steps) {
   int rc;
   for (int64_t left = steps; left > 0;) {
     const int chunk = (int)std::min<int64_t>(left, 1 << 20);
-    hipEvent_t t0, t1;
-    const bool timed = dispatch_events(n, &t0, &t1);
-    HIP_TRY(launch_persist(p, a, chunk, n->launch.block, n->stream, t0, t1));
-    if (timed) { ++n->launches_timed; n->steps_timed += chunk; }
+    if ((rc = launch_event(n, true, chunk)) != MC_OK) return rc;
+    HIP_TRY(launch_persist(p, a, chunk, n->launch.block, n->stream));
+    if ((rc = launch_event(n, false, chunk)) != MC_OK) return rc;
     left -= chunk;
   }
   n->steps_since_drain += steps;

@@ -51,7 +51,6 @@
 
 #include <algorithm>
 
-#include <hip/hip_ext.h>
 #include "mc_device.h"
 
 namespace mc {
@@ -610,24 +609,19 @@ const void* const kBucketFns[8] = {
     (const void*)k_bucket<false, true, kBPollPerLane>,  (const void*)k_bucket<true, true, kBPollPerLane>};
 
 template <bool kRec, bool kTime>
-static void launch_bucket_as(const DevNet& p, const BucketArgs& a, int steps, int block, hipStream_t s, hipEvent_t t0,
-                             hipEvent_t t1) {
+static void launch_bucket_as(const DevNet& p, const BucketArgs& a, int steps, int block, hipStream_t s) {
   auto* const kf = (a.inst_wg_max <= 64) ? k_bucket<kRec, kTime, 1> : k_bucket<kRec, kTime, kBPollPerLane>;
-  if (t0 || t1)
-    hipExtLaunchKernelGGL(kf, dim3(a.G), dim3(block), bucket_lds_bytes(a.B), s, t0, t1, 0, p, a, steps);
-  else
-    hipLaunchKernelGGL(kf, dim3(a.G), dim3(block), bucket_lds_bytes(a.B), s, p, a, steps);
+  hipLaunchKernelGGL(kf, dim3(a.G), dim3(block), bucket_lds_bytes(a.B), s, p, a, steps);
 }
 
-hipError_t launch_bucket(const DevNet& p, const BucketArgs& a, int steps, int block, hipStream_t s, hipEvent_t t0,
-                         hipEvent_t t1) {
+hipError_t launch_bucket(const DevNet& p, const BucketArgs& a, int steps, int block, hipStream_t s) {
   // a thread owns at most 64 targets (its spike mask), so B <= 64 threads
   if (a.B < 4 || a.B > 64 * block) return hipErrorInvalidValue;
   const bool rec = p.xrec != nullptr || p.ck_y != nullptr, tim = a.phase != nullptr;
-  if (rec && tim) launch_bucket_as<true, true>(p, a, steps, block, s, t0, t1);
-  else if (rec) launch_bucket_as<true, false>(p, a, steps, block, s, t0, t1);
-  else if (tim) launch_bucket_as<false, true>(p, a, steps, block, s, t0, t1);
-  else launch_bucket_as<false, false>(p, a, steps, block, s, t0, t1);
+  if (rec && tim) launch_bucket_as<true, true>(p, a, steps, block, s);
+  else if (rec) launch_bucket_as<true, false>(p, a, steps, block, s);
+  else if (tim) launch_bucket_as<false, true>(p, a, steps, block, s);
+  else launch_bucket_as<false, false>(p, a, steps, block, s);
   return hipGetLastError();
 }
 

@@ -113,10 +113,7 @@ hipError_t launch_near_fill(const int32_t* tgt, const int32_t* wq, const uint8_t
 hipError_t persist_static_lds(size_t* bytes);
 hipError_t persist_occupancy(int block, size_t lds, int* blocks_per_cu);
 hipError_t persist_set_lds_limit(size_t lds);
-// With t0/t1 the dispatch itself timestamps the two events (start and end
-// of the kernel), else the launch is untimed.
-hipError_t launch_persist(const DevNet& p, const PersistArgs& a, int steps, int block, hipStream_t s,
-                          hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
+hipError_t launch_persist(const DevNet& p, const PersistArgs& a, int steps, int block, hipStream_t s);
 // Scratch of the allocation-free entry point (mc_noalloc.hip): spike records
 // (noalloc_record_words() words, room for 512 workgroups) and the side array
 // (512 x kRecSlots x 512 ints) of this device; and a record clear by kernel.
@@ -198,8 +195,7 @@ struct BucketArgs {
 constexpr int kBucketMaxProducers = 512;   // workgroups of one instance
 constexpr int kBucketMaxBlock = 512;       // threads per workgroup
 constexpr int kBucketMaxB = 4092;          // targets per workgroup (12-bit local indices and count in the records)
-hipError_t launch_bucket(const DevNet& p, const BucketArgs& a, int steps, int block, hipStream_t s,
-                         hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
+hipError_t launch_bucket(const DevNet& p, const BucketArgs& a, int steps, int block, hipStream_t s);
 // co-resident workgroups per CU of the instances launched when no instance
 // has more than inst_wg_max workgroups
 hipError_t bucket_occupancy(int B, int block, int inst_wg_max, int* blocks_per_cu);

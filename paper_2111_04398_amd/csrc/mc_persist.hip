@@ -66,7 +66,6 @@
 #pragma clang fp contract(off)
 
 #include <algorithm>
-#include <hip/hip_ext.h>
 #include "mc_device.h"
 
 namespace mc {
@@ -1009,23 +1008,18 @@ hipError_t persist_occupancy(int block, size_t lds, int* blocks_per_cu) {
 }
 
 template <bool kRec, bool kTime>
-static void launch_persist_as(const DevNet& p, const PersistArgs& a, int steps, int block, size_t lds, hipStream_t s,
-                              hipEvent_t t0, hipEvent_t t1) {
+static void launch_persist_as(const DevNet& p, const PersistArgs& a, int steps, int block, size_t lds, hipStream_t s) {
   auto* const kf = (a.G <= 256) ? k_persist<kRec, kTime, 4> : k_persist<kRec, kTime, 8>;
-  if (t0 || t1)
-    hipExtLaunchKernelGGL(kf, dim3(a.G), dim3(block), lds, s, t0, t1, 0, p, a, steps);
-  else
-    hipLaunchKernelGGL(kf, dim3(a.G), dim3(block), lds, s, p, a, steps);
+  hipLaunchKernelGGL(kf, dim3(a.G), dim3(block), lds, s, p, a, steps);
 }
 
-hipError_t launch_persist(const DevNet& p, const PersistArgs& a, int steps, int block, hipStream_t s, hipEvent_t t0,
-                          hipEvent_t t1) {
+hipError_t launch_persist(const DevNet& p, const PersistArgs& a, int steps, int block, hipStream_t s) {
   const size_t lds = persist_lds_bytes(a.G, a.B, a.DL);
   const bool rec = p.xrec != nullptr || p.ck_y != nullptr, tim = a.phase != nullptr;
-  if (rec && tim) launch_persist_as<true, true>(p, a, steps, block, lds, s, t0, t1);
-  else if (rec) launch_persist_as<true, false>(p, a, steps, block, lds, s, t0, t1);
-  else if (tim) launch_persist_as<false, true>(p, a, steps, block, lds, s, t0, t1);
-  else launch_persist_as<false, false>(p, a, steps, block, lds, s, t0, t1);
+  if (rec && tim) launch_persist_as<true, true>(p, a, steps, block, lds, s);
+  else if (rec) launch_persist_as<true, false>(p, a, steps, block, lds, s);
+  else if (tim) launch_persist_as<false, true>(p, a, steps, block, lds, s);
+  else launch_persist_as<false, false>(p, a, steps, block, lds, s);
   return hipGetLastError();
 }
 
