@@ -45,19 +45,21 @@
 // workgroup, by step mod 4, so a record is never rewritten while a consumer
 // one step behind may still read it).  Compaction is one ballot per
 // wavefront (kept in LDS by step parity): a spike's position is the number
-// of spikes of lower threads, and each spiking thread stores its own id into
-// the record or the side array.  Word 0 = tag16 << 48 | count
-// << 36 | the block-local indices (9 bits each) of the first four spikes,
-// with tag16 = (step + 1) mod 65535 + 1 (never 0, distinct for consecutive
-// steps); words 1..3 = (step + 1) << 32 | id of spikes 5..7.  About four in
-// five workgroups publish no spike in a step and nearly all others at most
-// four, so one load of word 0 usually completes a record.  Every word carries
+// of spikes of lower threads; the first 39 spikes go into the record's
+// words (composed from the ballots by lanes 0..7 of wavefront 0), the rest
+// each spiking thread stores into the side array.  Word 0 = tag16 << 48 |
+// count << 36 | the block-local indices (9 bits each) of the first four
+// spikes, with tag16 = (step + 1) mod 65535 + 1 (never 0, distinct for
+// consecutive steps); word L = 1..7 = tag16 << 48 | the indices of spikes
+// 5L..5L+4.  About four in five workgroups publish no spike in a step and
+// nearly all others at most four, so one load of word 0 usually completes a
+// record, and the records of a burst carry up to 39 ids without a side array.  Every word carries
 // a tag, so a consumer accepts a record when all the words it needs show the
 // current step, whatever order the stores became visible in; a tag is the
 // step alone, which suffices because the last workgroup to finish a launch
 // clears every record, so that no record outlives the launch that wrote it
 // (also across rewinds of the state to earlier steps).  Spikes beyond
-// the seventh are written to a side array before word 0 (with a wait for
+// the 39th are written to a side array before word 0 (with a wait for
 // their completion), so they are visible once word 0 is.  All of these are
 // device-scope atomic accesses (coherent at the memory side), so the step
 // needs no L2 writeback or invalidate.  Every wait is bounded in time (wall
@@ -73,8 +75,9 @@ namespace mc {
 namespace {
 
 constexpr int kListCap = 1024;       // spikes of one step kept in LDS (more: delivered at once)
-constexpr int kInline = 7;           // spike ids carried by a record (more: side array)
-constexpr int kW0Ids = 4;            // of which in word 0 (9-bit block-local indices)
+constexpr int kW0Ids = 4;            // spike ids in word 0 of a record (9-bit block-local indices)
+constexpr int kWIds = 5;             // in each of words 1..7
+constexpr int kInline = kW0Ids + (kPersistFlagStride - 1) * kWIds;   // 39 carried by a record (more: side array)
 constexpr int kBigCap = 64;          // producers with more than kInline spikes listed per step
 constexpr int kEarlyNear = 64;       // ids near-delivered during the poll at most (all waves share the rest)
 constexpr int kItemSpikes = 16;      // spikes per claimed item of pipelined entries (~ one 256-entry chunk)
@@ -275,7 +278,7 @@ __device__ __forceinline__ void wave_near(const PersistArgs& a, const Block& b, 
 
 }  // namespace
 
-// LDS (dynamic): acc[DL*B] i64 | fbits[128*BW] u32 | s_pre[G+1] | s_inl[G*7] | s_ids[2][kListCap]
+// LDS (dynamic): acc[DL*B] i64 | fbits[128*BW] u32 | s_pre[G+1] | s_ids[2][kListCap]
 //                | s_len[2][kListCap] | s_lo[2][kListCap] i64
 // kRec: the adjoint's forward recording (input x and state checkpoints);
 // kTime: phase timestamps.  Plain simulation runs the instance with neither,
@@ -300,8 +303,7 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
   long long* acc = reinterpret_cast<long long*>(s_raw);
   unsigned* fbits = reinterpret_cast<unsigned*>(acc + (size_t)a.DL * a.B);
   int* s_pre = reinterpret_cast<int*>(fbits + 128 * a.BW);        // [G+1]
-  int* s_inl = s_pre + (a.G + 1);                                   // [G*7] inline ids per producer
-  int* s_ids = s_inl + a.G * kInline;                               // [2][kListCap] spike ids by step parity
+  int* s_ids = s_pre + (a.G + 1);                                   // [2][kListCap] spike ids by step parity
   int* s_len = s_ids + 2 * kListCap;                                // [2][kListCap] block sub-row lengths
   long long* s_lo = reinterpret_cast<long long*>(((uintptr_t)(s_len + 2 * kListCap) + 15) & ~(uintptr_t)15);
 
@@ -500,7 +502,6 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
       nloc += c;
     }
     pos += __popcll(bal & ((tid & 63) ? (~0ull >> (64 - (tid & 63))) : 0ull));
-    const unsigned long long tag = (unsigned long long)(m + 1) << 32;
     const unsigned long long tag16 = (unsigned long long)t16m << 48;
     const size_t rec = (size_t)g * kRecSlots + (size_t)(m & (kRecSlots - 1));
     unsigned long long* myrec = a.flags + rec * kPersistFlagStride;
@@ -508,26 +509,37 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
     if (spiked) {
       const int id = (int)(j0 + tid);
       if (pos >= kInline) st_dev(&a.pub[rec * a.B + pos], id);
-      else if (pos >= kW0Ids) st_dev(&myrec[1 + pos - kW0Ids], tag | (unsigned)id);
       if (fits) p.raster[(size_t)g * p.raster_cap + rcnt + pos] = make_int2((int)m, id);
     }
     if (nloc > kInline) {                   // side-array ids complete before word 0
       __builtin_amdgcn_s_waitcnt(0);
       upd_sync(&s_sidecnt, side_epoch);
     }
-    if (tid == 0) {                         // word 0: count and the local indices of the first four spikes
-      unsigned long long w0 = tag16 | (unsigned long long)nloc << 36;
-      int f = 0;
+    // word L (lanes 0..7 of wavefront 0): word 0 the count and the block-local
+    // indices of spikes 1..4, word L >= 1 those of spikes 5L..5L+4; each word
+    // carries the step tag
+    if (tid < kPersistFlagStride) {
+      const int L = tid;
+      const int first = (L == 0) ? 0 : kW0Ids + (L - 1) * kWIds, nf = (L == 0) ? kW0Ids : kWIds;
+      if (L == 0 || nloc > first) {
+        unsigned long long wv = tag16 | ((L == 0) ? (unsigned long long)nloc << 36 : 0ull);
+        int seen = 0, f = 0;
 #pragma unroll
-      for (int w = 0; w < kPersistMaxBlock / 64; ++w) {
-        uint64_t mm = mr[w];
-        while (mm && f < kW0Ids) {
-          w0 |= (unsigned long long)(64 * w + __builtin_ctzll(mm)) << (9 * f);
-          mm &= mm - 1;
-          ++f;
+        for (int w = 0; w < kPersistMaxBlock / 64; ++w) {
+          uint64_t mm = mr[w];
+          const int cw = __popcll(mm);
+          if (seen + cw <= first) { seen += cw; continue; }
+          while (mm && f < nf) {
+            if (seen >= first) {
+              wv |= (unsigned long long)(64 * w + __builtin_ctzll(mm)) << (9 * f);
+              ++f;
+            }
+            ++seen;
+            mm &= mm - 1;
+          }
         }
+        st_dev(&myrec[L], wv);
       }
-      st_dev(&myrec[0], w0);
     }
     if (fits) rcnt += nloc;
     else if (tid == 0) atomicOr(p.overflow, 1u);
@@ -561,7 +573,6 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
       // drive of step n+1
       if (upd && it + 1 < steps) kdrive = (int)((drive_counts(n + 1, qlocal, seed, qpops, s_table) >> (8 * qk)) & 0xFFu);
     }
-    const unsigned long long tag = (unsigned long long)(n + 1) << 32;              // records of step n
     const unsigned long long tag16 = (unsigned long long)t16n << 48;
     // ---- while the records of step n arrive: polling (the last wavefront,
     //      from the top of the step unless it holds targets); the pipelined
@@ -588,33 +599,32 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
           if (!((todo >> r) & 1u) || (w0[r] & 0xFFFF000000000000ull) != tag16) continue;
           const int h = lane + 64 * r;
           const int c = (int)((w0[r] >> 36) & 0x3FFu);
-          // ids 5..7 (one round trip for the three words, then their tags)
-          unsigned long long wk[kInline - kW0Ids];
+          // words 1.. for spikes 5..39 (one round trip for them, then their tags)
+          constexpr int kMoreWords = kPersistFlagStride - 1;
+          unsigned long long wk[kMoreWords];
+          const int nwk = (c > kW0Ids) ? (min(c, kInline) - kW0Ids + kWIds - 1) / kWIds : 0;
           bool ok = true;
-          if (c > kW0Ids) {
+          if (nwk > 0) {
             const unsigned long long* rec = a.flags + ((size_t)h * kRecSlots + rslot) * kPersistFlagStride;
 #pragma unroll
-            for (int k = 0; k < kInline - kW0Ids; ++k) wk[k] = ld_dev(&rec[1 + k]);
+            for (int k = 0; k < kMoreWords; ++k) wk[k] = (k < nwk) ? ld_dev(&rec[1 + k]) : 0ull;
 #pragma unroll
-            for (int k = 0; k < kInline - kW0Ids; ++k)
-              if (kW0Ids + k < c) ok &= ((wk[k] & 0xFFFFFFFF00000000ull) == tag);
+            for (int k = 0; k < kMoreWords; ++k)
+              if (k < nwk) ok &= ((wk[k] & 0xFFFF000000000000ull) == tag16);
           }
           if (!ok) continue;
-#pragma unroll
-          for (int k = 0; k < kW0Ids; ++k)
-            if (k < c) s_inl[h * kInline + k] = pbs[r] + (int)((w0[r] >> (9 * k)) & 0x1FFu);
-          if (c > kW0Ids) {
-#pragma unroll
-            for (int k = 0; k < kInline - kW0Ids; ++k)
-              if (kW0Ids + k < c) s_inl[h * kInline + kW0Ids + k] = (int)(wk[k] & 0xFFFFFFFFu);
-          }
           s_cnt[h] = c;
           // the step's id list in arrival order (the order of integer sums
-          // does not matter); ids beyond the seventh are fetched after the wait
+          // does not matter); ids beyond the 39th are fetched after the wait
           if (c > 0) {
             const int o = atomicAdd(&s_nids, c);
-            for (int k = 0; k < min(c, kInline); ++k)
-              if (o + k < kListCap) s_ids[par * kListCap + o + k] = s_inl[h * kInline + k];
+            const int ci = min(c, kInline);
+            for (int k = 0; k < ci; ++k) {
+              if (o + k >= kListCap) break;
+              const unsigned long long wv = (k < kW0Ids) ? w0[r] : wk[(k - kW0Ids) / kWIds];
+              const int f = (k < kW0Ids) ? k : (k - kW0Ids) % kWIds;
+              s_ids[par * kListCap + o + k] = pbs[r] + (int)((wv >> (9 * f)) & 0x1FFu);
+            }
             if (c > kInline) {
               const int b = atomicAdd(&s_nbig, 1);
               if (b < kBigCap) s_big[b] = make_int2(h, o);
@@ -693,7 +703,7 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
     int* ids_n = s_ids + par * kListCap;
     if (S <= list_cap && s_nbig <= kBigCap) {
       // ---- the spikes of step n are listed: fetch the ids beyond the
-      //      seventh of busy producers, then each wavefront delivers the near
+      //      39th of busy producers, then each wavefront delivers the near
       //      events of its share of the ids not delivered during the poll ---
       if (timing) { const long long t = wall_clock64(); ph[2] += t - tp0; tp0 = t; }
       const int nbig = s_nbig;
@@ -739,7 +749,14 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
         int lo = 0, hi = a.G;                 // producer h: s_pre[h] <= gk < s_pre[h+1]
         while (hi - lo > 1) { const int mid = (lo + hi) >> 1; if (s_pre[mid] <= gk) lo = mid; else hi = mid; }
         const int kk = gk - s_pre[lo];
-        ids_n[k] = (kk < kInline) ? s_inl[lo * kInline + kk] : ld_dev(&a.pub[((size_t)lo * kRecSlots + rslot) * a.B + kk]);
+        if (kk < kInline) {                   // from the producer's record word (still this step's)
+          const int wi = (kk < kW0Ids) ? 0 : 1 + (kk - kW0Ids) / kWIds;
+          const int f = (kk < kW0Ids) ? kk : (kk - kW0Ids) % kWIds;
+          const unsigned long long wv = ld_dev(&a.flags[((size_t)lo * kRecSlots + rslot) * kPersistFlagStride + wi]);
+          ids_n[k] = a.bstart[lo] + (int)((wv >> (9 * f)) & 0x1FFu);
+        } else {
+          ids_n[k] = ld_dev(&a.pub[((size_t)lo * kRecSlots + rslot) * a.B + kk]);
+        }
       }
       if (timing) { const long long t = wall_clock64(); ph[3] += t - tp0; tp0 = t; }
       if (S <= kListCap) {
@@ -971,7 +988,7 @@ __global__ void k_near_fill(const int32_t* tgt, const int32_t* wq, const uint8_t
 
 size_t persist_lds_bytes(int G, int B, int DL) {
   const int BW = (B + 31) / 32;
-  size_t b = (size_t)DL * B * 8 + (size_t)128 * BW * 4 + (size_t)(G + 1) * 4 + (size_t)G * kInline * 4 +
+  size_t b = (size_t)DL * B * 8 + (size_t)128 * BW * 4 + (size_t)(G + 1) * 4 +
              (size_t)kListCap * 4 * 4;
   b = (b + 15) & ~(size_t)15;
   return b + (size_t)2 * kListCap * 8;
