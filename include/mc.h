@@ -363,8 +363,11 @@ int mc_last_simulate_ms(mc_net* net, double* ms_out);
  * launches in the most recent mc_simulate (or mc_simulate_noalloc), how many
  * launches were timed (at most 64) and the steps they covered.  Every launch,
  * direct or replayed from a graph, is timed by HIP events recorded on the
- * simulation stream right before and after it.  Zero launches under the
- * other schemes.  Synchronizes on that call. */
+ * simulation stream right before and after it; an mc_simulate call that is a
+ * single launch is timed by the call's own two events instead (each event on
+ * the stream lengthens the call by a few microseconds), so then the result
+ * equals mc_last_simulate_ms.  Zero launches under the other schemes.
+ * Synchronizes on that call. */
 int mc_last_kernel_ms(mc_net* net, double* ms_out, int64_t* launches_out, int64_t* steps_out);
 /* GPU time (ms, HIP events) of the most recent mc_adjoint: its forward
  * (S steps with checkpoints) and its reverse pass (recompute, adjoint,

@@ -204,8 +204,10 @@ struct mc_net {
   int graph_steps = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_mid = nullptr;
   // HIP events around every persistent-kernel launch of the latest
-  // mc_simulate (pairs k, k+1; at most kLaunchEvents / 2 launches timed)
+  // mc_simulate (pairs k, k+1; at most kLaunchEvents / 2 launches timed);
+  // a call that is one launch is timed by ev0 and ev1 (whole_call)
   std::vector<hipEvent_t> ev_launch;
+  bool whole_call = false;
   std::vector<unsigned char> dq;       // 1024 quantiles of the store's delay histogram (atomic probe)
   int launches_timed = 0;
   int64_t steps_timed = 0;
@@ -785,10 +787,18 @@ constexpr int kLaunchEvents = 128;
 
 // Records the event that opens (begin) or closes a timed persistent launch on
 // the simulation stream; beyond kLaunchEvents / 2 launches nothing is timed.
-int launch_event(mc_net* n, bool begin, int64_t steps) {
+// A launch that is a whole mc_simulate call (`whole`: nothing else between the
+// call's events ev0 and ev1) records nothing and is timed by those two: every
+// event on the stream lengthens the call by ~4.5 us, a few per cent of a
+// 20-step call.
+int launch_event(mc_net* n, bool begin, int64_t steps, bool whole = false) {
   if ((n->launch.scheme != MC_SCHEME_PERSISTENT_LDS && n->launch.scheme != MC_SCHEME_PERSISTENT_BUCKETS) ||
       n->ev_launch.size() < (size_t)kLaunchEvents)
     return MC_OK;
+  if (whole) {
+    if (!begin) { n->whole_call = true; n->launches_timed = 1; n->steps_timed = steps; }
+    return MC_OK;
+  }
   const int k = 2 * n->launches_timed + (begin ? 0 : 1);
   if (k >= kLaunchEvents) return MC_OK;
   HIP_TRY(hipEventRecord(n->ev_launch[(size_t)k], n->stream));
@@ -797,34 +807,40 @@ int launch_event(mc_net* n, bool begin, int64_t steps) {
 }
 
 // Enqueues `steps` steps (no synchronization).  Steps are replayed from a
-// graph of steps_per_graph steps where possible (0: never).
-int enqueue_steps(mc_net* n, int64_t steps) {
+// graph of steps_per_graph steps where possible (0: never).  `call_events`:
+// the caller has just recorded ev0 and records ev1 right after, so a call
+// that is one launch is timed by those.
+int enqueue_steps(mc_net* n, int64_t steps, bool call_events = false) {
   int rc;
   int64_t left = steps;
+  bool drained = false;
   while (left > 0) {
     int64_t room = n->cap_steps - n->steps_since_drain;
     if (room <= 0) {
       if ((rc = drain(n)) != MC_OK) return rc;
       room = n->cap_steps;
+      drained = true;
     }
     int64_t chunk = std::min(left, room);
     const int S = n->launch.steps_per_graph;
     if (S > 0 && chunk >= S) {
       if ((rc = build_graph(n)) != MC_OK) return rc;
       const int64_t reps = chunk / S;
+      const bool whole = call_events && !drained && reps == 1 && S == steps;
       for (int64_t k = 0; k < reps; ++k) {
-        if ((rc = launch_event(n, true, S)) != MC_OK) return rc;
+        if ((rc = launch_event(n, true, S, whole)) != MC_OK) return rc;
         HIP_TRY(hipGraphLaunch(n->graph, n->stream));
-        if ((rc = launch_event(n, false, S)) != MC_OK) return rc;
+        if ((rc = launch_event(n, false, S, whole)) != MC_OK) return rc;
       }
       chunk = reps * S;
     } else {
       chunk = std::min<int64_t>(chunk, 1 << 20);
-      // stream events around the launch (events that the dispatch itself
-      // timestamps cost ~17 us per launch, a tenth of a 20-step call)
-      if ((rc = launch_event(n, true, chunk)) != MC_OK) return rc;
+      // stream events around the launch, unless the call's own bracket it
+      // (events that the dispatch itself timestamps cost ~17 us per launch)
+      const bool whole = call_events && !drained && chunk == steps;
+      if ((rc = launch_event(n, true, chunk, whole)) != MC_OK) return rc;
       HIP_TRY(enqueue_direct(n, (int)chunk, n->stream));
-      if ((rc = launch_event(n, false, chunk)) != MC_OK) return rc;
+      if ((rc = launch_event(n, false, chunk, whole)) != MC_OK) return rc;
     }
     n->steps_since_drain += chunk;
     n->step += chunk;
@@ -1053,7 +1069,8 @@ int mc_simulate(mc_net* n, int64_t steps) {
   HIP_TRY(hipEventRecord(n->ev0, n->stream));
   n->launches_timed = 0;
   n->steps_timed = 0;
-  int rc = enqueue_steps(n, steps);
+  n->whole_call = false;
+  int rc = enqueue_steps(n, steps, true);
   if (rc != MC_OK) { n->failed = true; return rc; }
   HIP_TRY(hipEventRecord(n->ev1, n->stream));
   return MC_OK;
@@ -1080,6 +1097,7 @@ int mc_simulate_noalloc(mc_net* n, int64_t steps) {
   HIP_TRY(hipEventRecord(n->ev0, n->stream));
   n->launches_timed = 0;
   n->steps_timed = 0;
+  n->whole_call = false;
   HIP_TRY(launch_clear_records(rec, persist_flag_words(n->pG), n->stream));
   const DevNet p = n->dev();
   PersistArgs a = n->persist();
@@ -1105,7 +1123,8 @@ int mc_last_kernel_ms(mc_net* n, double* ms_out, int64_t* launches_out, int64_t*
   double total = 0.0;
   for (int k = 0; k < n->launches_timed; ++k) {
     float ms = 0;
-    HIP_TRY(hipEventElapsedTime(&ms, n->ev_launch[(size_t)2 * k], n->ev_launch[(size_t)2 * k + 1]));
+    if (n->whole_call) HIP_TRY(hipEventElapsedTime(&ms, n->ev0, n->ev1));
+    else HIP_TRY(hipEventElapsedTime(&ms, n->ev_launch[(size_t)2 * k], n->ev_launch[(size_t)2 * k + 1]));
     total += ms;
   }
   *ms_out = total;
@@ -1407,6 +1426,9 @@ int mc_profile_phases(mc_net* n, int64_t steps, double* us) {
   const int spg = n->launch.steps_per_graph;
   n->launch.steps_per_graph = 0;
   n->phase_on = true;
+  n->launches_timed = 0;
+  n->steps_timed = 0;
+  n->whole_call = false;
   rc = enqueue_steps(n, steps);
   n->phase_on = false;
   n->launch.steps_per_graph = spg;

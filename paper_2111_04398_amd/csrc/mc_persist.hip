@@ -338,30 +338,39 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
   // delay, or further after an injection or a loaded state).  Inside a launch
   // only the owner workgroup touches its targets' ring entries, so device-
   // scope loads and stores suffice (no read-modify-write).
-  const int take = min(DL, a.horizon), scan = min(127, a.horizon);
-  constexpr int kPro = 8;                  // ring loads in flight per thread
-  for (int k0 = tid; k0 < scan * Bg; k0 += kPro * nthr) {
-    long long v[kPro];
+  // Element (m, jl) is ring slot m ahead of step n0, owned target jl; each
+  // thread steps through the elements nthr at a time, carrying (m, jl) along
+  // so the slot arithmetic stays in 32 bits (a division per element costs
+  // more than its load).
+  if (Bg > 0) {
+    const int take = min(DL, a.horizon), scan = min(127, a.horizon);
+    const int sl0 = (int)(n0 % DL), rs0 = (int)(n0 & kRingMask);   // LDS and ring slot of step n0
+    const int dq = nthr / Bg, dr = nthr - dq * Bg;
+    constexpr int kPro = 8;                  // ring loads in flight per thread
+    int m = tid / Bg, jl = tid - m * Bg;
+    while (m < scan) {
+      long long v[kPro];
+      int mu[kPro], ju[kPro];
 #pragma unroll
-    for (int u = 0; u < kPro; ++u) {
-      const int k = k0 + u * nthr;
-      v[u] = 0;
-      if (k < scan * Bg) {
-        const int m = k / Bg, jl = k - m * Bg;
-        v[u] = ld_dev(p.ring + (size_t)((n0 + m) & kRingMask) * p.ring_stride + j0 + jl);
+      for (int u = 0; u < kPro; ++u) {
+        mu[u] = m;
+        ju[u] = jl;
+        v[u] = (m < scan) ? ld_dev(p.ring + (size_t)((rs0 + m) & kRingMask) * p.ring_stride + j0 + jl) : 0ll;
+        jl += dr;
+        m += dq;
+        if (jl >= Bg) { jl -= Bg; ++m; }
       }
-    }
 #pragma unroll
-    for (int u = 0; u < kPro; ++u) {
-      const int k = k0 + u * nthr;
-      if (k >= scan * Bg) break;
-      const int m = k / Bg, jl = k - m * Bg;
-      const long long step = n0 + m;
-      if (m < take) {
-        acc[(size_t)(step % DL) * a.B + jl] = v[u];
-        if (v[u] != 0) st_dev(p.ring + (size_t)(step & kRingMask) * p.ring_stride + j0 + jl, 0ll);
-      } else if (m >= DL && v[u] != 0) {
-        atomicOr(&fbits[(step & kRingMask) * a.BW + (jl >> 5)], 1u << (jl & 31));
+      for (int u = 0; u < kPro; ++u) {
+        const int mm = mu[u], jj = ju[u];
+        if (mm >= scan) break;
+        const int rs = (rs0 + mm) & kRingMask;
+        if (mm < take) {
+          acc[(size_t)(sl0 + mm >= DL ? sl0 + mm - DL : sl0 + mm) * a.B + jj] = v[u];
+          if (v[u] != 0) st_dev(p.ring + (size_t)rs * p.ring_stride + j0 + jj, 0ll);
+        } else if (mm >= DL && v[u] != 0) {
+          atomicOr(&fbits[rs * a.BW + (jj >> 5)], 1u << (jj & 31));
+        }
       }
     }
   }
@@ -820,17 +829,25 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
     p.wg_events[g] += s_events;
   }
   // the global entry of a window slot is zero unless far events were added
-  // to it (its far bit): a store, else an add
-  for (int k = tid; k < DL * Bg; k += nthr) {
-    const int m = k / Bg, jl = k - m * Bg;
-    const long long step = n_end + m;
-    const long long v = acc[(size_t)(step % DL) * a.B + jl];
-    if (v == 0) continue;
-    long long* e = p.ring + (size_t)(step & kRingMask) * p.ring_stride + j0 + jl;
-    if (fbits[(step & kRingMask) * a.BW + (jl >> 5)] & (1u << (jl & 31)))
-      atomicAdd(reinterpret_cast<unsigned long long*>(e), (unsigned long long)v);
-    else
-      st_dev(e, v);
+  // to it (its far bit): a store, else an add.  (m, jl) stepped as in the prologue.
+  if (Bg > 0) {
+    const int sl0 = (int)(n_end % DL), rs0 = (int)(n_end & kRingMask);
+    const int dq = nthr / Bg, dr = nthr - dq * Bg;
+    int m = tid / Bg, jl = tid - m * Bg;
+    while (m < DL) {
+      const long long v = acc[(size_t)(sl0 + m >= DL ? sl0 + m - DL : sl0 + m) * a.B + jl];
+      if (v != 0) {
+        const int rs = (rs0 + m) & kRingMask;
+        long long* e = p.ring + (size_t)rs * p.ring_stride + j0 + jl;
+        if (fbits[rs * a.BW + (jl >> 5)] & (1u << (jl & 31)))
+          atomicAdd(reinterpret_cast<unsigned long long*>(e), (unsigned long long)v);
+        else
+          st_dev(e, v);
+      }
+      jl += dr;
+      m += dq;
+      if (jl >= Bg) { jl -= Bg; ++m; }
+    }
   }
   // The last workgroup to finish (every other one has read all the records it
   // will read) clears the spike records for the next launch and advances the

@@ -601,7 +601,8 @@ def test_probes_and_launch_timing_leave_the_trajectory():
     persistent exchange) measure within physical bounds and leave the
     network untouched; the persistent kernel's launches are timed one by
     one (graph replays and the direct remainder) and their summed time lies
-    inside the simulate span.  The trajectory stays the oracle's."""
+    inside the simulate span; a call that is one launch is timed by the
+    call's span.  The trajectory stays the oracle's."""
     w = workloads.balanced()
     net, o = mc.Network(w), oracle.Oracle(w.to_dict())
     net.simulate(100)
@@ -617,12 +618,15 @@ def test_probes_and_launch_timing_leave_the_trajectory():
     for scheme, block in ((1, 512), (3, 256)):
         net.set_launch(scheme=scheme, block=block, neurons_per_wg=0, steps_per_graph=100)
         floor = net.probe_exchange(500) if scheme == 1 else None   # the LDS-window scheme's shape only
-        net.reserve(250)
+        net.reserve(300)
         net.simulate(250)                               # two graph replays of 100 steps, one direct launch of 50
         k = net.last_kernel_ms()
         assert k["launches"] == 3 and k["steps"] == 250
         assert 0.0 < k["ms"] <= net.last_simulate_ms()
         if floor is not None:
             assert 0.0 < floor * 250 * 1e-3 <= k["ms"] * 1.5, (floor, k)
-    o.run(600)
+        net.simulate(50)                                # one direct launch: timed by the call's own events
+        k = net.last_kernel_ms()
+        assert k["launches"] == 1 and k["steps"] == 50 and k["ms"] == net.last_simulate_ms()
+    o.run(700)
     assert_same(net, o, what="after probes and timed launches")
