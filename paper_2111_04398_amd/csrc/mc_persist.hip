@@ -333,47 +333,6 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
   if (tid == 0) { s_abort = 0; s_events = 0; s_work = 0; s_pubcnt = 0; s_sidecnt = 0; s_nready = 0; s_polldone = 0; s_ndone = 0; }
   if (tid < kMaxPops) s_popcnt[tid] = 0;
   __syncthreads();
-  // take the next DL steps of pending input of my targets into LDS; mark far
-  // entries.  Only the first `horizon` slots can hold input (the largest
-  // delay, or further after an injection or a loaded state).  Inside a launch
-  // only the owner workgroup touches its targets' ring entries, so device-
-  // scope loads and stores suffice (no read-modify-write).
-  // Element (m, jl) is ring slot m ahead of step n0, owned target jl; each
-  // thread steps through the elements nthr at a time, carrying (m, jl) along
-  // so the slot arithmetic stays in 32 bits (a division per element costs
-  // more than its load).
-  if (Bg > 0) {
-    const int take = min(DL, a.horizon), scan = min(127, a.horizon);
-    const int sl0 = (int)(n0 % DL), rs0 = (int)(n0 & kRingMask);   // LDS and ring slot of step n0
-    const int dq = nthr / Bg, dr = nthr - dq * Bg;
-    constexpr int kPro = 8;                  // ring loads in flight per thread
-    int m = tid / Bg, jl = tid - m * Bg;
-    while (m < scan) {
-      long long v[kPro];
-      int mu[kPro], ju[kPro];
-#pragma unroll
-      for (int u = 0; u < kPro; ++u) {
-        mu[u] = m;
-        ju[u] = jl;
-        v[u] = (m < scan) ? ld_dev(p.ring + (size_t)((rs0 + m) & kRingMask) * p.ring_stride + j0 + jl) : 0ll;
-        jl += dr;
-        m += dq;
-        if (jl >= Bg) { jl -= Bg; ++m; }
-      }
-#pragma unroll
-      for (int u = 0; u < kPro; ++u) {
-        const int mm = mu[u], jj = ju[u];
-        if (mm >= scan) break;
-        const int rs = (rs0 + mm) & kRingMask;
-        if (mm < take) {
-          acc[(size_t)(sl0 + mm >= DL ? sl0 + mm - DL : sl0 + mm) * a.B + jj] = v[u];
-          if (v[u] != 0) st_dev(p.ring + (size_t)rs * p.ring_stride + j0 + jj, 0ll);
-        } else if (mm >= DL && v[u] != 0) {
-          atomicOr(&fbits[rs * a.BW + (jj >> 5)], 1u << (jj & 31));
-        }
-      }
-    }
-  }
   // neuron state into registers: thread t < Bg owns neuron j0+t; the four
   // threads of a quad draw the same Philox block and take their own word
   double y = 0.0, I = 0.0;
@@ -561,6 +520,51 @@ __global__ __launch_bounds__(kPersistMaxBlock) void k_persist(DevNet p, PersistA
     const int sp = decide(n0);
     publish(n0, sp, t16n);
   }
+  // Then take the next DL steps of pending input of my targets into LDS and
+  // mark far entries (step n0's decision does not need them, so every
+  // workgroup's first record is out while this scan runs).  Only the first
+  // `horizon` slots can hold input (the largest delay, or further after an
+  // injection or a loaded state).  Inside a launch only the owner workgroup
+  // touches its targets' ring entries, so device-scope loads and stores
+  // suffice (no read-modify-write).
+  // Element (m, jl) is ring slot m ahead of step n0, owned target jl; each
+  // thread steps through the elements nthr at a time, carrying (m, jl) along
+  // so the slot arithmetic stays in 32 bits (a division per element costs
+  // more than its load).
+  if (Bg > 0) {
+    const int take = min(DL, a.horizon), scan = min(127, a.horizon);
+    const int sl0 = (int)(n0 % DL), rs0 = (int)(n0 & kRingMask);   // LDS and ring slot of step n0
+    const int dq = nthr / Bg, dr = nthr - dq * Bg;
+    constexpr int kPro = 8;                  // ring loads in flight per thread
+    int m = tid / Bg, jl = tid - m * Bg;
+    while (m < scan) {
+      long long v[kPro];
+      int mu[kPro], ju[kPro];
+#pragma unroll
+      for (int u = 0; u < kPro; ++u) {
+        mu[u] = m;
+        ju[u] = jl;
+        v[u] = (m < scan) ? ld_dev(p.ring + (size_t)((rs0 + m) & kRingMask) * p.ring_stride + j0 + jl) : 0ll;
+        jl += dr;
+        m += dq;
+        if (jl >= Bg) { jl -= Bg; ++m; }
+      }
+#pragma unroll
+      for (int u = 0; u < kPro; ++u) {
+        const int mm = mu[u], jj = ju[u];
+        if (mm >= scan) break;
+        const int rs = (rs0 + mm) & kRingMask;
+        if (mm < take) {
+          acc[(size_t)(sl0 + mm >= DL ? sl0 + mm - DL : sl0 + mm) * a.B + jj] = v[u];
+          if (v[u] != 0) st_dev(p.ring + (size_t)rs * p.ring_stride + j0 + jj, 0ll);
+        } else if (mm >= DL && v[u] != 0) {
+          atomicOr(&fbits[rs * a.BW + (jj >> 5)], 1u << (jj & 31));
+        }
+      }
+    }
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();                            // the window is in LDS before step n0's input is read
   for (int it = 0; it < steps; ++it) {
     const long long n = n0 + it;
     const bool timing = kTime && tid == 0;
