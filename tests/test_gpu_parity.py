@@ -79,7 +79,7 @@ def test_balanced_network_full_protocol():
 @pytest.mark.parametrize("scheme,block,npw,spg", [
     (0, 64, 64, 1), (0, 256, 256, 1000), (0, 256, 1024, 7), (0, 1024, 512, 333), (0, 128, 16, 50), (0, 256, 256, 0),
     (1, 512, 0, 1000), (1, 256, 0, 100), (1, 512, 64, 7), (1, 512, 512, 250), (1, 512, 200, 0), (1, 128, 24, 50),
-    (1, 64, 64, 50),
+    (1, 64, 64, 50), (1, 512, 0, 1),
     (2, 256, 256, 1000), (2, 64, 16, 7), (2, 1024, 1024, 0), (2, 128, 100, 33),
     (3, 256, 0, 1000), (3, 256, 16, 7), (3, 512, 2048, 0), (3, 128, 100, 33), (3, 64, 384, 50), (3, 512, 0, 1),
     (3, 256, 4092, 20)])
@@ -97,6 +97,33 @@ def test_launch_configuration_invariance(scheme, block, npw, spg):
     net.simulate(1200)
     o.run(1200)
     assert_same(net, o, what=f"{scheme},{block},{npw},{spg}")
+
+
+@pytest.mark.parametrize("npw", [0, 512])
+def test_persistent_launches_shorter_than_the_window(npw):
+    """Direct persistent launches of 1 to 34 steps.  With the automatic block
+    size the LDS delay window (101 steps) is longer than every launch, so the
+    window the prologue takes from the ring and the one the epilogue writes
+    back overlap; with 512 targets per workgroup it holds ~30 steps and most
+    events take the far path through the ring's marked slots.  A 1-step launch
+    publishes its only record before its ring scan.  Every call gives the
+    oracle's bits and is timed as one launch by the call's own events."""
+    w = workloads.balanced()
+    net, o = mc.Network(w), oracle.Oracle(w.to_dict())
+    net.set_launch(scheme=1, block=512, neurons_per_wg=npw, steps_per_graph=0)
+    dl = net.persist_shape()["lds_steps"]
+    assert (dl > 34) if npw == 0 else (dl < 34), dl
+    net.reserve(600)
+    net.simulate(300)
+    o.run(300)
+    for k in (1, 2, 3, 1, 5, 8, 13, 1, 1, 21, 34, 2):
+        net.simulate(k)
+        o.run(k)
+        t = net.last_kernel_ms()
+        assert t["launches"] == 1 and t["steps"] == k and t["ms"] == net.last_simulate_ms(), (k, t)
+        if k == 1:
+            assert_same(net, o, what=f"after a 1-step launch at step {o.step}")
+    assert_same(net, o, what="short launches")
 
 
 # the launch shapes mc_tune times (same list and steps per graph)
