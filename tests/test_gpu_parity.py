@@ -126,6 +126,33 @@ def test_persistent_launches_shorter_than_the_window(npw):
     assert_same(net, o, what="short launches")
 
 
+@pytest.mark.parametrize("npw", [0, 512])
+def test_injections_ahead_between_persistent_launches(npw):
+    """Inputs injected 1 to d_max steps ahead (the oracle's ring holds d_max
+    + 1 steps) between persistent launches of 1 to 120 steps.  With 512
+    targets per workgroup the LDS window holds ~30 steps, so most reach the
+    kernel through the ring's far slots, which the raised horizon makes the
+    next launch's scan read and mark.  The trajectory stays the oracle's
+    given the same injections."""
+    w = workloads.balanced()
+    net, o = mc.Network(w), oracle.Oracle(w.to_dict())
+    net.set_launch(scheme=1, block=512, neurons_per_wg=npw, steps_per_graph=0)
+    net.reserve(1000)
+    net.simulate(50)
+    o.run(50)
+    rng = np.random.default_rng(11 + npw)
+    depth = w.to_dict()["d_max_steps"] + 1
+    for steps in (1, 7, 40, 3, 90, 2, 120, 5):
+        for _ in range(6):
+            k, i = int(rng.integers(1, depth)), int(rng.integers(0, net.N))
+            v = int(rng.integers(-6_000_000, 6_000_000))
+            net.inject(k, i, v)
+            o.inject(k, i, v)
+        net.simulate(steps)
+        o.run(steps)
+    assert_same(net, o, what=f"injections ahead, neurons_per_wg {npw}")
+
+
 # the launch shapes mc_tune times (same list and steps per graph)
 TUNER_CANDIDATES = [(1, 512, 0, 10000, 0), (1, 256, 0, 10000, 0), (1, 512, 256, 10000, 0), (1, 512, 512, 10000, 0),
                     (1, 256, 128, 10000, 0), (0, 256, 256, 1000, 0), (0, 256, 256, 1000, 1), (0, 256, 1024, 1000, 0),
