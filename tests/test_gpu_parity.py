@@ -126,17 +126,18 @@ def test_persistent_launches_shorter_than_the_window(npw):
     assert_same(net, o, what="short launches")
 
 
-@pytest.mark.parametrize("npw", [0, 512])
-def test_injections_ahead_between_persistent_launches(npw):
+@pytest.mark.parametrize("scheme,block,npw", [(1, 512, 0), (1, 512, 512), (3, 256, 0), (0, 256, 256)])
+def test_injections_ahead_between_launches(scheme, block, npw):
     """Inputs injected 1 to d_max steps ahead (the oracle's ring holds d_max
     + 1 steps) between persistent launches of 1 to 120 steps.  With 512
     targets per workgroup the LDS window holds ~30 steps, so most reach the
     kernel through the ring's far slots, which the raised horizon makes the
     next launch's scan read and mark.  The trajectory stays the oracle's
-    given the same injections."""
+    given the same injections; likewise for the bucket scheme and the step
+    kernels."""
     w = workloads.balanced()
     net, o = mc.Network(w), oracle.Oracle(w.to_dict())
-    net.set_launch(scheme=1, block=512, neurons_per_wg=npw, steps_per_graph=0)
+    net.set_launch(scheme=scheme, block=block, neurons_per_wg=npw, steps_per_graph=0)
     net.reserve(1000)
     net.simulate(50)
     o.run(50)
@@ -150,7 +151,7 @@ def test_injections_ahead_between_persistent_launches(npw):
             o.inject(k, i, v)
         net.simulate(steps)
         o.run(steps)
-    assert_same(net, o, what=f"injections ahead, neurons_per_wg {npw}")
+    assert_same(net, o, what=f"injections ahead, launch {scheme},{block},{npw}")
 
 
 # the launch shapes mc_tune times (same list and steps per graph)
